@@ -1,0 +1,266 @@
+"""FP64 CPU oracle for the sequential multi-view deconvolution update.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously correct reference
+that the GPU library is checked against.  Only the test-suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the product path never
+does.  It shares no code with the HIP library: no kernels, no headers, no
+tables, no pre- or post-processing.
+
+Paper: Preibisch et al., "Efficient Bayesian-based Multi-View Deconvolution"
+(arXiv 1308.0730).  Every function below names the passage it follows.
+
+Conventions (the paper is silent on them; each is a documented reading):
+  * Arrays are C-ordered [z][y][x]; a volume of dims (nx, ny, nz) has numpy
+    shape (nz, ny, nx).  A kernel of extents (kx, ky, kz) has shape (kz, ky, kx).
+  * Kernels are centred at c = (k - 1) / 2 per axis; even extents get one
+    trailing zero plane first so that every extent is odd.
+  * "convolution" in the update is circular over the volume (the views are
+    registered onto one periodic grid):  (f * K)[x] = sum_d K[c + d] f[x - d].
+  * P* is P mirrored through its centre: P*[c + d] = P[c - d]
+    (section "Integrating xi and x", which explains why the second
+    convolution of eq. 15 uses the inverted kernel).
+  * Scale s = mean of all views; psi^0 = s everywhere (eq. 15 text: a
+    constant guess at the average intensity); eps = 1e-6 s guards the ratio;
+    lambda' = lambda / s makes the Tikhonov weight dimensionless.
+  * Tikhonov: the update solves lambda' t^2 + t = u, evaluated as
+    t = 2u / (1 + sqrt(1 + 4 lambda' u)) (no cancellation).
+  * Weights blend the step: psi <- psi + w (t - psi)  (section on partially
+    overlapping data: w is the fraction of one RL step that is applied).
+
+Parity status: every function here is pinned by tests in
+tests/test_oracle_pins.py (brute-force direct convolution, explicit-matrix
+EM/OSEM, fixed point, flux, non-negativity, closed forms, delta-kernel special
+cases, finite differences).  No function is "parity unpinned".
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+from scipy import signal
+
+RL, EFF, OPT1, OPT2 = 0, 1, 2, 3
+VARIANT_NAMES = {RL: "rl", EFF: "eff", OPT1: "opt1", OPT2: "opt2"}
+
+EPS_SCALE = 1e-6
+
+
+# ---------------------------------------------------------------- kernels --
+
+def normalize(P):
+    """Probability constraint of eq. 3: a PSF integrates to one."""
+    P = np.asarray(P, dtype=np.float64)
+    s = P.sum()
+    if not s > 0:
+        raise ValueError("kernel sum must be positive")
+    return P / s
+
+
+def pad_odd(P):
+    """Append one zero plane to every even extent (centre convention)."""
+    P = np.asarray(P, dtype=np.float64)
+    pads = [(0, 1 - (n % 2)) for n in P.shape]
+    return np.pad(P, pads)
+
+
+def mirror(P):
+    """P*: the kernel inverted through its centre (eq. 51, mirrored kernels)."""
+    return np.ascontiguousarray(P[::-1, ::-1, ::-1])
+
+
+def prepare_psf(P):
+    """Normalise (eq. 3) and make every extent odd."""
+    return pad_odd(normalize(P))
+
+
+def conv_full(a, b):
+    """Full linear convolution of two small kernels (FP64 FFT; pinned against
+    direct summation in the tests).
+
+    Centre bookkeeping: if a is centred at ca and b at cb, the result is
+    centred at ca + cb.
+    """
+    return signal.fftconvolve(a, b, mode="full")
+
+
+def conv_full_direct(a, b):
+    """Full linear convolution of two small kernels by direct summation."""
+    return signal.convolve(a, b, mode="full", method="direct")
+
+
+def crop_center(K, shape):
+    """Window of `shape` (odd extents) around the centre of K (odd extents)."""
+    sl = []
+    for n, m in zip(K.shape, shape):
+        c = (n - 1) // 2
+        h = (m - 1) // 2
+        if m > n:
+            raise ValueError("crop larger than kernel")
+        sl.append(slice(c - h, c + h + 1))
+    return K[tuple(sl)]
+
+
+def compound_kernel(psfs, v, variant):
+    """Back-projection kernel of view v for each variant.
+
+    RL   : P_v*                                  (eq. 51, sequential form of section 7)
+    EFF  : P_v* . prod_{w != v} (P_v* * P_w * P_w*)   (eq. 220 / 222)
+    OPT1 : P_v* . prod_{w != v} (P_v* * P_w)          (eq. 230, Optimization I)
+    OPT2 : prod of N factors P_v*  = (P_v*)^N         (eq. 240, Optimization II)
+    '*' is convolution, '.' the pointwise product.  Each factor is cropped to
+    the window of P_v (exact: the product with P_v* vanishes outside it) and
+    the result is normalised to sum one, as every kernel is a probability
+    distribution (eq. 3).  With one view every variant reduces to P_v*.
+    """
+    P = [prepare_psf(p) for p in psfs]
+    Pv_m = mirror(P[v])
+    n = len(P)
+    if variant == RL:
+        return Pv_m.copy()
+    if variant == OPT2:
+        return normalize(Pv_m ** n)
+    K = Pv_m.copy()
+    for w in range(n):
+        if w == v:
+            continue
+        f = conv_full(Pv_m, P[w])
+        if variant == EFF:
+            f = conv_full(f, mirror(P[w]))
+        elif variant != OPT1:
+            raise ValueError("unknown variant")
+        K = K * crop_center(f, Pv_m.shape)
+    return normalize(K)
+
+
+# ------------------------------------------------------------ convolution --
+
+def embed(K, shape):
+    """Wrap-embed a centred odd kernel into a periodic grid: h[d mod n] = K[c + d]."""
+    h = np.zeros(shape, dtype=np.float64)
+    kz, ky, kx = K.shape
+    cz, cy, cx = (kz - 1) // 2, (ky - 1) // 2, (kx - 1) // 2
+    iz = (np.arange(kz) - cz) % shape[0]
+    iy = (np.arange(ky) - cy) % shape[1]
+    ix = (np.arange(kx) - cx) % shape[2]
+    np.add.at(h, np.ix_(iz, iy, ix), K)
+    return h
+
+
+def circ_conv(f, K):
+    """Circular convolution with a centred kernel via the FP64 FFT."""
+    f = np.asarray(f, dtype=np.float64)
+    H = sfft.rfftn(embed(K, f.shape), workers=-1)
+    return sfft.irfftn(sfft.rfftn(f, workers=-1) * H, s=f.shape, workers=-1)
+
+
+def circ_conv_direct(f, K):
+    """Circular convolution by brute-force summation over the kernel support."""
+    f = np.asarray(f, dtype=np.float64)
+    kz, ky, kx = K.shape
+    cz, cy, cx = (kz - 1) // 2, (ky - 1) // 2, (kx - 1) // 2
+    out = np.zeros_like(f)
+    for a in range(kz):
+        for b in range(ky):
+            for c in range(kx):
+                k = K[a, b, c]
+                if k != 0.0:
+                    out += k * np.roll(f, shift=(a - cz, b - cy, c - cx), axis=(0, 1, 2))
+    return out
+
+
+# ----------------------------------------------------------------- update --
+
+def tikhonov(u, lam_p):
+    """MAP step for the Tikhonov prior: the t >= 0 solving lam' t^2 + t = u.
+
+    The paper offers Tikhonov regularisation without printing its form
+    (section on noise and regularisation); this is the reading documented in
+    the module header, evaluated in the rationalised form.
+    """
+    if lam_p == 0.0:
+        return u
+    return 2.0 * u / (1.0 + np.sqrt(1.0 + 4.0 * lam_p * u))
+
+
+def scale_of(views):
+    """Mean intensity over all voxels of all views (psi^0 of eq. 15)."""
+    return float(np.mean([np.mean(np.asarray(v, dtype=np.float64)) for v in views]))
+
+
+def view_update(psi, phi, P, K, w=None, lam_p=0.0, eps=0.0, conv=circ_conv, stats=None):
+    """One view's update of psi (section 7, one line of the sequential scheme).
+
+    b = psi * P_v (expected view, eq. 1); q = phi / max(b, eps);
+    c = q * K_v; u = psi . max(c, 0); t = T_lambda(u); psi <- psi + w (t - psi).
+    """
+    b = conv(psi, P)
+    q = phi / np.maximum(b, eps)
+    c = conv(q, K)
+    u = psi * np.maximum(c, 0.0)
+    t = tikhonov(u, lam_p)
+    if stats is not None:
+        stats["ratio_clamps"] = stats.get("ratio_clamps", 0) + int(np.count_nonzero(b < eps))
+        stats["neg_clamps"] = stats.get("neg_clamps", 0) + int(np.count_nonzero(c < 0))
+    if w is None:
+        return t
+    return psi + w * (t - psi)
+
+
+class Problem:
+    """Inputs of one deconvolution: views, PSFs, optional weights, lambda."""
+
+    def __init__(self, views, psfs, weights=None, lam=0.0):
+        self.views = [np.asarray(v, dtype=np.float64) for v in views]
+        self.psfs = [np.asarray(p, dtype=np.float64) for p in psfs]
+        self.weights = None if weights is None else [np.asarray(w, dtype=np.float64) for w in weights]
+        self.lam = float(lam)
+        self.n = len(self.views)
+        self.shape = self.views[0].shape
+        self.s = scale_of(self.views)
+        self.eps = EPS_SCALE * self.s
+        self.lam_p = self.lam / self.s
+        self.P = [prepare_psf(p) for p in self.psfs]
+        self._K = {}
+
+    def kernels(self, variant):
+        if variant not in self._K:
+            self._K[variant] = [compound_kernel(self.psfs, v, variant) for v in range(self.n)]
+        return self._K[variant]
+
+    def psi0(self):
+        return np.full(self.shape, self.s, dtype=np.float64)
+
+    def iterate(self, psi, n_iter, variant, conv=circ_conv, flux=None, stats=None):
+        """n_iter iterations; one iteration applies every view once, in index
+        order (section 7; an iteration is complete when all views have
+        contributed once)."""
+        K = self.kernels(variant)
+        psi = np.array(psi, dtype=np.float64)
+        for _ in range(n_iter):
+            for v in range(self.n):
+                w = None if self.weights is None else self.weights[v]
+                psi = view_update(psi, self.views[v], self.P[v], K[v], w, self.lam_p,
+                                  self.eps, conv=conv, stats=stats)
+                if flux is not None:
+                    flux.append(float(psi.sum()))
+        return psi
+
+
+def run(views, psfs, n_iter, variant, weights=None, lam=0.0, psi0=None, trajectory=False):
+    """Deconvolve from psi0 (default: flat at the mean); optionally return
+    the estimate after every iteration."""
+    pb = Problem(views, psfs, weights, lam)
+    psi = pb.psi0() if psi0 is None else np.asarray(psi0, dtype=np.float64)
+    traj = []
+    for _ in range(n_iter):
+        psi = pb.iterate(psi, 1, variant)
+        if trajectory:
+            traj.append(psi.copy())
+    return (psi, traj) if trajectory else psi
+
+
+# ---------------------------------------------------------------- metrics --
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
