@@ -1,0 +1,191 @@
+/*
+ * mvd.h -- C ABI of the MI355X (gfx950) sequential multi-view deconvolution
+ * library (Preibisch et al., "Efficient Bayesian-based Multi-View
+ * Deconvolution", arXiv 1308.0730).
+ *
+ * What the library computes.  For views phi_v, PSFs P_v, optional weights
+ * w_v and a Tikhonov weight lambda, every iteration applies each view once, in
+ * index order (section 7, "Alternative iteration for faster convergence"):
+ *
+ *   b   = psi (x) P_v                     expected view (eq. 1, eq. 51)
+ *   q   = phi_v / max(b, eps)             ratio of observed to expected (eq. 15)
+ *   c   = q (x) K_v                       back-projection
+ *   u   = psi * max(c, 0)                 multiplicative RL step (eq. 15)
+ *   t   = 2u / (1 + sqrt(1 + 4 lambda' u))  Tikhonov MAP step (solves lambda' t^2 + t = u)
+ *   psi = psi + w_v (t - psi)             weights: fraction of the step applied
+ *                                         (section 10, partially overlapping data)
+ *
+ * (x) is circular 3-D convolution on the volume grid with kernels centred at
+ * (k-1)/2.  K_v is selected by the variant:
+ *   MVD_RL   K_v = P_v*, the mirrored PSF (eq. 15/51; sequential = OS-EM, section 7.1)
+ *   MVD_EFF  K_v = P_v* . prod_{w!=v} (P_v* (x) P_w (x) P_w*)   (eq. 220/222)
+ *   MVD_OPT1 K_v = P_v* . prod_{w!=v} (P_v* (x) P_w)            (eq. 230, Optimization I)
+ *   MVD_OPT2 K_v = (P_v*)^N                                     (eq. 240, Optimization II)
+ * each normalised to sum one (every kernel is a probability distribution, eq. 3).
+ * Scale: s = mean over all voxels of all views; psi starts flat at s (the
+ * constant initial guess of eq. 15); eps = eps_scale * s; lambda' = lambda / s.
+ *
+ * Layout.  A volume of dims {nx, ny, nz} is nx*ny*nz float32, C order
+ * [z][y][x], x fastest.  A PSF of dims {kx, ky, kz} is kx*ky*kz float32 in the
+ * same order.  Even PSF extents are padded with one trailing zero plane.
+ *
+ * Ownership.  Every input is copied at create; the caller may free it on
+ * return.  The handle owns all device memory (through the allocator callbacks
+ * if given, else hipMalloc).  A handle is not thread-safe; separate handles
+ * are independent.
+ *
+ * Errors.  Every function returns MVD_OK (0) or a negative code; no C++
+ * exception crosses the ABI.  On failure of a create call *out stays NULL and
+ * nothing leaks.  mvd_last_error() gives a message (per handle, or
+ * thread-local for calls that have no handle).  Work is asynchronous on the
+ * handle's stream: device-side faults (a non-finite estimate) surface as
+ * MVD_ENONFINITE at the next synchronising call (mvd_get_estimate, mvd_stats,
+ * mvd_synchronize).
+ */
+#ifndef MVD_H
+#define MVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MVD_OK 0
+#define MVD_EINVAL (-1)     /* invalid argument, shape or value */
+#define MVD_ENOMEM (-2)     /* device allocation failed */
+#define MVD_EDEVICE (-3)    /* HIP runtime error */
+#define MVD_ENONFINITE (-4) /* the estimate became NaN or Inf */
+#define MVD_ESTATE (-5)     /* call out of order */
+
+#define MVD_RL 0
+#define MVD_EFF 1
+#define MVD_OPT1 2
+#define MVD_OPT2 3
+
+#define MVD_MEM_HOST 0
+#define MVD_MEM_DEVICE 1
+
+#define MVD_MAX_VIEWS 64
+#define MVD_MAX_LEN 512 /* largest ny, nz and nx/2 */
+
+typedef struct mvd_handle mvd_handle;
+
+/* One volume to deconvolve (a block of the batched form).
+ *   n_views   1..MVD_MAX_VIEWS
+ *   dims      {nx, ny, nz}: nx even, every extent 5-smooth (2^a 3^b 5^c),
+ *             4 <= nx <= 2*MVD_MAX_LEN, 2 <= ny, nz <= MVD_MAX_LEN
+ *   views     n_views pointers to nx*ny*nz floats, finite and >= 0, registered
+ *             onto the common grid (section 6: identity transformation)
+ *   psfs      n_views pointers; psf_dims[3*v + {0,1,2}] = {kx, ky, kz};
+ *             finite, >= 0, positive sum, each extent (after odd padding)
+ *             no larger than the volume's
+ *   weights   NULL (all ones) or n_views pointers to nx*ny*nz floats in [0, 1]
+ *   mem_kind  MVD_MEM_HOST or MVD_MEM_DEVICE for views, psfs and weights
+ */
+typedef struct mvd_problem {
+  int n_views;
+  int dims[3];
+  const float* const* views;
+  const float* const* psfs;
+  const int* psf_dims;
+  const float* const* weights;
+  int mem_kind;
+} mvd_problem;
+
+typedef void* (*mvd_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mvd_free_fn)(void* ptr, void* ctx);
+
+/* Options (NULL = all defaults).
+ *   lambda     Tikhonov weight >= 0 (0 disables), dimensionless (divided by s)
+ *   eps_scale  ratio guard relative to s (0 selects 1e-6)
+ *   stream     hipStream_t the work is ordered on (NULL = default stream)
+ *   alloc/free device allocator and its context (NULL = hipMalloc/hipFree);
+ *              alloc returns NULL on failure, and must return 256-byte aligned memory
+ *   use_graphs 0 = launch kernels directly, 1 = replay one HIP graph per
+ *              iteration (default when options are NULL)
+ *   tile_config  0 = autotuned/default pass shapes; k > 0 forces candidate k-1
+ */
+typedef struct mvd_options {
+  double lambda;
+  double eps_scale;
+  void* stream;
+  mvd_alloc_fn alloc;
+  mvd_free_fn free;
+  void* alloc_ctx;
+  int use_graphs;
+  int tile_config;
+} mvd_options;
+
+typedef struct mvd_stats_t {
+  int64_t iterations;        /* iterations run since create / set_estimate */
+  int n_views;
+  int n_blocks;
+  double scale;              /* s of block 0 */
+  double flux[MVD_MAX_VIEWS]; /* sum of psi after each view-update of the last
+                                 iteration, added over blocks (FP64) */
+  int64_t ratio_clamps;      /* voxels with b < eps in the last iteration */
+  int64_t neg_clamps;        /* voxels with c < 0 in the last iteration */
+  int nonfinite;             /* 1 if psi became NaN/Inf since the last reset */
+} mvd_stats_t;
+
+/* Create a handle for one volume (the plain form).  Validates everything
+ * listed at mvd_problem (MVD_EINVAL), copies the inputs, computes s, the
+ * PSF spectra and sets psi to the flat start. */
+int mvd_create(mvd_handle** out, const mvd_problem* p, const mvd_options* o);
+
+/* Batched form: n_blocks independent volumes of any valid dims with the same
+ * n_views, deconvolved together; every pass of an iteration is one launch
+ * that covers all blocks. */
+int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
+                     const mvd_options* o);
+
+/* Run n >= 0 iterations of `variant` (MVD_RL..MVD_OPT2).  Asynchronous.  The
+ * compound-kernel spectra of a variant are built on its first use. */
+int mvd_iterate(mvd_handle* h, int n, int variant);
+
+/* Copy the estimate of `block` (0 for the plain form) into dst (nx*ny*nz
+ * floats, host or device memory).  Synchronises; returns MVD_ENONFINITE if
+ * the estimate became non-finite (the copy is still made). */
+int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block);
+
+/* Replace the estimate of `block` (finite, >= 0); resets the iteration count
+ * and the non-finite flag.  Use to resume from a checkpoint or to start the
+ * differentiated form from a given psi_0. */
+int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block);
+
+/* Synchronise and report statistics of the last mvd_iterate call. */
+int mvd_stats(mvd_handle* h, mvd_stats_t* s);
+
+/* Wait for all queued work; MVD_ENONFINITE if psi became non-finite. */
+int mvd_synchronize(mvd_handle* h);
+
+/* Release everything the handle owns.  NULL is accepted. */
+int mvd_destroy(mvd_handle* h);
+
+/* Message of the last failure on h (or of this thread when h is NULL). */
+const char* mvd_last_error(const mvd_handle* h);
+
+/* ---- host utilities (no device needed) ---------------------------------
+ * Compound kernel of view v (FP64, host): the same K_v the handle uses,
+ * normalised, in the odd window of P_v.  out receives kx*ky*kz doubles of
+ * the padded window; out_dims (may be NULL) receives its {kx, ky, kz}. */
+int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_dims, int v,
+                        int variant, double* out, int* out_dims);
+
+/* Spectrum of a centred odd kernel on the volume grid, as the handle stores
+ * it: H[kz][ky][kx] = (1/V) sum_d K[c+d] exp(-2 pi i k.d / n) for
+ * kx < nx/2 into main (complex float pairs, nz*ny*(nx/2)), and kx = nx/2 into
+ * nyq (nz*ny pairs).  FP64 arithmetic, rounded once. */
+int mvd_kernel_spectrum(const double* kernel, const int* kdims, const int* dims, float* main_out,
+                        float* nyq_out);
+
+/* Library version string. */
+const char* mvd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVD_H */

@@ -1,0 +1,271 @@
+// FP64 host-side preparation of the kernels the passes multiply by.
+#include "mvd_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <functional>
+#include <stdexcept>
+#include <thread>
+
+namespace mvdh {
+
+namespace {
+
+int n_threads() {
+  unsigned h = std::thread::hardware_concurrency();
+  if (h == 0) h = 4;
+  return (int)std::min(h, 32u);
+}
+
+// Run f(i) for i in [0, n) on a few threads.
+void parallel_for(int n, const std::function<void(int)>& f) {
+  const int nt = std::min(n, n_threads());
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+inline int wrap(long long k, long long d, int n) {
+  long long m = (k * d) % n;
+  if (m < 0) m += n;
+  return (int)m;
+}
+
+// Centred DFT of K on a periodic grid (gx, gy, gz), full complex [kz][ky][kx]:
+// F[k] = sum_d K[c + d] exp(-2 pi i k.d / g).
+std::vector<cd> dft_grid(const Kern& K, int gx, int gy, int gz) {
+  const auto tx = twiddles(gx), ty = twiddles(gy), tz = twiddles(gz);
+  const int cx = (K.kx - 1) / 2, cy = (K.ky - 1) / 2, cz = (K.kz - 1) / 2;
+  std::vector<cd> A((size_t)K.kz * K.ky * gx);
+  for (int z = 0; z < K.kz; ++z)
+    for (int y = 0; y < K.ky; ++y)
+      for (int k = 0; k < gx; ++k) {
+        cd s = 0;
+        for (int x = 0; x < K.kx; ++x) s += K.at(z, y, x) * tx[wrap(k, x - cx, gx)];
+        A[((size_t)z * K.ky + y) * gx + k] = s;
+      }
+  std::vector<cd> B((size_t)K.kz * gy * gx);
+  for (int z = 0; z < K.kz; ++z)
+    for (int k = 0; k < gy; ++k)
+      for (int y = 0; y < K.ky; ++y) {
+        const cd w = ty[wrap(k, y - cy, gy)];
+        const cd* a = &A[((size_t)z * K.ky + y) * gx];
+        cd* b = &B[((size_t)z * gy + k) * gx];
+        for (int x = 0; x < gx; ++x) b[x] += a[x] * w;
+      }
+  std::vector<cd> F((size_t)gz * gy * gx);
+  for (int k = 0; k < gz; ++k)
+    for (int z = 0; z < K.kz; ++z) {
+      const cd w = tz[wrap(k, z - cz, gz)];
+      const cd* b = &B[(size_t)z * gy * gx];
+      cd* f = &F[(size_t)k * gy * gx];
+      for (size_t i = 0; i < (size_t)gy * gx; ++i) f[i] += b[i] * w;
+    }
+  return F;
+}
+
+// Inverse DFT of S on the grid, evaluated only at offsets d in the centred
+// window (wx, wy, wz); real part, divided by the grid size.
+std::vector<double> idft_window(const std::vector<cd>& S, int gx, int gy, int gz, int wx, int wy,
+                                int wz) {
+  const auto tx = twiddles(gx), ty = twiddles(gy), tz = twiddles(gz);
+  const int cx = (wx - 1) / 2, cy = (wy - 1) / 2, cz = (wz - 1) / 2;
+  std::vector<cd> T1((size_t)wz * gy * gx);
+  for (int z = 0; z < wz; ++z)
+    for (int k = 0; k < gz; ++k) {
+      const cd w = std::conj(tz[wrap(k, z - cz, gz)]);
+      const cd* s = &S[(size_t)k * gy * gx];
+      cd* t = &T1[(size_t)z * gy * gx];
+      for (size_t i = 0; i < (size_t)gy * gx; ++i) t[i] += s[i] * w;
+    }
+  std::vector<cd> T2((size_t)wz * wy * gx);
+  for (int z = 0; z < wz; ++z)
+    for (int y = 0; y < wy; ++y)
+      for (int k = 0; k < gy; ++k) {
+        const cd w = std::conj(ty[wrap(k, y - cy, gy)]);
+        const cd* s = &T1[((size_t)z * gy + k) * gx];
+        cd* t = &T2[((size_t)z * wy + y) * gx];
+        for (int x = 0; x < gx; ++x) t[x] += s[x] * w;
+      }
+  const double inv = 1.0 / ((double)gx * gy * gz);
+  std::vector<double> out((size_t)wz * wy * wx);
+  for (int z = 0; z < wz; ++z)
+    for (int y = 0; y < wy; ++y)
+      for (int x = 0; x < wx; ++x) {
+        cd s = 0;
+        const cd* t = &T2[((size_t)z * wy + y) * gx];
+        for (int k = 0; k < gx; ++k) s += t[k] * std::conj(tx[wrap(k, x - cx, gx)]);
+        out[((size_t)z * wy + y) * wx + x] = s.real() * inv;
+      }
+  return out;
+}
+
+void normalize(Kern& K) {
+  double s = 0;
+  for (double v : K.a) s += v;
+  if (!(s > 0) || !std::isfinite(s)) throw std::invalid_argument("kernel sum must be positive");
+  for (double& v : K.a) v /= s;
+}
+
+}  // namespace
+
+bool is_smooth5(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+std::vector<int> factorize(int n) {
+  std::vector<int> r;
+  while (n % 8 == 0) {
+    r.push_back(8);
+    n /= 8;
+  }
+  if (n % 4 == 0) {
+    r.push_back(4);
+    n /= 4;
+  }
+  if (n % 2 == 0) {
+    r.push_back(2);
+    n /= 2;
+  }
+  while (n % 3 == 0) {
+    r.push_back(3);
+    n /= 3;
+  }
+  while (n % 5 == 0) {
+    r.push_back(5);
+    n /= 5;
+  }
+  if (n != 1) throw std::invalid_argument("length is not 5-smooth");
+  return r;
+}
+
+std::vector<cd> twiddles(int n) {
+  std::vector<cd> t(n);
+  const double a = -2.0 * M_PI / n;
+  for (int m = 0; m < n; ++m) t[m] = cd(std::cos(a * m), std::sin(a * m));
+  return t;
+}
+
+Kern prepare_psf(const float* p, int kx, int ky, int kz) {
+  if (kx < 1 || ky < 1 || kz < 1) throw std::invalid_argument("PSF extents must be >= 1");
+  Kern K;
+  K.kx = kx | 1;
+  K.ky = ky | 1;
+  K.kz = kz | 1;
+  K.a.assign((size_t)K.kx * K.ky * K.kz, 0.0);
+  for (int z = 0; z < kz; ++z)
+    for (int y = 0; y < ky; ++y)
+      for (int x = 0; x < kx; ++x) {
+        const float v = p[((size_t)z * ky + y) * kx + x];
+        if (!std::isfinite(v) || v < 0) throw std::invalid_argument("PSF values must be finite and >= 0");
+        K.at(z, y, x) = v;
+      }
+  normalize(K);
+  return K;
+}
+
+Kern mirror(const Kern& k) {
+  Kern m = k;
+  for (int z = 0; z < k.kz; ++z)
+    for (int y = 0; y < k.ky; ++y)
+      for (int x = 0; x < k.kx; ++x) m.at(z, y, x) = k.at(k.kz - 1 - z, k.ky - 1 - y, k.kx - 1 - x);
+  return m;
+}
+
+Kern compound_kernel(const std::vector<Kern>& P, int v, int variant) {
+  const int n = (int)P.size();
+  Kern K = mirror(P[v]);
+  if (variant == 0 || n == 1) return K;
+  if (variant == 3) {
+    for (double& a : K.a) a = std::pow(a, n);
+    normalize(K);
+    return K;
+  }
+  if (variant != 1 && variant != 2) throw std::invalid_argument("unknown variant");
+  // grid on which the partner factor's circular convolution equals the
+  // linear one inside the window of P_v
+  int mx = 0, my = 0, mz = 0;
+  for (int w = 0; w < n; ++w) {
+    mx = std::max(mx, P[w].kx);
+    my = std::max(my, P[w].ky);
+    mz = std::max(mz, P[w].kz);
+  }
+  const int f = variant == 1 ? 2 : 1;
+  const int gx = P[v].kx + f * mx, gy = P[v].ky + f * my, gz = P[v].kz + f * mz;
+  const std::vector<cd> Fv = dft_grid(P[v], gx, gy, gz);
+  std::vector<std::vector<double>> fac(n);
+  parallel_for(n, [&](int w) {
+    if (w == v) return;
+    std::vector<cd> S = dft_grid(P[w], gx, gy, gz);
+    for (size_t i = 0; i < S.size(); ++i) {
+      cd s = std::conj(Fv[i]) * S[i];        // P_v* (x) P_w
+      if (variant == 1) s *= std::conj(S[i]);  // (x) P_w*
+      S[i] = s;
+    }
+    fac[w] = idft_window(S, gx, gy, gz, K.kx, K.ky, K.kz);
+  });
+  for (int w = 0; w < n; ++w) {
+    if (w == v) continue;
+    for (size_t i = 0; i < K.a.size(); ++i) K.a[i] *= fac[w][i];
+  }
+  normalize(K);
+  return K;
+}
+
+std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny) {
+  const int M = nx / 2;
+  const auto tx = twiddles(nx), ty = twiddles(ny);
+  const int cx = (K.kx - 1) / 2, cy = (K.ky - 1) / 2;
+  std::vector<cd> A2((size_t)K.kz * ny * (M + 1));
+  parallel_for(K.kz, [&](int z) {
+    std::vector<cd> A1((size_t)K.ky * (M + 1));
+    for (int y = 0; y < K.ky; ++y)
+      for (int k = 0; k <= M; ++k) {
+        cd s = 0;
+        for (int x = 0; x < K.kx; ++x) s += K.at(z, y, x) * tx[wrap(k, x - cx, nx)];
+        A1[(size_t)y * (M + 1) + k] = s;
+      }
+    for (int k = 0; k < ny; ++k) {
+      cd* a2 = &A2[((size_t)z * ny + k) * (M + 1)];
+      for (int y = 0; y < K.ky; ++y) {
+        const cd w = ty[wrap(k, y - cy, ny)];
+        const cd* a1 = &A1[(size_t)y * (M + 1)];
+        for (int x = 0; x <= M; ++x) a2[x] += a1[x] * w;
+      }
+    }
+  });
+  return A2;
+}
+
+void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float* nyq_out) {
+  const int M = nx / 2;
+  const auto A2 = spectrum_xy(K, nx, ny);
+  const auto tz = twiddles(nz);
+  const int cz = (K.kz - 1) / 2;
+  const double invV = 1.0 / ((double)nx * ny * nz);
+  parallel_for(nz, [&](int kz) {
+    for (int ky = 0; ky < ny; ++ky)
+      for (int kx = 0; kx <= M; ++kx) {
+        cd s = 0;
+        for (int z = 0; z < K.kz; ++z) s += A2[((size_t)z * ny + ky) * (M + 1) + kx] * tz[wrap(kz, z - cz, nz)];
+        s *= invV;
+        float* o = kx < M ? main_out + 2 * (((size_t)kz * ny + ky) * M + kx) : nyq_out + 2 * ((size_t)kz * ny + ky);
+        o[0] = (float)s.real();
+        o[1] = (float)s.imag();
+      }
+  });
+}
+
+}  // namespace mvdh

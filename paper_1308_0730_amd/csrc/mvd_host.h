@@ -1,0 +1,46 @@
+// FP64 host-side preparation: PSF normalisation, compound kernels, kernel
+// spectra, FFT plans and twiddle tables.  No device code.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mvdh {
+
+using cd = std::complex<double>;
+
+// A centred kernel with odd extents, [z][y][x] doubles.
+struct Kern {
+  int kx = 0, ky = 0, kz = 0;
+  std::vector<double> a;
+  double& at(int z, int y, int x) { return a[((size_t)z * ky + y) * kx + x]; }
+  double at(int z, int y, int x) const { return a[((size_t)z * ky + y) * kx + x]; }
+};
+
+bool is_smooth5(int n);
+// Radices (8, 4, 2, 3, 5) of a 5-smooth length, largest first.
+std::vector<int> factorize(int n);
+
+// Normalise to sum one and pad even extents with a trailing zero plane.
+// Throws std::invalid_argument on negative / non-finite values or zero sum.
+Kern prepare_psf(const float* p, int kx, int ky, int kz);
+Kern mirror(const Kern& k);
+
+// Compound back-projection kernel of view v (0 = RL, 1 = EFF, 2 = OPT1,
+// 3 = OPT2), in the window of P_v, normalised.  The partner factors
+// P_v* (x) P_w (x) P_w* (EFF) and P_v* (x) P_w (OPT1) are evaluated exactly
+// by a direct DFT on a grid large enough that circular equals linear
+// convolution, then cropped to the window.
+Kern compound_kernel(const std::vector<Kern>& P, int v, int variant);
+
+// Stages x and y of the spectrum of a centred kernel on a volume grid:
+// A2[dz][ky][kx], kx in [0, nx/2], for every kernel plane dz.
+std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny);
+// exp(-2 pi i m / n), m < n.
+std::vector<cd> twiddles(int n);
+// Full spectrum on the host (all three stages), scaled by 1/V, split into
+// the main part [kz][ky][kx < nx/2] and the Nyquist plane [kz][ky].
+void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float* nyq_out);
+
+}  // namespace mvdh

@@ -1,0 +1,34 @@
+// Host-side entry points of the gfx950 kernels (launch wrappers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mvd_types.h"
+
+struct LaunchArgs {
+  const JobDesc* jobs;   // device job table
+  int njobs;
+  const FftPlan* plans;  // device plan table
+  const float2* tw;      // device twiddle pool
+  hipStream_t stream;
+  int grid;              // total tiles of the pass over all jobs
+};
+
+int mvd_num_cfgs(int kind);
+int mvd_cfg_threads(int kind, int cfg);
+int mvd_cfg_param(int kind, int cfg);   // rows (x) or lines (y, z) per tile
+int mvd_cfg_maxlen(int kind, int cfg);  // largest transform length it accepts
+
+// mode 0: R2C of psi; 1: blur -> ratio -> R2C; 2: back-projection -> update -> R2C
+hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
+                        int write_spec);
+hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v);
+hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH);
+hipError_t mvd_launch_reduce(const Partial* parts, int ntiles, int nviews, double* flux,
+                             unsigned long long* ratio, unsigned long long* neg, hipStream_t s);
+hipError_t mvd_launch_check(const float* x, int64_t n, float lo, float hi, double* psum,
+                            unsigned long long* pbad, int nblocks, hipStream_t s);
+hipError_t mvd_launch_fill(float* x, int64_t n, float val, hipStream_t s);
+hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s);
+hipError_t mvd_launch_spec_z(const double* A2, int kz, int cz, int M, int ny, int nz,
+                             const double* twz, double invV, float* main_out, float* nyq_out,
+                             hipStream_t s);

@@ -1,0 +1,589 @@
+// gfx950 kernels of the sequential multi-view update.
+//
+// One view-update (section 7) is two circular convolutions and the pointwise
+// steps of eq. 15 around them.  With the x axis transformed real-to-complex
+// (half spectrum), one convolution is four passes over the volume:
+//
+//   y forward  ->  z forward, x H_v, z inverse  ->  y inverse  ->  x pass
+//
+// and the x pass of the first convolution (blur with P_v) is fused with the
+// ratio phi_v / max(b, eps) and the forward x transform of the ratio; the x
+// pass of the second (back-projection with K_v) is fused with the
+// multiplicative update, the Tikhonov step, the weight blend, the FP64 flux
+// partials and the forward x transform of the new estimate, which is the
+// input of the next view's blur.  So a view-update is 8 launches and every
+// voxel crosses HBM 8 times (plus the reads of phi_v, w_v and the spectra).
+// The 1/V of the inverse transforms is folded into the stored spectra.
+#include <hip/hip_runtime.h>
+
+#include "fft_engine.h"
+#include "mvd_kernels.h"
+
+using namespace mvdk;
+
+namespace {
+
+__device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int njobs, int kind,
+                                        int param, int& local) {
+  int t = blockIdx.x;
+  for (int j = 0; j < njobs; ++j) {
+    const int c = mvd_tiles(jobs[j], kind, param);
+    if (t < c) {
+      local = t;
+      return j;
+    }
+    t -= c;
+  }
+  local = 0;
+  return -1;
+}
+
+template <int T>
+__device__ __forceinline__ void block_reduce(double& f, unsigned& a, unsigned& b, double* sf,
+                                             unsigned* sa, unsigned* sb) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    f += __shfl_xor(f, o);
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sf[w] = f;
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    f = 0.0;
+    a = b = 0;
+    for (int i = 0; i < T / 64; ++i) {
+      f += sf[i];
+      a += sa[i];
+      b += sb[i];
+    }
+  }
+}
+
+__device__ __forceinline__ float tikhonov(float u, float lamp) {
+  // solves lamp t^2 + t = u for t >= 0 in the form without cancellation
+  return lamp > 0.f ? 2.f * u / (1.f + sqrtf(1.f + 4.f * lamp * u)) : u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// x pass.  MODE 0: forward real-to-complex of psi.  MODE 1: inverse x of the
+// blurred spectrum -> b, q = phi / max(b, eps), forward x of q.  MODE 2:
+// inverse x of the back-projected spectrum -> c, update psi, forward x of the
+// new psi (skipped when write_spec == 0).
+//
+// A row of nx reals is handled as M = nx/2 complex values z[n] = x[2n] +
+// i x[2n+1]; the half spectrum follows from the M-point transform Z by
+//   X[k] = (Z[k] + conj Z[M-k])/2 - i e^{-2 pi i k/nx} (Z[k] - conj Z[M-k])/2
+// and the inverse rebuilds Z from X before an M-point inverse transform.
+template <int MODE, int T, int RW, int MAXM>
+__global__ void __launch_bounds__(T)
+    k_xpass(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+            const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
+            int write_spec) {
+  __shared__ float2 lds[RW * MAXM];
+  __shared__ double rf[T / 64];
+  __shared__ unsigned ra[T / 64], rb[T / 64];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_X, RW, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  const int tid = threadIdx.x;
+  if (MODE != 0 && v >= J.nviews) {
+    if (tid == 0 && parts) {
+      if (MODE == 2) {
+        parts[blockIdx.x].flux = 0.0;
+        parts[blockIdx.x].neg_clamps = 0;
+      } else {
+        parts[blockIdx.x].ratio_clamps = 0;
+      }
+    }
+    return;
+  }
+  const int M = J.M, nx = J.nx;
+  const int row0 = local * RW;
+  const int nrows = min(RW, J.ny * J.nz - row0);
+  float2* spec = reinterpret_cast<float2*>(J.spec);
+  float2* nyq = spec + J.spec_main;
+  const float2* pp = twp + J.pp;
+  const FftPlan pl = plans[J.plan_x];
+  const LdsRow<MAXM> L{lds};
+  constexpr int EPT = (RW * MAXM + T - 1) / T;
+  constexpr int NPIT = (RW * (MAXM / 2 + 1) + T - 1) / T;
+  const int npair = M / 2 + 1;
+  const int64_t vo = (int64_t)v * J.V;
+  const float eps = J.eps, lamp = J.lamp;
+  const float* wv = J.w ? J.w + vo : nullptr;
+
+  // prefetch the pointwise operands of this thread's elements
+  float2 pa[EPT], pb[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int it = tid + i * T;
+    const int r = it / M, p = it - r * M;
+    pa[i] = pb[i] = make_float2(0.f, 0.f);
+    if (r < nrows) {
+      const int64_t g = (int64_t)(row0 + r) * nx + 2 * p;
+      if (MODE == 1) pa[i] = *reinterpret_cast<const float2*>(J.phi + vo + g);
+      if (MODE != 1) pa[i] = *reinterpret_cast<const float2*>(J.psi + g);
+      if (MODE == 2 && wv) pb[i] = *reinterpret_cast<const float2*>(wv + g);
+    }
+  }
+
+  double flux = 0.0;
+  unsigned ncr = 0, ncn = 0;
+  bool bad = false;
+  if (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int it = tid + i * T;
+      const int r = it / M, p = it - r * M;
+      if (r < nrows) L.st(r, p, pa[i]);
+    }
+    __syncthreads();
+  } else {
+    // rebuild the M-point spectrum Z of this row from its half spectrum X
+    float2 xa[NPIT], xb[NPIT];
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = tid + i * T;
+      const int r = it / npair, k = it - r * npair;
+      if (r < nrows) {
+        const int64_t rbase = (int64_t)(row0 + r) * M;
+        xa[i] = spec[rbase + k];
+        xb[i] = (k == 0) ? nyq[row0 + r] : spec[rbase + M - k];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = tid + i * T;
+      const int r = it / npair, k = it - r * npair;
+      if (r < nrows) {
+        const float2 a = xa[i], b = xb[i], t = pp[k];
+        // Z[k] = (a + conj b) + i conj(t) (a - conj b)
+        const float2 s = make_float2(a.x + b.x, a.y - b.y);
+        const float2 d = make_float2(a.x - b.x, a.y + b.y);
+        const float2 e = cmul(cconj(t), d);
+        L.st(r, k, make_float2(s.x - e.y, s.y + e.x));
+        if (k != 0 && 2 * k != M) {
+          // Z[M-k] = (b + conj a) - i t (b - conj a)
+          const float2 s2 = make_float2(b.x + a.x, b.y - a.y);
+          const float2 d2 = make_float2(b.x - a.x, b.y + a.y);
+          const float2 e2 = cmul(t, d2);
+          L.st(r, M - k, make_float2(s2.x + e2.y, s2.y - e2.x));
+        }
+      }
+    }
+    __syncthreads();
+    fft_lines<true, MAXM, T, RW, false>(pl, twp, L, L, L);
+
+    // pointwise step on the real values held two per complex entry
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int it = tid + i * T;
+      const int r = it / M, p = it - r * M;
+      if (r < nrows) {
+        const float2 z = L.ld(r, p);
+        float2 o;
+        if (MODE == 1) {
+          ncr += (z.x < eps) + (z.y < eps);
+          o = make_float2(pa[i].x / fmaxf(z.x, eps), pa[i].y / fmaxf(z.y, eps));
+        } else {
+          ncn += (z.x < 0.f) + (z.y < 0.f);
+          const float ux = pa[i].x * (z.x > 0.f ? z.x : 0.f);
+          const float uy = pa[i].y * (z.y > 0.f ? z.y : 0.f);
+          const float tx = tikhonov(ux, lamp), ty = tikhonov(uy, lamp);
+          if (wv) {
+            o = make_float2(pa[i].x + pb[i].x * (tx - pa[i].x), pa[i].y + pb[i].y * (ty - pa[i].y));
+          } else {
+            o = make_float2(tx, ty);
+          }
+          *reinterpret_cast<float2*>(J.psi + (int64_t)(row0 + r) * nx + 2 * p) = o;
+          flux += (double)o.x + (double)o.y;
+          bad |= !(isfinite(o.x) && isfinite(o.y));
+        }
+        L.st(r, p, o);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (MODE == 0 || write_spec) {
+    fft_lines<false, MAXM, T, RW, false>(pl, twp, L, L, L);
+    // half spectrum of the row from the M-point transform
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = tid + i * T;
+      const int r = it / npair, k = it - r * npair;
+      if (r < nrows) {
+        const int64_t rbase = (int64_t)(row0 + r) * M;
+        const float2 zk = L.ld(r, k);
+        if (k == 0) {
+          spec[rbase] = make_float2(zk.x + zk.y, 0.f);
+          nyq[row0 + r] = make_float2(zk.x - zk.y, 0.f);
+        } else {
+          const float2 zm = L.ld(r, M - k);
+          const float2 t = pp[k];
+          const float2 s = make_float2(zk.x + zm.x, zk.y - zm.y);
+          const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+          const float2 e = cmul(t, d);
+          spec[rbase + k] = make_float2(0.5f * (s.x + e.y), 0.5f * (s.y - e.x));
+          if (2 * k != M) {
+            const float2 s2 = make_float2(zm.x + zk.x, zm.y - zk.y);
+            const float2 d2 = make_float2(zm.x - zk.x, zm.y + zk.y);
+            const float2 e2 = cmul(cconj(t), d2);
+            spec[rbase + M - k] = make_float2(0.5f * (s2.x - e2.y), 0.5f * (s2.y + e2.x));
+          }
+        }
+      }
+    }
+  }
+
+  if (MODE != 0) {
+    if (MODE == 2 && bad) atomicOr(flags, 1);
+    if (parts) {
+      block_reduce<T>(flux, ncr, ncn, rf, ra, rb);
+      if (tid == 0) {
+        if (MODE == 2) {
+          parts[blockIdx.x].flux = flux;
+          parts[blockIdx.x].neg_clamps = ncn;
+        } else {
+          parts[blockIdx.x].ratio_clamps = ncr;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y pass: complex transform along y of TX adjacent kx columns (main part) or
+// TX z-lines of the Nyquist plane, in place.
+template <bool INV, int T, int TX, int MAXL>
+__global__ void __launch_bounds__(T)
+    k_ypass(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+            const float2* __restrict__ twp, int v) {
+  __shared__ float2 lds[MAXL * TX];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  const int M = J.M, ny = J.ny, nz = J.nz;
+  float2* spec = reinterpret_cast<float2*>(J.spec);
+  const int nxt = mvd_cdiv(M, TX);
+  GTile g;
+  if (local < nxt * nz) {
+    const int xt = local % nxt, z = local / nxt;
+    g.base = spec + (int64_t)z * ny * M + xt * TX;
+    g.ls = 1;
+    g.ps = M;
+    g.nl = min(TX, M - xt * TX);
+  } else {
+    const int t2 = local - nxt * nz;
+    g.base = spec + J.spec_main + (int64_t)t2 * TX * ny;
+    g.ls = ny;
+    g.ps = 1;
+    g.nl = min(TX, nz - t2 * TX);
+  }
+  const FftPlan pl = plans[J.plan_y];
+  fft_lines<INV, MAXL, T, TX, true>(pl, twp, g, LdsCol<TX>{lds}, g);
+}
+
+// ---------------------------------------------------------------------------
+// z pass with the spectral product: forward z transform, multiply by the
+// kernel spectrum of view v (conjugated for the mirrored kernel P_v*), inverse
+// z transform, all while the tile stays in LDS.
+template <int T, int TX, int MAXL>
+__global__ void __launch_bounds__(T)
+    k_zconv(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+            const float2* __restrict__ twp, int v, int role, int conjH) {
+  __shared__ float2 lds[MAXL * TX];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  const int M = J.M, ny = J.ny, nz = J.nz;
+  const int nxt = mvd_cdiv(M, TX);
+  int64_t off, ps;
+  int nl;
+  if (local < nxt * ny) {
+    const int xt = local % nxt, y = local / nxt;
+    off = (int64_t)y * M + xt * TX;
+    ps = (int64_t)ny * M;
+    nl = min(TX, M - xt * TX);
+  } else {
+    const int t2 = local - nxt * ny;
+    off = J.spec_main + (int64_t)t2 * TX;
+    ps = ny;
+    nl = min(TX, ny - t2 * TX);
+  }
+  const float2* H = reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.spec_elems + off;
+  GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
+  constexpr int EPT = (TX * MAXL + T - 1) / T;
+  const int tid = threadIdx.x;
+  float2 h[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * T;
+    const int line = e % TX, pos = e / TX;
+    h[i] = (pos < nz && line < nl) ? H[line + pos * ps] : make_float2(0.f, 0.f);
+  }
+  const FftPlan pl = plans[J.plan_z];
+  const LdsCol<TX> S{lds};
+  fft_lines<false, MAXL, T, TX, true>(pl, twp, g, S, S);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * T;
+    const int line = e % TX, pos = e / TX;
+    if (pos < nz) {
+      const float2 a = S.ld(line, pos);
+      S.st(line, pos, cmul(a, conjH ? cconj(h[i]) : h[i]));
+    }
+  }
+  __syncthreads();
+  fft_lines<true, MAXL, T, TX, true>(pl, twp, S, S, g);
+}
+
+// ---------------------------------------------------------------------------
+// Sum the per-tile partials of one iteration: block v handles view v.
+__global__ void __launch_bounds__(256)
+    k_reduce(const Partial* __restrict__ parts, int ntiles, double* __restrict__ flux,
+             unsigned long long* __restrict__ ratio, unsigned long long* __restrict__ neg) {
+  __shared__ double sf[256];
+  __shared__ unsigned long long sa[256], sb[256];
+  const Partial* p = parts + (int64_t)blockIdx.x * ntiles;
+  double f = 0.0;
+  unsigned long long a = 0, b = 0;
+  for (int t = threadIdx.x; t < ntiles; t += 256) {
+    f += p[t].flux;
+    a += p[t].ratio_clamps;
+    b += p[t].neg_clamps;
+  }
+  sf[threadIdx.x] = f;
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sf[threadIdx.x] += sf[threadIdx.x + s];
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    flux[blockIdx.x] = sf[0];
+    ratio[blockIdx.x] = sa[0];
+    neg[blockIdx.x] = sb[0];
+  }
+}
+
+// Count values that are non-finite or outside [lo, hi] and sum them in FP64,
+// one partial per block (the host adds the partials in a fixed order).
+__global__ void __launch_bounds__(256)
+    k_check(const float* __restrict__ x, int64_t n, float lo, float hi, double* __restrict__ psum,
+            unsigned long long* __restrict__ pbad) {
+  __shared__ double sf[256];
+  __shared__ unsigned long long sb[256];
+  double f = 0.0;
+  unsigned long long b = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float a = x[i];
+    if (!(a >= lo && a <= hi)) ++b;  // also catches NaN
+    f += (double)a;
+  }
+  sf[threadIdx.x] = f;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sf[threadIdx.x] += sf[threadIdx.x + s];
+      sb[threadIdx.x] += sb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    psum[blockIdx.x] = sf[0];
+    pbad[blockIdx.x] = sb[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill(float* __restrict__ x, int64_t n, float val) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    x[i] = val;
+}
+
+__global__ void k_set_int(int* __restrict__ p, int val) {
+  if (threadIdx.x == 0) *p = val;
+}
+
+// Last stage of the kernel-spectrum build, in FP64: for every (kx, ky) the
+// z sum over the kernel's support, scaled by 1/V and rounded once to FP32.
+__global__ void __launch_bounds__(256)
+    k_spec_z(const double2* __restrict__ A2, int kz, int cz, int M, int ny, int nz,
+             const double2* __restrict__ twz, double invV, float2* __restrict__ main_out,
+             float2* __restrict__ nyq_out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)(M + 1) * ny * nz;
+  if (idx >= total) return;
+  const int kx = (int)(idx % (M + 1));
+  const int64_t rest = idx / (M + 1);
+  const int ky = (int)(rest % ny);
+  const int kzp = (int)(rest / ny);
+  double sr = 0.0, si = 0.0;
+  for (int dz = 0; dz < kz; ++dz) {
+    const double2 a = A2[((int64_t)dz * ny + ky) * (M + 1) + kx];
+    int64_t m = ((int64_t)kzp * (dz - cz)) % nz;
+    if (m < 0) m += nz;
+    const double2 w = twz[m];
+    sr += a.x * w.x - a.y * w.y;
+    si += a.x * w.y + a.y * w.x;
+  }
+  const float2 o = make_float2((float)(sr * invV), (float)(si * invV));
+  if (kx < M)
+    main_out[((int64_t)kzp * ny + ky) * M + kx] = o;
+  else
+    nyq_out[(int64_t)kzp * ny + ky] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape candidates.  Column passes: (threads, lines per tile, max
+// length).  Row passes: (threads, rows per tile, max half-row length).
+
+#define MVD_COL_CFGS(X) \
+  X(0, 64, 16, 64)      \
+  X(1, 128, 16, 128)    \
+  X(2, 256, 16, 256)    \
+  X(3, 256, 16, 512)    \
+  X(4, 256, 8, 512)     \
+  X(5, 128, 8, 256)     \
+  X(6, 512, 16, 512)    \
+  X(7, 256, 32, 128)    \
+  X(8, 256, 8, 256)
+
+#define MVD_ROW_CFGS(X) \
+  X(0, 256, 32, 32)     \
+  X(1, 256, 16, 64)     \
+  X(2, 256, 8, 128)     \
+  X(3, 256, 4, 256)     \
+  X(4, 256, 2, 512)     \
+  X(5, 256, 8, 256)     \
+  X(6, 256, 4, 512)     \
+  X(7, 128, 4, 128)
+
+static const int kColCfg[][3] = {
+#define X(i, t, tx, l) {t, tx, l},
+    MVD_COL_CFGS(X)
+#undef X
+};
+static const int kRowCfg[][3] = {
+#define X(i, t, rw, m) {t, rw, m},
+    MVD_ROW_CFGS(X)
+#undef X
+};
+
+int mvd_num_cfgs(int kind) {
+  return kind == PASS_X ? (int)(sizeof(kRowCfg) / sizeof(kRowCfg[0]))
+                        : (int)(sizeof(kColCfg) / sizeof(kColCfg[0]));
+}
+int mvd_cfg_threads(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][0] : kColCfg[cfg][0]; }
+int mvd_cfg_param(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][1] : kColCfg[cfg][1]; }
+int mvd_cfg_maxlen(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][2] : kColCfg[cfg][2]; }
+
+hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
+                        int write_spec) {
+  switch (cfg) {
+#define X(i, t, rw, m)                                                                              \
+  case i:                                                                                           \
+    if (mode == 0)                                                                                  \
+      k_xpass<0, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
+                                                       flags, write_spec);                         \
+    else if (mode == 1)                                                                             \
+      k_xpass<1, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
+                                                       flags, write_spec);                         \
+    else                                                                                            \
+      k_xpass<2, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
+                                                       flags, write_spec);                         \
+    break;
+    MVD_ROW_CFGS(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v) {
+  switch (cfg) {
+#define X(i, t, tx, l)                                                                          \
+  case i:                                                                                       \
+    if (inv)                                                                                    \
+      k_ypass<true, t, tx, l><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v);  \
+    else                                                                                        \
+      k_ypass<false, t, tx, l><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v); \
+    break;
+    MVD_COL_CFGS(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH) {
+  switch (cfg) {
+#define X(i, t, tx, l)                                                                              \
+  case i:                                                                                           \
+    k_zconv<t, tx, l><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, role, conjH); \
+    break;
+    MVD_COL_CFGS(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_reduce(const Partial* parts, int ntiles, int nviews, double* flux,
+                             unsigned long long* ratio, unsigned long long* neg, hipStream_t s) {
+  k_reduce<<<nviews, 256, 0, s>>>(parts, ntiles, flux, ratio, neg);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_check(const float* x, int64_t n, float lo, float hi, double* psum,
+                            unsigned long long* pbad, int nblocks, hipStream_t s) {
+  k_check<<<nblocks, 256, 0, s>>>(x, n, lo, hi, psum, pbad);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_fill(float* x, int64_t n, float val, hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  k_fill<<<(int)nb, 256, 0, s>>>(x, n, val);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s) {
+  k_set_int<<<1, 64, 0, s>>>(p, val);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_spec_z(const double* A2, int kz, int cz, int M, int ny, int nz,
+                             const double* twz, double invV, float* main_out, float* nyq_out,
+                             hipStream_t s) {
+  const int64_t total = (int64_t)(M + 1) * ny * nz;
+  const int64_t nb = (total + 255) / 256;
+  k_spec_z<<<(unsigned)nb, 256, 0, s>>>(reinterpret_cast<const double2*>(A2), kz, cz, M, ny, nz,
+                                         reinterpret_cast<const double2*>(twz), invV,
+                                         reinterpret_cast<float2*>(main_out),
+                                         reinterpret_cast<float2*>(nyq_out));
+  return hipGetLastError();
+}

@@ -1,0 +1,742 @@
+// Runtime behind the C ABI: validation, device buffers, plans, kernel
+// spectra, pass scheduling and HIP-graph replay of one iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "mvd.h"
+#include "mvd_host.h"
+#include "mvd_kernels.h"
+#include "mvd_types.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      if (e_ == hipErrorOutOfMemory) throw Error(MVD_ENOMEM, std::string(#expr) + ": out of memory"); \
+      throw Error(MVD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    }                                                                                    \
+  } while (0)
+
+[[noreturn]] void bad(const std::string& m) { throw Error(MVD_EINVAL, m); }
+
+struct Block {
+  int nx = 0, ny = 0, nz = 0, M = 0;
+  int64_t V = 0, spec_main = 0, spec_elems = 0;
+  float* psi = nullptr;
+  float* spec = nullptr;
+  float* phi = nullptr;
+  float* w = nullptr;
+  float* H[N_ROLES] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<mvdh::Kern> P;  // prepared PSFs
+  double s = 0;
+  float eps = 0, lamp = 0;
+};
+
+}  // namespace
+
+struct mvd_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  mvd_alloc_fn alloc = nullptr;
+  mvd_free_fn free_fn = nullptr;
+  void* actx = nullptr;
+  std::vector<void*> allocs;
+  std::vector<Block> blocks;
+  int nviews = 0;
+  double lambda = 0, eps_scale = 1e-6;
+  bool use_graphs = true;
+  int force_cfg = 0;
+  // device tables
+  JobDesc* d_jobs = nullptr;
+  FftPlan* d_plans = nullptr;
+  float2* d_tw = nullptr;
+  Partial* d_parts = nullptr;
+  int* d_flags = nullptr;
+  double* d_flux = nullptr;
+  unsigned long long* d_ratio = nullptr;
+  unsigned long long* d_neg = nullptr;
+  double* d_chk_sum = nullptr;
+  unsigned long long* d_chk_bad = nullptr;
+  std::vector<JobDesc> jobs;
+  std::map<int, int> plan_of_len;
+  std::map<int, int> pp_of_nx;
+  int cfg_x = 0, cfg_y = 0, cfg_z = 0;
+  int grid_x = 0, grid_y = 0, grid_z = 0;
+  bool spec_valid = false;
+  bool built[N_ROLES] = {true, false, false, false};
+  int64_t iterations = 0;
+  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::string err;
+
+  void* dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, actx);
+      if (!p) throw Error(MVD_ENOMEM, "allocator callback failed for " + std::to_string(bytes) + " bytes");
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error(MVD_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+      }
+    }
+    allocs.push_back(p);
+    return p;
+  }
+
+  void release() {
+    for (auto& g : exec)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    if (cap) (void)hipDeviceSynchronize();
+    for (void* p : allocs) {
+      if (alloc && free_fn)
+        free_fn(p, actx);
+      else if (!alloc)
+        (void)hipFree(p);
+    }
+    allocs.clear();
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+};
+
+namespace {
+
+int64_t vox(const int* d) { return (int64_t)d[0] * d[1] * d[2]; }
+
+void validate_shape(const mvd_problem* p, int idx) {
+  const std::string b = "block " + std::to_string(idx) + ": ";
+  if (!p) bad(b + "problem is NULL");
+  if (p->n_views < 1 || p->n_views > MVD_MAX_VIEWS) bad(b + "n_views must be in [1, 64]");
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  if (nx < 4 || nx % 2 || nx / 2 > MVD_MAX_LEN) bad(b + "nx must be even, >= 4 and <= 1024");
+  if (ny < 2 || ny > MVD_MAX_LEN || nz < 2 || nz > MVD_MAX_LEN) bad(b + "ny and nz must be in [2, 512]");
+  if (!mvdh::is_smooth5(nx / 2) || !mvdh::is_smooth5(ny) || !mvdh::is_smooth5(nz))
+    bad(b + "every extent must be 5-smooth (2^a 3^b 5^c)");
+  if (!p->views || !p->psfs || !p->psf_dims) bad(b + "views, psfs and psf_dims are required");
+  if (p->mem_kind != MVD_MEM_HOST && p->mem_kind != MVD_MEM_DEVICE) bad(b + "mem_kind must be host or device");
+  for (int v = 0; v < p->n_views; ++v) {
+    if (!p->views[v] || !p->psfs[v]) bad(b + "view or PSF pointer " + std::to_string(v) + " is NULL");
+    if (p->weights && !p->weights[v]) bad(b + "weight pointer " + std::to_string(v) + " is NULL");
+    const int* k = p->psf_dims + 3 * v;
+    for (int a = 0; a < 3; ++a) {
+      if (k[a] < 1) bad(b + "PSF extents must be >= 1");
+      if ((k[a] | 1) > p->dims[a]) bad(b + "PSF " + std::to_string(v) + " (odd-padded) is larger than the volume");
+    }
+  }
+}
+
+void validate_host_values(const mvd_problem* p, int idx) {
+  const std::string b = "block " + std::to_string(idx) + ": ";
+  const int64_t V = vox(p->dims);
+  for (int v = 0; v < p->n_views; ++v) {
+    const float* x = p->views[v];
+    for (int64_t i = 0; i < V; ++i)
+      if (!(x[i] >= 0.f) || !std::isfinite(x[i])) bad(b + "view " + std::to_string(v) + " has a negative or non-finite value");
+    if (p->weights) {
+      const float* w = p->weights[v];
+      for (int64_t i = 0; i < V; ++i)
+        if (!(w[i] >= 0.f && w[i] <= 1.f)) bad(b + "weights " + std::to_string(v) + " outside [0, 1]");
+    }
+  }
+}
+
+std::vector<float> fetch_psf(const mvd_problem* p, int v) {
+  const int* k = p->psf_dims + 3 * v;
+  const size_t n = (size_t)k[0] * k[1] * k[2];
+  std::vector<float> h(n);
+  if (p->mem_kind == MVD_MEM_HOST)
+    std::memcpy(h.data(), p->psfs[v], n * sizeof(float));
+  else
+    HIPCHECK(hipMemcpy(h.data(), p->psfs[v], n * sizeof(float), hipMemcpyDeviceToHost));
+  return h;
+}
+
+// Device check of one array: count of values outside [lo, hi] (or
+// non-finite) and the FP64 sum.
+void device_check(mvd_handle* h, const float* x, int64_t n, float lo, float hi, double* sum,
+                  unsigned long long* nbad) {
+  const int nb = 1024;
+  if (!h->d_chk_sum) {
+    h->d_chk_sum = (double*)h->dalloc(nb * sizeof(double));
+    h->d_chk_bad = (unsigned long long*)h->dalloc(nb * sizeof(unsigned long long));
+  }
+  double* ps = h->d_chk_sum;
+  unsigned long long* pb = h->d_chk_bad;
+  HIPCHECK(mvd_launch_check(x, n, lo, hi, ps, pb, nb, h->stream));
+  std::vector<double> hs(nb);
+  std::vector<unsigned long long> hb(nb);
+  HIPCHECK(hipMemcpyAsync(hs.data(), ps, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(hb.data(), pb, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  double s = 0;
+  unsigned long long c = 0;
+  for (int i = 0; i < nb; ++i) {
+    s += hs[i];
+    c += hb[i];
+  }
+  *sum = s;
+  *nbad = c;
+}
+
+int plan_for(mvd_handle* h, int L, std::vector<FftPlan>& plans, std::vector<float2>& tw) {
+  auto it = h->plan_of_len.find(L);
+  if (it != h->plan_of_len.end()) return it->second;
+  FftPlan pl{};
+  pl.L = L;
+  const auto r = mvdh::factorize(L);
+  pl.nst = (int)r.size();
+  for (int i = 0; i < pl.nst; ++i) pl.radix[i] = r[i];
+  pl.tw = (int)tw.size();
+  for (const auto& c : mvdh::twiddles(L)) tw.push_back(make_float2((float)c.real(), (float)c.imag()));
+  plans.push_back(pl);
+  h->plan_of_len[L] = (int)plans.size() - 1;
+  return (int)plans.size() - 1;
+}
+
+// Spectrum of a centred kernel into the stored layout (main part then the
+// Nyquist plane), scaled by 1/V: x and y stages on the host, z on the device.
+void upload_spectrum(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* dst) {
+  const auto A2 = mvdh::spectrum_xy(K, B.nx, B.ny);
+  const auto tz = mvdh::twiddles(B.nz);
+  double* dA = nullptr;
+  double* dT = nullptr;
+  HIPCHECK(hipMalloc(&dA, A2.size() * sizeof(mvdh::cd)));
+  hipError_t e = hipMalloc(&dT, tz.size() * sizeof(mvdh::cd));
+  if (e != hipSuccess) {
+    (void)hipFree(dA);
+    HIPCHECK(e);
+  }
+  try {
+    HIPCHECK(hipMemcpyAsync(dA, A2.data(), A2.size() * sizeof(mvdh::cd), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(dT, tz.data(), tz.size() * sizeof(mvdh::cd), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(mvd_launch_spec_z(dA, K.kz, (K.kz - 1) / 2, B.M, B.ny, B.nz, dT, 1.0 / (double)B.V, dst,
+                               dst + 2 * B.spec_main, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  } catch (...) {
+    (void)hipFree(dA);
+    (void)hipFree(dT);
+    throw;
+  }
+  (void)hipFree(dA);
+  (void)hipFree(dT);
+}
+
+int pick_cfg(int kind, int maxlen, int force) {
+  const int n = mvd_num_cfgs(kind);
+  if (force > 0) {
+    const int c = force - 1;
+    if (c < n && mvd_cfg_maxlen(kind, c) >= maxlen) return c;
+  }
+  // default: the smallest tile family that holds the longest line
+  static const int xo[] = {0, 1, 2, 3, 4};
+  static const int co[] = {0, 1, 2, 3};
+  if (kind == PASS_X) {
+    for (int c : xo)
+      if (mvd_cfg_maxlen(kind, c) >= maxlen) return c;
+  } else {
+    for (int c : co)
+      if (mvd_cfg_maxlen(kind, c) >= maxlen) return c;
+  }
+  bad("no launch shape holds length " + std::to_string(maxlen));
+}
+
+int total_tiles(const mvd_handle* h, int kind, int param) {
+  int64_t t = 0;
+  for (const auto& j : h->jobs) t += mvd_tiles(j, kind, param);
+  if (t > 0x7fffffff) bad("too many tiles");
+  return (int)t;
+}
+
+void build_jobs(mvd_handle* h) {
+  h->jobs.clear();
+  for (auto& B : h->blocks) {
+    JobDesc j{};
+    j.nx = B.nx;
+    j.ny = B.ny;
+    j.nz = B.nz;
+    j.M = B.M;
+    j.nviews = h->nviews;
+    j.plan_x = h->plan_of_len.at(B.M);
+    j.plan_y = h->plan_of_len.at(B.ny);
+    j.plan_z = h->plan_of_len.at(B.nz);
+    j.pp = h->pp_of_nx.at(B.nx);
+    j.V = B.V;
+    j.spec_main = B.spec_main;
+    j.spec_elems = B.spec_elems;
+    j.psi = B.psi;
+    j.spec = B.spec;
+    j.phi = B.phi;
+    j.w = B.w;
+    for (int r = 0; r < N_ROLES; ++r) j.H[r] = B.H[r];
+    j.eps = B.eps;
+    j.lamp = B.lamp;
+    h->jobs.push_back(j);
+  }
+  HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
+                          h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options* o) {
+  if (nb < 1) bad("n_blocks must be >= 1");
+  if (!ps) bad("problem is NULL");
+  for (int b = 0; b < nb; ++b) validate_shape(&ps[b], b);
+  for (int b = 1; b < nb; ++b)
+    if (ps[b].n_views != ps[0].n_views) bad("every block needs the same number of views");
+  if (o) {
+    if (!(o->lambda >= 0) || !std::isfinite(o->lambda)) bad("lambda must be finite and >= 0");
+    if (!(o->eps_scale >= 0) || !std::isfinite(o->eps_scale)) bad("eps_scale must be finite and >= 0");
+    if ((o->alloc == nullptr) != (o->free == nullptr)) bad("alloc and free callbacks come together");
+    if (o->tile_config < 0) bad("tile_config must be >= 0");
+    h->lambda = o->lambda;
+    h->eps_scale = o->eps_scale > 0 ? o->eps_scale : 1e-6;
+    h->stream = (hipStream_t)o->stream;
+    h->alloc = o->alloc;
+    h->free_fn = o->free;
+    h->actx = o->alloc_ctx;
+    h->use_graphs = o->use_graphs != 0;
+    h->force_cfg = o->tile_config;
+  }
+  h->nviews = ps[0].n_views;
+  // host-memory values are checked before any device call
+  std::vector<std::vector<mvdh::Kern>> prepared(nb);
+  for (int b = 0; b < nb; ++b) {
+    if (ps[b].mem_kind == MVD_MEM_HOST) {
+      validate_host_values(&ps[b], b);
+      for (int v = 0; v < ps[b].n_views; ++v) {
+        const int* k = ps[b].psf_dims + 3 * v;
+        try {
+          prepared[b].push_back(mvdh::prepare_psf(ps[b].psfs[v], k[0], k[1], k[2]));
+        } catch (const std::invalid_argument& e) {
+          bad("block " + std::to_string(b) + " PSF " + std::to_string(v) + ": " + e.what());
+        }
+      }
+    }
+  }
+
+  HIPCHECK(hipGetDevice(&h->device));
+  HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+
+  std::vector<FftPlan> plans;
+  std::vector<float2> tw;
+  h->blocks.resize(nb);
+  const int N = h->nviews;
+  for (int b = 0; b < nb; ++b) {
+    const mvd_problem& p = ps[b];
+    Block& B = h->blocks[b];
+    B.nx = p.dims[0];
+    B.ny = p.dims[1];
+    B.nz = p.dims[2];
+    B.M = B.nx / 2;
+    B.V = vox(p.dims);
+    B.spec_main = (int64_t)B.M * B.ny * B.nz;
+    B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
+    B.psi = (float*)h->dalloc(B.V * sizeof(float));
+    B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
+    B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
+    if (p.weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
+    B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.spec_elems * 2 * sizeof(float));
+    const hipMemcpyKind kind = p.mem_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    for (int v = 0; v < N; ++v) {
+      HIPCHECK(hipMemcpyAsync(B.phi + (size_t)v * B.V, p.views[v], B.V * sizeof(float), kind, h->stream));
+      if (p.weights)
+        HIPCHECK(hipMemcpyAsync(B.w + (size_t)v * B.V, p.weights[v], B.V * sizeof(float), kind, h->stream));
+    }
+    // FP64 mean over all views, plus the value checks of device inputs
+    double total = 0;
+    for (int v = 0; v < N; ++v) {
+      double s;
+      unsigned long long nbad;
+      device_check(h, B.phi + (size_t)v * B.V, B.V, 0.f, INFINITY, &s, &nbad);
+      if (nbad) bad("block " + std::to_string(b) + ": view " + std::to_string(v) + " has a negative or non-finite value");
+      total += s;
+      if (p.weights) {
+        device_check(h, B.w + (size_t)v * B.V, B.V, 0.f, 1.f, &s, &nbad);
+        if (nbad) bad("block " + std::to_string(b) + ": weights " + std::to_string(v) + " outside [0, 1]");
+      }
+    }
+    B.s = total / ((double)N * (double)B.V);
+    if (!(B.s > 0)) bad("block " + std::to_string(b) + ": the views are all zero");
+    B.eps = (float)(h->eps_scale * B.s);
+    B.lamp = (float)(h->lambda / B.s);
+    if (p.mem_kind == MVD_MEM_DEVICE) {
+      for (int v = 0; v < N; ++v) {
+        const int* k = p.psf_dims + 3 * v;
+        const auto hp = fetch_psf(&p, v);
+        try {
+          prepared[b].push_back(mvdh::prepare_psf(hp.data(), k[0], k[1], k[2]));
+        } catch (const std::invalid_argument& e) {
+          bad("block " + std::to_string(b) + " PSF " + std::to_string(v) + ": " + e.what());
+        }
+      }
+    }
+    B.P = std::move(prepared[b]);
+    for (int v = 0; v < N; ++v) upload_spectrum(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.spec_elems * 2);
+    plan_for(h, B.M, plans, tw);
+    plan_for(h, B.ny, plans, tw);
+    plan_for(h, B.nz, plans, tw);
+    if (!h->pp_of_nx.count(B.nx)) {
+      h->pp_of_nx[B.nx] = (int)tw.size();
+      const auto t = mvdh::twiddles(B.nx);
+      for (int k = 0; k < B.M; ++k) tw.push_back(make_float2((float)t[k].real(), (float)t[k].imag()));
+    }
+    HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, h->stream));
+  }
+  h->d_plans = (FftPlan*)h->dalloc(plans.size() * sizeof(FftPlan));
+  h->d_tw = (float2*)h->dalloc(tw.size() * sizeof(float2));
+  HIPCHECK(hipMemcpyAsync(h->d_plans, plans.data(), plans.size() * sizeof(FftPlan), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, h->stream));
+  h->d_jobs = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
+
+  int maxM = 0, maxY = 0, maxZ = 0;
+  for (auto& B : h->blocks) {
+    maxM = std::max(maxM, B.M);
+    maxY = std::max(maxY, B.ny);
+    maxZ = std::max(maxZ, B.nz);
+  }
+  build_jobs(h);
+  h->cfg_x = pick_cfg(PASS_X, maxM, h->force_cfg);
+  h->cfg_y = pick_cfg(PASS_Y, maxY, h->force_cfg);
+  h->cfg_z = pick_cfg(PASS_Z, maxZ, h->force_cfg);
+  h->grid_x = total_tiles(h, PASS_X, mvd_cfg_param(PASS_X, h->cfg_x));
+  h->grid_y = total_tiles(h, PASS_Y, mvd_cfg_param(PASS_Y, h->cfg_y));
+  h->grid_z = total_tiles(h, PASS_Z, mvd_cfg_param(PASS_Z, h->cfg_z));
+  h->d_parts = (Partial*)h->dalloc((size_t)N * h->grid_x * sizeof(Partial));
+  h->d_flags = (int*)h->dalloc(sizeof(int));
+  h->d_flux = (double*)h->dalloc(N * sizeof(double));
+  h->d_ratio = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+  h->d_neg = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+  HIPCHECK(hipMemsetAsync(h->d_parts, 0, (size_t)N * h->grid_x * sizeof(Partial), h->stream));
+  HIPCHECK(hipMemsetAsync(h->d_flux, 0, N * sizeof(double), h->stream));
+  HIPCHECK(hipMemsetAsync(h->d_ratio, 0, N * sizeof(unsigned long long), h->stream));
+  HIPCHECK(hipMemsetAsync(h->d_neg, 0, N * sizeof(unsigned long long), h->stream));
+  HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->spec_valid = false;
+}
+
+void ensure_role(mvd_handle* h, int role) {
+  if (h->built[role]) return;
+  const int variant = role;  // ROLE_EFF == MVD_EFF etc.
+  for (auto& B : h->blocks) {
+    B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.spec_elems * 2 * sizeof(float));
+    for (int v = 0; v < h->nviews; ++v) {
+      const mvdh::Kern K = mvdh::compound_kernel(B.P, v, variant);
+      upload_spectrum(h, B, K, B.H[role] + (size_t)v * B.spec_elems * 2);
+    }
+  }
+  build_jobs(h);
+  h->built[role] = true;
+}
+
+LaunchArgs args(mvd_handle* h, hipStream_t s, int grid) {
+  LaunchArgs a;
+  a.jobs = h->d_jobs;
+  a.njobs = (int)h->jobs.size();
+  a.plans = h->d_plans;
+  a.tw = h->d_tw;
+  a.stream = s;
+  a.grid = grid;
+  return a;
+}
+
+// One iteration: every view once, in index order (section 7).
+void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant) {
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  const int conj_back = variant == MVD_RL ? 1 : 0;
+  const LaunchArgs ax = args(h, s, h->grid_x), ay = args(h, s, h->grid_y), az = args(h, s, h->grid_z);
+  for (int v = 0; v < h->nviews; ++v) {
+    Partial* parts = h->d_parts + (size_t)v * h->grid_x;
+    // b = psi (x) P_v, then q = phi_v / max(b, eps)
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
+    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, ROLE_P, 0));
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
+    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 1, v, parts, h->d_flags, 1));
+    // c = q (x) K_v, then the update of psi
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
+    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, role, conj_back));
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
+    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 2, v, parts, h->d_flags, 1));
+  }
+}
+
+hipGraphExec_t graph_for(mvd_handle* h, int variant) {
+  if (h->exec[variant]) return h->exec[variant];
+  hipGraph_t g = nullptr;
+  HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue_iteration(h, h->cap, variant);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(h->cap, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHECK(e);
+  h->exec[variant] = ex;
+  return ex;
+}
+
+void iterate_impl(mvd_handle* h, int n, int variant) {
+  if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
+  if (n < 0) bad("n must be >= 0");
+  if (n == 0) return;
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  ensure_role(h, role);
+  if (!h->spec_valid) {
+    HIPCHECK(mvd_launch_x(args(h, h->stream, h->grid_x), h->cfg_x, 0, 0, nullptr, h->d_flags, 1));
+    h->spec_valid = true;
+  }
+  if (h->use_graphs) {
+    hipGraphExec_t ex = graph_for(h, variant);
+    for (int i = 0; i < n; ++i) HIPCHECK(hipGraphLaunch(ex, h->stream));
+  } else {
+    for (int i = 0; i < n; ++i) enqueue_iteration(h, h->stream, variant);
+  }
+  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, h->stream));
+  h->iterations += n;
+}
+
+int read_flag(mvd_handle* h) {
+  int f = 0;
+  HIPCHECK(hipMemcpyAsync(&f, h->d_flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return f;
+}
+
+const Block& block_of(mvd_handle* h, int b) {
+  if (b < 0 || b >= (int)h->blocks.size()) bad("block index out of range");
+  return h->blocks[b];
+}
+
+template <class F>
+int guard(mvd_handle* h, F&& f) {
+  try {
+    f();
+    if (h) h->err.clear();
+    return MVD_OK;
+  } catch (const Error& e) {
+    (h ? h->err : g_err) = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    (h ? h->err : g_err) = "host allocation failed";
+    return MVD_ENOMEM;
+  } catch (const std::exception& e) {
+    (h ? h->err : g_err) = e.what();
+    return MVD_EINVAL;
+  } catch (...) {
+    (h ? h->err : g_err) = "unknown failure";
+    return MVD_EDEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks, const mvd_options* o) {
+  if (!out) {
+    g_err = "out is NULL";
+    return MVD_EINVAL;
+  }
+  *out = nullptr;
+  mvd_handle* h = new (std::nothrow) mvd_handle();
+  if (!h) {
+    g_err = "host allocation failed";
+    return MVD_ENOMEM;
+  }
+  const int rc = guard(nullptr, [&] { create_impl(h, n_blocks, blocks, o); });
+  if (rc != MVD_OK) {
+    h->release();
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MVD_OK;
+}
+
+int mvd_create(mvd_handle** out, const mvd_problem* p, const mvd_options* o) {
+  return mvd_create_batch(out, 1, p, o);
+}
+
+int mvd_iterate(mvd_handle* h, int n, int variant) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { iterate_impl(h, n, variant); });
+}
+
+int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  int nonfinite = 0;
+  int rc = guard(h, [&] {
+    const Block& B = block_of(h, block);
+    if (!dst) bad("dst is NULL");
+    if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
+    HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
+                            dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+    nonfinite = read_flag(h);
+  });
+  if (rc == MVD_OK && nonfinite) {
+    h->err = "the estimate became non-finite";
+    return MVD_ENONFINITE;
+  }
+  return rc;
+}
+
+int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    Block& B = const_cast<Block&>(block_of(h, block));
+    if (!src) bad("src is NULL");
+    if (src_kind == MVD_MEM_HOST) {
+      for (int64_t i = 0; i < B.V; ++i)
+        if (!(src[i] >= 0.f) || !std::isfinite(src[i])) bad("estimate has a negative or non-finite value");
+      HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    } else if (src_kind == MVD_MEM_DEVICE) {
+      double s;
+      unsigned long long nb;
+      device_check(h, src, B.V, 0.f, INFINITY, &s, &nb);
+      if (nb) bad("estimate has a negative or non-finite value");
+      HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      bad("src_kind must be host or device");
+    }
+    HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    h->spec_valid = false;
+    h->iterations = 0;
+  });
+}
+
+int mvd_stats(mvd_handle* h, mvd_stats_t* s) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (!s) bad("stats is NULL");
+    std::memset(s, 0, sizeof(*s));
+    const int N = h->nviews;
+    std::vector<double> f(N);
+    std::vector<unsigned long long> a(N), b(N);
+    HIPCHECK(hipMemcpyAsync(f.data(), h->d_flux, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipMemcpyAsync(a.data(), h->d_ratio, N * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipMemcpyAsync(b.data(), h->d_neg, N * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+    s->nonfinite = read_flag(h);
+    s->iterations = h->iterations;
+    s->n_views = N;
+    s->n_blocks = (int)h->blocks.size();
+    s->scale = h->blocks[0].s;
+    for (int v = 0; v < N; ++v) {
+      s->flux[v] = f[v];
+      s->ratio_clamps += (int64_t)a[v];
+      s->neg_clamps += (int64_t)b[v];
+    }
+  });
+}
+
+int mvd_synchronize(mvd_handle* h) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  int nonfinite = 0;
+  int rc = guard(h, [&] { nonfinite = read_flag(h); });
+  if (rc == MVD_OK && nonfinite) {
+    h->err = "the estimate became non-finite";
+    return MVD_ENONFINITE;
+  }
+  return rc;
+}
+
+int mvd_destroy(mvd_handle* h) {
+  if (!h) return MVD_OK;
+  h->release();
+  delete h;
+  return MVD_OK;
+}
+
+const char* mvd_last_error(const mvd_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_dims, int v, int variant,
+                        double* out, int* out_dims) {
+  return guard(nullptr, [&] {
+    if (n_views < 1 || n_views > MVD_MAX_VIEWS) bad("n_views must be in [1, 64]");
+    if (!psfs || !psf_dims || !out) bad("psfs, psf_dims and out are required");
+    if (v < 0 || v >= n_views) bad("v out of range");
+    if (variant < MVD_RL || variant > MVD_OPT2) bad("unknown variant");
+    std::vector<mvdh::Kern> P;
+    for (int i = 0; i < n_views; ++i) {
+      if (!psfs[i]) bad("PSF pointer is NULL");
+      const int* k = psf_dims + 3 * i;
+      try {
+        P.push_back(mvdh::prepare_psf(psfs[i], k[0], k[1], k[2]));
+      } catch (const std::invalid_argument& e) {
+        bad(e.what());
+      }
+    }
+    const mvdh::Kern K = mvdh::compound_kernel(P, v, variant);
+    std::memcpy(out, K.a.data(), K.a.size() * sizeof(double));
+    if (out_dims) {
+      out_dims[0] = K.kx;
+      out_dims[1] = K.ky;
+      out_dims[2] = K.kz;
+    }
+  });
+}
+
+int mvd_kernel_spectrum(const double* kernel, const int* kdims, const int* dims, float* main_out,
+                        float* nyq_out) {
+  return guard(nullptr, [&] {
+    if (!kernel || !kdims || !dims || !main_out || !nyq_out) bad("NULL argument");
+    if (dims[0] < 4 || dims[0] % 2 || dims[1] < 2 || dims[2] < 2) bad("bad volume dims");
+    mvdh::Kern K;
+    K.kx = kdims[0];
+    K.ky = kdims[1];
+    K.kz = kdims[2];
+    if (K.kx < 1 || K.ky < 1 || K.kz < 1 || !(K.kx & 1) || !(K.ky & 1) || !(K.kz & 1))
+      bad("kernel extents must be odd and >= 1");
+    if (K.kx > dims[0] || K.ky > dims[1] || K.kz > dims[2]) bad("kernel larger than the volume");
+    K.a.assign(kernel, kernel + (size_t)K.kx * K.ky * K.kz);
+    mvdh::spectrum_host(K, dims[0], dims[1], dims[2], main_out, nyq_out);
+  });
+}
+
+const char* mvd_version(void) { return "mvd 0.1 (gfx950)"; }
+
+}  // extern "C"

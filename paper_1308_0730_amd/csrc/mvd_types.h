@@ -1,0 +1,64 @@
+// Descriptors shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#define MVD_MAX_STAGES 12
+
+// Mixed-radix plan of one 1-D complex FFT length (radices 2, 3, 4, 5, 8).
+// tw is the offset of the length-L twiddle table exp(-2 pi i m / L) in the pool.
+struct FftPlan {
+  int L;
+  int nst;
+  int tw;
+  int radix[MVD_MAX_STAGES];
+};
+
+// Spectrum roles: which kernel spectrum a convolution pass multiplies by.
+enum { ROLE_P = 0, ROLE_EFF = 1, ROLE_OPT1 = 2, ROLE_OPT2 = 3, N_ROLES = 4 };
+
+// One volume (a block of the batched form) as the kernels see it.
+// Volumes are [z][y][x] float32; the half spectrum is kept as a main part
+// [z][y][kx < M] (M = nx/2 complex per row) followed by the kx = M
+// (Nyquist) plane [z][y], complex float32 interleaved.
+struct JobDesc {
+  int nx, ny, nz, M;
+  int nviews;
+  int plan_x, plan_y, plan_z;  // plans of lengths M, ny, nz
+  int pp;                      // offset of exp(-2 pi i k / nx), k < M, in the twiddle pool
+  int pad0;
+  int64_t V;
+  int64_t spec_main;           // M * ny * nz
+  int64_t spec_elems;          // spec_main + ny * nz
+  float* psi;
+  float* spec;                 // complex interleaved, spec_elems entries
+  const float* phi;            // [nviews][V]
+  const float* w;              // [nviews][V] or nullptr
+  const float* H[N_ROLES];     // [nviews][spec_elems] complex, scaled by 1/V; nullptr if not built
+  float eps, lamp;
+  int pad1, pad2;
+};
+
+// Per-workgroup partial results of the x passes (one entry per x tile).
+struct Partial {
+  double flux;
+  unsigned int ratio_clamps;
+  unsigned int neg_clamps;
+};
+
+enum PassKind { PASS_X = 0, PASS_Y = 1, PASS_Z = 2 };
+
+#if defined(__HIPCC__)
+#define MVD_HD __host__ __device__
+#else
+#define MVD_HD
+#endif
+
+MVD_HD inline int mvd_cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Number of tiles of a job for a pass.  x: rows of RW; y and z: TX adjacent
+// lines of the main part plus TX lines of the Nyquist plane.
+MVD_HD inline int mvd_tiles(const JobDesc& j, int kind, int param) {
+  if (kind == PASS_X) return mvd_cdiv(j.ny * j.nz, param);
+  if (kind == PASS_Y) return mvd_cdiv(j.M, param) * j.nz + mvd_cdiv(j.nz, param);
+  return mvd_cdiv(j.M, param) * j.ny + mvd_cdiv(j.ny, param);
+}

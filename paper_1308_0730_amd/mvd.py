@@ -1,0 +1,283 @@
+"""Python binding of libmvd (ctypes over include/mvd.h).
+
+Argument marshalling only: every step of the deconvolution runs in the HIP
+library.  PyTorch provides device memory (the library allocates through
+torch's caching allocator) and the stream the work is ordered on.  Importing
+this module raises if the built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library shares
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmvd.so")
+
+MVD_OK, MVD_EINVAL, MVD_ENOMEM, MVD_EDEVICE, MVD_ENONFINITE, MVD_ESTATE = 0, -1, -2, -3, -4, -5
+RL, EFF, OPT1, OPT2 = 0, 1, 2, 3
+MEM_HOST, MEM_DEVICE = 0, 1
+MAX_VIEWS = 64
+VARIANTS = {"rl": RL, "eff": EFF, "opt1": OPT1, "opt2": OPT2}
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_views", C.c_int), ("dims", C.c_int * 3), ("views", C.POINTER(C.c_void_p)),
+                ("psfs", C.POINTER(C.c_void_p)), ("psf_dims", C.POINTER(C.c_int)),
+                ("weights", C.POINTER(C.c_void_p)), ("mem_kind", C.c_int)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Options(C.Structure):
+    _fields_ = [("lam", C.c_double), ("eps_scale", C.c_double), ("stream", C.c_void_p),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("use_graphs", C.c_int), ("tile_config", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("n_views", C.c_int), ("n_blocks", C.c_int),
+                ("scale", C.c_double), ("flux", C.c_double * MAX_VIEWS), ("ratio_clamps", C.c_int64),
+                ("neg_clamps", C.c_int64), ("nonfinite", C.c_int)]
+
+
+class MVDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mvd error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmvd.so (built in-tree by paper_1308_0730_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python paper_1308_0730_amd/build.py`")
+    L = C.CDLL(LIB_PATH)
+    H = C.c_void_p
+    L.mvd_create.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options)]
+    L.mvd_create_batch.argtypes = [C.POINTER(H), C.c_int, C.POINTER(Problem), C.POINTER(Options)]
+    L.mvd_iterate.argtypes = [H, C.c_int, C.c_int]
+    L.mvd_get_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
+    L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
+    L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
+    L.mvd_synchronize.argtypes = [H]
+    L.mvd_destroy.argtypes = [H]
+    L.mvd_last_error.argtypes = [H]
+    L.mvd_last_error.restype = C.c_char_p
+    L.mvd_compound_kernel.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int, C.c_int,
+                                      C.c_void_p, C.POINTER(C.c_int)]
+    L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
+    L.mvd_version.restype = C.c_char_p
+    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_get_estimate", "mvd_set_estimate",
+                 "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, h=None):
+    if rc != MVD_OK:
+        raise MVDError(rc, lib().mvd_last_error(h).decode())
+
+
+def _variant(v):
+    return VARIANTS[v.lower()] if isinstance(v, str) else int(v)
+
+
+def _ptr(x):
+    return x.data_ptr() if isinstance(x, torch.Tensor) else x.ctypes.data
+
+
+class _Marshalled:
+    """Keeps the arrays of one problem alive while the library copies them."""
+
+    def __init__(self, views, psfs, weights, device, on_device):
+        def conv(a):
+            if on_device:
+                t = a if isinstance(a, torch.Tensor) else torch.from_numpy(
+                    np.ascontiguousarray(np.asarray(a, np.float32)))
+                return t.detach().to(device=device, dtype=torch.float32).contiguous()
+            if isinstance(a, torch.Tensor):
+                a = a.detach().cpu().numpy()
+            return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+        self.views = [conv(v) for v in views]
+        self.psfs = [conv(p) for p in psfs]
+        self.weights = None if weights is None else [conv(w) for w in weights]
+        n = len(self.views)
+        if len(self.psfs) != n or (self.weights is not None and len(self.weights) != n):
+            raise ValueError("views, psfs and weights need one entry per view")
+        shape = tuple(self.views[0].shape)
+        if len(shape) != 3:
+            raise ValueError("views are 3-D arrays (nz, ny, nx)")
+        self.dims = (shape[2], shape[1], shape[0])
+        for v in self.views:
+            if tuple(v.shape) != shape:
+                raise ValueError("every view has the volume's shape")
+        for p in self.psfs:
+            if len(p.shape) != 3:
+                raise ValueError("PSFs are 3-D arrays (kz, ky, kx)")
+        if self.weights is not None:
+            for w in self.weights:
+                if tuple(w.shape) != shape:
+                    raise ValueError("weights have the volume's shape")
+        self._v = (C.c_void_p * n)(*[_ptr(v) for v in self.views])
+        self._p = (C.c_void_p * n)(*[_ptr(p) for p in self.psfs])
+        self._k = (C.c_int * (3 * n))(*sum([[p.shape[2], p.shape[1], p.shape[0]] for p in self.psfs], []))
+        self._w = None if self.weights is None else (C.c_void_p * n)(*[_ptr(w) for w in self.weights])
+        self.problem = Problem(n, (C.c_int * 3)(*self.dims), C.cast(self._v, C.POINTER(C.c_void_p)),
+                               C.cast(self._p, C.POINTER(C.c_void_p)), C.cast(self._k, C.POINTER(C.c_int)),
+                               None if self._w is None else C.cast(self._w, C.POINTER(C.c_void_p)),
+                               MEM_DEVICE if on_device else MEM_HOST)
+
+
+class Deconvolver:
+    """Sequential multi-view deconvolution of one volume or a batch of blocks.
+
+    Deconvolver(views, psfs, weights=None, lam=0.0)              plain form
+    Deconvolver.batch([(views, psfs, weights), ...], lam=0.0)    batched form
+
+    Volumes are (nz, ny, nx) float32; PSFs (kz, ky, kx).  Inputs may be numpy
+    arrays (copied from host memory) or CUDA tensors (device memory).
+    """
+
+    def __init__(self, views=None, psfs=None, weights=None, lam=0.0, eps_scale=0.0, use_graphs=True,
+                 tile_config=0, device=None, _blocks=None):
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self._bufs = {}
+        dev = self.device
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+            except RuntimeError:
+                return None
+            self._bufs[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, ctx):
+            self._bufs.pop(ptr, None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.stream = torch.cuda.current_stream(dev)
+        opts = Options(float(lam), float(eps_scale), C.c_void_p(self.stream.cuda_stream), self._alloc_cb,
+                       self._free_cb, None, 1 if use_graphs else 0, int(tile_config))
+        blocks = _blocks if _blocks is not None else [(views, psfs, weights)]
+        on_device = any(isinstance(v, torch.Tensor) and v.is_cuda for b in blocks for v in b[0])
+        with torch.cuda.device(dev):
+            ms = [_Marshalled(v, p, w, dev, on_device) for (v, p, w) in blocks]
+            arr = (Problem * len(ms))(*[m.problem for m in ms])
+            h = C.c_void_p()
+            rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, C.byref(opts))
+        if rc != MVD_OK:
+            self._h = None
+            raise MVDError(rc, lib().mvd_last_error(None).decode())
+        self._h = h
+        self.dims = [m.dims for m in ms]
+        self.n_views = len(ms[0].views)
+        self.n_blocks = len(ms)
+
+    @classmethod
+    def batch(cls, blocks, **kw):
+        return cls(_blocks=[(b[0], b[1], b[2] if len(b) > 2 else None) for b in blocks], **kw)
+
+    def iterate(self, n, variant="eff"):
+        _check(lib().mvd_iterate(self._h, int(n), _variant(variant)), self._h)
+        return self
+
+    def estimate(self, block=0, out=None):
+        """The current estimate as a CUDA tensor (nz, ny, nx)."""
+        nx, ny, nz = self.dims[block]
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        rc = lib().mvd_get_estimate(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE, block)
+        _check(rc, self._h)
+        return out
+
+    def set_estimate(self, psi, block=0):
+        if isinstance(psi, torch.Tensor) and psi.is_cuda:
+            t = psi.detach().to(torch.float32).contiguous()
+            rc = lib().mvd_set_estimate(self._h, C.c_void_p(t.data_ptr()), MEM_DEVICE, block)
+        else:
+            a = np.ascontiguousarray(np.asarray(psi.cpu() if isinstance(psi, torch.Tensor) else psi, np.float32))
+            rc = lib().mvd_set_estimate(self._h, C.c_void_p(a.ctypes.data), MEM_HOST, block)
+        _check(rc, self._h)
+        return self
+
+    def stats(self):
+        s = Stats()
+        _check(lib().mvd_stats(self._h, C.byref(s)), self._h)
+        return dict(iterations=s.iterations, n_views=s.n_views, n_blocks=s.n_blocks, scale=s.scale,
+                    flux=list(s.flux[:s.n_views]), ratio_clamps=s.ratio_clamps, neg_clamps=s.neg_clamps,
+                    nonfinite=bool(s.nonfinite))
+
+    def synchronize(self):
+        _check(lib().mvd_synchronize(self._h), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mvd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def create_raw(blocks, options=None):
+    """mvd_create_batch on host-memory blocks [(views, psfs, weights), ...].
+
+    Returns (return code, handle or None, message); used to exercise the
+    argument checks, which run before any device call."""
+    ms = [_Marshalled(v, p, w, None, False) for (v, p, w) in blocks]
+    arr = (Problem * len(ms))(*[m.problem for m in ms])
+    h = C.c_void_p()
+    rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, None if options is None else C.byref(options))
+    msg = lib().mvd_last_error(None).decode()
+    return rc, (h if h.value else None), msg
+
+
+def compound_kernel(psfs, v, variant):
+    """K_v of the library's host code (FP64), shape (kz, ky, kx) odd."""
+    ps = [np.ascontiguousarray(np.asarray(p, np.float32)) for p in psfs]
+    n = len(ps)
+    ptrs = (C.c_void_p * n)(*[p.ctypes.data for p in ps])
+    dims = (C.c_int * (3 * n))(*sum([[p.shape[2], p.shape[1], p.shape[0]] for p in ps], []))
+    k = ps[v].shape
+    out = np.zeros((k[0] | 1, k[1] | 1, k[2] | 1), np.float64)
+    od = (C.c_int * 3)()
+    rc = lib().mvd_compound_kernel(n, C.cast(ptrs, C.POINTER(C.c_void_p)), C.cast(dims, C.POINTER(C.c_int)), v,
+                                   _variant(variant), out.ctypes.data, od)
+    _check(rc)
+    return out
+
+
+def kernel_spectrum(K, dims):
+    """(main, nyquist) spectrum of a centred odd kernel on a volume of dims (nx, ny, nz)."""
+    K = np.ascontiguousarray(np.asarray(K, np.float64))
+    nx, ny, nz = dims
+    main = np.zeros((nz, ny, nx // 2), np.complex64)
+    nyq = np.zeros((nz, ny), np.complex64)
+    kd = (C.c_int * 3)(K.shape[2], K.shape[1], K.shape[0])
+    dd = (C.c_int * 3)(nx, ny, nz)
+    _check(lib().mvd_kernel_spectrum(K.ctypes.data, kd, dd, main.ctypes.data, nyq.ctypes.data))
+    return main, nyq
