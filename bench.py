@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the sequential multi-view deconvolution on one MI355X.
+
+A step is one whole deconvolution run of the workload (every iteration, every
+view-update) on inputs already resident in HBM.  Default workload: the
+embryo-scale volume, 512x512x256 float32, six views at 60-degree steps,
+31x31x41 PSFs, per-view overlap weights, lambda = 0.0006, Optimization I,
+10 iterations (60 view-updates).
+
+Prints one JSON line: voxel-view updates/s over the timed steps, the
+roofline position of the dominant pass (per-launch HIP-event durations,
+algorithmic bytes), and the FP64 CPU oracle timed on a bounded sample on this
+host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+PASS_NAMES = ("y_forward", "y_inverse", "z_product", "x_ratio", "x_update")
+KERNEL_SOURCES = ("paper_1308_0730_amd/csrc/mvd_kernels.hip", "paper_1308_0730_amd/csrc/fft_engine.h")
+
+
+def workload(cfg):
+    from paper_1308_0730_amd import synth
+    if cfg == 1:
+        s = synth.config1()
+        return [s], dict(workload="tiny 64^3, 2 views, 17^3 PSFs, efficient update, 5 iterations",
+                         variant="eff", iterations=5, lam=0.0)
+    if cfg == 2:
+        s = synth.config2()
+        return [s], dict(workload="128^3, 4 views, 25^3 PSFs, efficient update, 20 iterations",
+                         variant="eff", iterations=20, lam=0.0)
+    if cfg == 3:
+        s = synth.config3()
+        return [s], dict(workload="embryo 512x512x256, 6 views at 60 deg, 31x31x41 PSFs, overlap weights, "
+                                  "lambda 0.0006, Optimization I, 10 iterations",
+                         variant="opt1", iterations=10, lam=0.0006)
+    if cfg == 4:
+        blocks = synth.config4()
+        return blocks, dict(workload="batched: 48 blocks (x,y in [96,256], z in [96,160]), 4 views, 17^3 PSFs, "
+                                     "efficient update, 10 iterations",
+                            variant="eff", iterations=10, lam=0.0)
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def pass_bytes(blocks, weighted):
+    """Algorithmic HBM bytes of one launch of each pass kind (all blocks)."""
+    out = dict.fromkeys(PASS_NAMES, 0.0)
+    for b in blocks:
+        nx, ny, nz = b.dims
+        V = nx * ny * nz
+        S = ((nx // 2) * ny * nz + ny * nz) * 8.0  # half spectrum, complex float32
+        out["y_forward"] += 2 * S
+        out["y_inverse"] += 2 * S
+        out["z_product"] += 3 * S
+        out["x_ratio"] += 2 * S + 4 * V
+        out["x_update"] += 2 * S + (12 if weighted else 8) * V
+    return out
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    if not m or m.group(1) != source_hash():
+        return None
+    m = re.search(rf"^{kernel}:\s*([0-9.eE+]+)\s*bytes_per_launch", txt, re.M)
+    return float(m.group(1)) if m else None
+
+
+def cpu_baseline(blocks, meta, budget_s=25.0):
+    """The FP64 oracle on this host: view-updates of the same workload until
+    about budget_s of work, scaled to voxel-view updates per second."""
+    from oracle import mvd_oracle as O
+    s = blocks[0]
+    pb = O.Problem(s.views, s.psfs, s.weights, meta["lam"])
+    variant = {"rl": O.RL, "eff": O.EFF, "opt1": O.OPT1, "opt2": O.OPT2}[meta["variant"]]
+    K = pb.kernels(variant)
+    psi = pb.psi0()
+    V = int(np.prod(s.dims))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        v = n % pb.n
+        w = None if pb.weights is None else pb.weights[v]
+        psi = O.view_update(psi, pb.views[v], pb.P[v], K[v], w, pb.lam_p, pb.eps)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= pb.n * meta["iterations"]:
+            break
+    return {"value": V * n / el / 1e9, "unit": "Gvox/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{n} view-update(s) of block 0 of the same workload in FP64 (scipy.fft, all host cores), "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--profile-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU form",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1308_0730_amd import mvd
+
+    t0 = time.time()
+    blocks, meta = workload(args.config)
+    print(f"[bench] generated workload in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    weighted = blocks[0].weights is not None
+    t0 = time.time()
+    if len(blocks) == 1:
+        d = mvd.Deconvolver(blocks[0].views, blocks[0].psfs, blocks[0].weights, lam=meta["lam"])
+    else:
+        d = mvd.Deconvolver.batch([(b.views, b.psfs, b.weights) for b in blocks], lam=meta["lam"])
+    d.iterate(1, meta["variant"])  # builds the compound spectra and the graph
+    d.synchronize()
+    print(f"[bench] created handle in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    its = meta["iterations"]
+    for _ in range(args.warmup):
+        d.iterate(its, meta["variant"])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        d.iterate(its, meta["variant"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = d.stats()
+    print(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    n_views = d.n_views
+    vox_updates = sum(int(np.prod(b.dims)) for b in blocks) * n_views * its
+    value = vox_updates / (ms / 1e3) / 1e9
+
+    prof = d.profile(args.profile_iters, meta["variant"])
+    d.synchronize()
+    by = pass_bytes(blocks, weighted)
+    total = {k: prof[k][0] * prof[k][1] for k in PASS_NAMES}
+    dom = max(total, key=total.get)
+    avg = prof[dom][0]
+    ach = by[dom] / (avg / 1e3) / 1e9
+    name = {1: "tiny64", 2: "cube128", 3: "embryo512", 4: "batched48"}[args.config]
+    tr = measured_traffic(name, dom)
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
+            "bytes_per_launch": by[dom], "avg_launch_ms": round(avg, 5)}
+    passes = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1],
+                  "GBps": round(by[k] / (prof[k][0] / 1e3) / 1e9, 1) if prof[k][0] > 0 else None}
+              for k in PASS_NAMES}
+    d.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del d
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(blocks, meta, args.cpu_budget)
+
+    dims = [list(b.dims) for b in blocks]
+    out = {
+        "metric": "voxel-view updates/s", "value": round(value, 3), "unit": "Gvox/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": meta["workload"], "dims": dims if len(dims) > 1 else dims[0],
+                   "views": n_views, "iterations": its,
+                   "variant": meta["variant"], "lambda": meta["lam"], "weights": weighted,
+                   "voxel_view_updates_per_step": vox_updates},
+        "roofline": roof, "passes": passes, "cpu_baseline": cpu,
+        "stats": {"flux_last_iteration": st["flux"], "ratio_clamps": st["ratio_clamps"],
+                  "neg_clamps": st["neg_clamps"], "nonfinite": st["nonfinite"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

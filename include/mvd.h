@@ -145,6 +145,19 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
  * compound-kernel spectra of a variant are built on its first use. */
 int mvd_iterate(mvd_handle* h, int n, int variant);
 
+/* Apply one view-update (view `view`, all blocks) -- the inspection hook of
+ * a single line of the sequential scheme of section 7.  Asynchronous; does
+ * not advance the iteration count. */
+int mvd_view_update(mvd_handle* h, int view, int variant);
+
+/* Profiling hook: run n >= 1 iterations with every pass launched directly
+ * and bracketed by HIP events on the handle's stream; avg_ms[k] and calls[k]
+ * (k < MVD_PASS_KINDS) receive the mean duration and the number of launches
+ * of pass kind k: 0 y forward, 1 y inverse, 2 z transform with the spectral
+ * product, 3 x pass with the ratio, 4 x pass with the update.  Synchronises. */
+#define MVD_PASS_KINDS 5
+int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
+
 /* Copy the estimate of `block` (0 for the plain form) into dst (nx*ny*nz
  * floats, host or device memory).  Synchronises; returns MVD_ENONFINITE if
  * the estimate became non-finite (the copy is still made). */

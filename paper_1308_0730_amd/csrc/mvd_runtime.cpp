@@ -464,23 +464,72 @@ LaunchArgs args(mvd_handle* h, hipStream_t s, int grid) {
   return a;
 }
 
-// One iteration: every view once, in index order (section 7).
-void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant) {
+// Per-launch event timing of the passes (profiling hook): kinds are
+// 0 y forward, 1 y inverse, 2 z product, 3 x ratio, 4 x update.
+struct PassTimer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  hipStream_t s = nullptr;
+  void mark(int k) {
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    ev.push_back(a);
+    ev.push_back(b);
+    kind.push_back(k);
+    HIPCHECK(hipEventRecord(a, s));
+  }
+  void done() { HIPCHECK(hipEventRecord(ev.back(), s)); }
+  ~PassTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// One view-update of view v: two convolutions and the pointwise steps.
+void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t = nullptr) {
   const int role = variant == MVD_RL ? ROLE_P : variant;
   const int conj_back = variant == MVD_RL ? 1 : 0;
   const LaunchArgs ax = args(h, s, h->grid_x), ay = args(h, s, h->grid_y), az = args(h, s, h->grid_z);
-  for (int v = 0; v < h->nviews; ++v) {
-    Partial* parts = h->d_parts + (size_t)v * h->grid_x;
-    // b = psi (x) P_v, then q = phi_v / max(b, eps)
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
-    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, ROLE_P, 0));
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
-    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 1, v, parts, h->d_flags, 1));
-    // c = q (x) K_v, then the update of psi
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
-    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, role, conj_back));
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
-    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 2, v, parts, h->d_flags, 1));
+  Partial* parts = h->d_parts + (size_t)v * h->grid_x;
+  auto run = [&](int kind, hipError_t (*fn)(mvd_handle*, const LaunchArgs&, int, int, int, Partial*),
+                 const LaunchArgs& a, int p0, int p1) {
+    if (t) t->mark(kind);
+    HIPCHECK(fn(h, a, v, p0, p1, parts));
+    if (t) t->done();
+  };
+  auto yp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int inv, int, Partial*) {
+    return mvd_launch_y(a, hh->cfg_y, inv, vv);
+  };
+  auto zp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int rl, int cj, Partial*) {
+    return mvd_launch_z(a, hh->cfg_z, vv, rl, cj);
+  };
+  auto xp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int mode, int, Partial* pp) {
+    return mvd_launch_x(a, hh->cfg_x, mode, vv, pp, hh->d_flags, 1);
+  };
+  // b = psi (x) P_v, then q = phi_v / max(b, eps)
+  run(0, yp, ay, 0, 0);
+  run(2, zp, az, ROLE_P, 0);
+  run(1, yp, ay, 1, 0);
+  run(3, xp, ax, 1, 0);
+  // c = q (x) K_v, then the update of psi
+  run(0, yp, ay, 0, 0);
+  run(2, zp, az, role, conj_back);
+  run(1, yp, ay, 1, 0);
+  run(4, xp, ax, 2, 0);
+}
+
+// One iteration: every view once, in index order (section 7).
+void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t = nullptr) {
+  for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, t);
+}
+
+void prepare_run(mvd_handle* h, int variant) {
+  if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  ensure_role(h, role);
+  if (!h->spec_valid) {
+    HIPCHECK(mvd_launch_x(args(h, h->stream, h->grid_x), h->cfg_x, 0, 0, nullptr, h->d_flags, 1));
+    h->spec_valid = true;
   }
 }
 
@@ -508,12 +557,7 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (n < 0) bad("n must be >= 0");
   if (n == 0) return;
-  const int role = variant == MVD_RL ? ROLE_P : variant;
-  ensure_role(h, role);
-  if (!h->spec_valid) {
-    HIPCHECK(mvd_launch_x(args(h, h->stream, h->grid_x), h->cfg_x, 0, 0, nullptr, h->d_flags, 1));
-    h->spec_valid = true;
-  }
+  prepare_run(h, variant);
   if (h->use_graphs) {
     hipGraphExec_t ex = graph_for(h, variant);
     for (int i = 0; i < n; ++i) HIPCHECK(hipGraphLaunch(ex, h->stream));
@@ -692,6 +736,47 @@ int mvd_destroy(mvd_handle* h) {
 }
 
 const char* mvd_last_error(const mvd_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int mvd_view_update(mvd_handle* h, int view, int variant) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (view < 0 || view >= h->nviews) bad("view index out of range");
+    prepare_run(h, variant);
+    enqueue_view(h, h->stream, variant, view);
+  });
+}
+
+int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (n < 1) bad("n must be >= 1");
+    if (!avg_ms || !calls) bad("avg_ms and calls are required");
+    prepare_run(h, variant);
+    PassTimer t;
+    t.s = h->stream;
+    for (int i = 0; i < n; ++i) enqueue_iteration(h, h->stream, variant, &t);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    double tot[MVD_PASS_KINDS] = {0};
+    int cnt[MVD_PASS_KINDS] = {0};
+    for (size_t i = 0; i < t.kind.size(); ++i) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+      tot[t.kind[i]] += ms;
+      cnt[t.kind[i]] += 1;
+    }
+    for (int k = 0; k < MVD_PASS_KINDS; ++k) {
+      avg_ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
+      calls[k] = cnt[k];
+    }
+    h->iterations += n;
+  });
+}
 
 int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_dims, int v, int variant,
                         double* out, int* out_dims) {

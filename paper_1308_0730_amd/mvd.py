@@ -68,6 +68,8 @@ def lib():
     L.mvd_get_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
+    L.mvd_view_update.argtypes = [H, C.c_int, C.c_int]
+    L.mvd_profile.argtypes = [H, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.mvd_synchronize.argtypes = [H]
     L.mvd_destroy.argtypes = [H]
     L.mvd_last_error.argtypes = [H]
@@ -77,7 +79,8 @@ def lib():
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_version.restype = C.c_char_p
     for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_get_estimate", "mvd_set_estimate",
-                 "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum"):
+                 "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
+                 "mvd_view_update", "mvd_profile"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -195,6 +198,21 @@ class Deconvolver:
     def iterate(self, n, variant="eff"):
         _check(lib().mvd_iterate(self._h, int(n), _variant(variant)), self._h)
         return self
+
+    def view_update(self, view, variant="eff"):
+        """One view-update (one line of the sequential scheme)."""
+        _check(lib().mvd_view_update(self._h, int(view), _variant(variant)), self._h)
+        return self
+
+    PASS_NAMES = ("y_forward", "y_inverse", "z_product", "x_ratio", "x_update")
+
+    def profile(self, n, variant="eff"):
+        """Run n iterations with per-launch HIP-event timing; returns
+        {pass: (mean ms, launches)}."""
+        ms = (C.c_double * 5)()
+        calls = (C.c_int * 5)()
+        _check(lib().mvd_profile(self._h, int(n), _variant(variant), ms, calls), self._h)
+        return {k: (ms[i], calls[i]) for i, k in enumerate(self.PASS_NAMES)}
 
     def estimate(self, block=0, out=None):
         """The current estimate as a CUDA tensor (nz, ny, nx)."""

@@ -13,6 +13,8 @@ View angles rotate the detection axis (z at 0 deg) about y.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -110,16 +112,18 @@ def make_views(dims, centers, sig, amp, angles, sigma_xy, sigma_z, background):
     """Noise-free views: each blob seen through view v's PSF is a Gaussian with
     covariance sigma^2 I + Sigma_v and the same mass."""
     shape = (dims[2], dims[1], dims[0])
-    out = []
-    for th in angles:
+
+    def one(th):
         Cp = psf_cov(sigma_xy, sigma_z, th)
         covs, amps = [], []
         for s, a in zip(sig, amp):
             C = s * s * np.eye(3) + Cp
             covs.append(C)
             amps.append(a * s ** 3 / math.sqrt(np.linalg.det(C)))
-        out.append(render(shape, centers, amps, covs, background))
-    return out
+        return render(shape, centers, amps, covs, background)
+
+    with ThreadPoolExecutor(max(1, min(len(angles), os.cpu_count() or 1))) as ex:
+        return list(ex.map(one, angles))
 
 
 def make_truth(dims, centers, sig, amp, background):
@@ -159,8 +163,20 @@ def overlap_weights(dims, angles, band=32.0, ramp=16.0):
     return out
 
 
-def _noisy(rng, vol, scale=1.0):
-    return (rng.poisson(vol * scale).astype(np.float32))
+def _noisy(seq, vol, scale=1.0, chunks=16):
+    """Poisson counts of vol * scale; z-slabs draw from their own child seeds
+    (so the result does not depend on the thread count)."""
+    kids = seq.spawn(chunks)
+    edges = np.linspace(0, vol.shape[0], chunks + 1).astype(int)
+    out = np.empty(vol.shape, np.float32)
+
+    def slab(i):
+        a, b = edges[i], edges[i + 1]
+        out[a:b] = np.random.default_rng(kids[i]).poisson(vol[a:b] * scale)
+
+    with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
+        list(ex.map(slab, range(chunks)))
+    return out
 
 
 def make_problem(dims, n_blobs, angles, psf_extent, sigma_xy, sigma_z, seed,
@@ -172,17 +188,17 @@ def make_problem(dims, n_blobs, angles, psf_extent, sigma_xy, sigma_z, seed,
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(4)
     rng_blobs = np.random.default_rng(kids[0])
-    rng_noise = np.random.default_rng(kids[1])
+    noise_seqs = kids[1].spawn(len(angles))
     centers, sig, amp = blob_params(rng_blobs, n_blobs, dims, shell)
     truth = make_truth(dims, centers, sig, amp, background)
     clean = make_views(dims, centers, sig, amp, angles, sigma_xy, sigma_z, background)
     if noise == "none":
         views = [v.astype(np.float32) for v in clean]
     elif noise == "photons":
-        views = [_noisy(rng_noise, v) for v in clean]
+        views = [_noisy(q, v) for q, v in zip(noise_seqs, clean)]
     elif noise == "peak1000":
         sc = 1000.0 / max(float(v.max()) for v in clean)
-        views = [_noisy(rng_noise, v, sc) for v in clean]
+        views = [_noisy(q, v, sc) for q, v in zip(noise_seqs, clean)]
         truth = truth * sc
     else:
         raise ValueError(noise)

@@ -68,6 +68,7 @@ def test_one_iteration_from_oracle_estimate(mvd, variant, weighted, lam):
         d.set_estimate(psi_r)
         d.iterate(1, variant)
         got = d.estimate().cpu().numpy()
+    print(f"rel_l2={rel(got, ref):.3e}")
     assert rel(got, ref) <= ONE_STEP, rel(got, ref)
 
 
@@ -84,6 +85,7 @@ def test_one_iteration_odd_and_mixed_radix_sizes(mvd, dims):
         d.set_estimate(psi_r)
         d.iterate(1, O.EFF)
         got = d.estimate().cpu().numpy()
+    print(f"rel_l2={rel(got, ref):.3e}")
     assert rel(got, ref) <= ONE_STEP, rel(got, ref)
 
 
@@ -97,6 +99,7 @@ def test_trajectory_config1(mvd):
             psi = pb.iterate(psi, 1, O.EFF)
             d.iterate(1, O.EFF)
             e = rel(d.estimate().cpu().numpy(), psi)
+            print(f"iteration {it}: rel_l2={e:.3e}")
             assert e <= TRAJ, (it, e)
         st = d.stats()
     assert st["iterations"] == s.n_iter and not st["nonfinite"]
@@ -114,12 +117,13 @@ def test_trajectory_config2(mvd, variant):
             d.iterate(1, variant)
             if it % 5 == 4 or it == 0:
                 e = rel(d.estimate().cpu().numpy(), psi)
-                assert e <= TRAJ, (it, e)
+                print(f"iteration {it}: rel_l2={e:.3e}")
+            assert e <= TRAJ, (it, e)
 
 
 @pytest.mark.parametrize("variant", [O.RL, O.EFF, O.OPT1, O.OPT2])
 def test_fixed_point(mvd, variant):
-    views, psfs, w = problem((48, 40, 36), 3, 13, weighted=True)
+    views, psfs, w = problem((48, 40, 36), 3, 13, weights=True)
     rng = np.random.default_rng(3)
     truth = rng.uniform(1.0, 20.0, size=views[0].shape)
     clean = [O.circ_conv(truth, O.prepare_psf(p)).astype(np.float32) for p in psfs]
@@ -144,7 +148,7 @@ def test_flux_identity_rl(mvd):
 
 
 def test_graph_replay_equals_direct_launches(mvd):
-    views, psfs, w = problem((40, 36, 30), 3, 15, weighted=True)
+    views, psfs, w = problem((40, 36, 30), 3, 15, weights=True)
     outs = []
     for g in (True, False):
         with mvd.Deconvolver(views, psfs, w, lam=0.01, use_graphs=g) as d:
@@ -165,7 +169,7 @@ def test_single_view_delta_psf_returns_the_view(mvd):
 
 
 def test_device_inputs_equal_host_inputs(mvd):
-    views, psfs, w = problem((40, 36, 30), 2, 16, weighted=True)
+    views, psfs, w = problem((40, 36, 30), 2, 16, weights=True)
     with mvd.Deconvolver(views, psfs, w) as d:
         d.iterate(2, O.EFF)
         a = d.estimate().cpu().numpy()
