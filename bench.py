@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--profile-iters", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU form",
@@ -146,6 +148,15 @@ def main():
     d.iterate(1, meta["variant"])  # builds the compound spectra and the graph
     d.synchronize()
     print(f"[bench] created handle in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.time()
+    if args.tiles:
+        d.set_tiles(*[int(x) for x in args.tiles.split(",")])
+    elif not args.no_tune:
+        from paper_1308_0730_amd import tune
+        tune.autotune(d, meta["variant"], iters=1, cache_path=None, verbose=True)
+    tiles = d.tiles()
+    launch = {k: dict(mvd.tile_shape(i, c), candidate=c) for i, (k, c) in enumerate(zip(("x", "y", "z"), tiles))}
+    print(f"[bench] launch shapes {tiles} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
 
     its = meta["iterations"]
     for _ in range(args.warmup):
@@ -199,7 +210,7 @@ def main():
                    "views": n_views, "iterations": its,
                    "variant": meta["variant"], "lambda": meta["lam"], "weights": weighted,
                    "voxel_view_updates_per_step": vox_updates},
-        "roofline": roof, "passes": passes, "cpu_baseline": cpu,
+        "roofline": roof, "passes": passes, "launch": launch, "cpu_baseline": cpu,
         "stats": {"flux_last_iteration": st["flux"], "ratio_clamps": st["ratio_clamps"],
                   "neg_clamps": st["neg_clamps"], "nonfinite": st["nonfinite"]},
     }

@@ -158,6 +158,18 @@ int mvd_view_update(mvd_handle* h, int view, int variant);
 #define MVD_PASS_KINDS 5
 int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
 
+/* Launch shapes (the autotuner's knobs).  Pass kinds: 0 x (rows), 1 y,
+ * 2 z (columns).  Candidate c of a kind has a thread count, a tile size
+ * (rows or columns per workgroup) and the longest transform it accepts.
+ * mvd_tile_candidates lists, into out[0..cap), the candidates that hold
+ * max_len and returns how many exist.  mvd_set_tiles selects one candidate
+ * per kind for a handle (MVD_EINVAL if one is too small for its volumes);
+ * later iterations use them.  mvd_get_tiles reports the current choice. */
+int mvd_tile_candidates(int kind, int max_len, int* out, int cap);
+int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len);
+int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z);
+int mvd_get_tiles(const mvd_handle* h, int* cfg);
+
 /* Copy the estimate of `block` (0 for the plain form) into dst (nx*ny*nz
  * floats, host or device memory).  Synchronises; returns MVD_ENONFINITE if
  * the estimate became non-finite (the copy is still made). */

@@ -13,6 +13,10 @@
 // contiguous runs of NL complex values and LDS is laid out [pos][line].
 // Position-fast mapping (row passes): consecutive lanes take consecutive
 // butterflies of one row, LDS laid out [line][pos].
+//
+// Synchronisation is either the whole workgroup (tiles shared by all waves)
+// or one wavefront (a wave that owns its rows and its LDS region needs no
+// workgroup barrier: a wave's LDS operations complete in issue order).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -141,11 +145,12 @@ struct LdsRow {
   __device__ __forceinline__ void st(int line, int pos, float2 v) const { p[line * PITCH + pos] = v; }
 };
 
-// Global tile: element (line, pos) at base[line * ls + pos * ps]; lines >= nl
-// read as zero and are not written.
+// Global tile: element (line, pos) at base[line * ls + pos * ps] (32-bit
+// element offsets from the tile's base); lines >= nl read as zero and are
+// not written.
 struct GTile {
   float2* base;
-  int64_t ls, ps;
+  int ls, ps;
   int nl;
   static constexpr bool lds = false;
   __device__ __forceinline__ float2 ld(int line, int pos) const {
@@ -156,17 +161,45 @@ struct GTile {
   }
 };
 
+// ---- synchronisation ---------------------------------------------------------
+
+enum { SYNC_BLOCK = 0, SYNC_WAVE = 1 };
+
+template <int SY>
+__device__ __forceinline__ void gsync() {
+  if (SY == SYNC_BLOCK) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+__device__ __forceinline__ int udiv(int j, unsigned magic) { return (int)__umulhi((unsigned)j, magic); }
+
 // ---- one Stockham stage ------------------------------------------------------
 
-// MAXL bounds L; T threads; NL lines; LF selects the line-fast mapping.
-template <int R, bool INV, int MAXL, int T, int NL, bool LF, class S, class D>
-__device__ __forceinline__ void stage(int L, int Ns, const float2* __restrict__ tw, const S& src,
+struct StageInfo {
+  int L, Ns, tws;
+  unsigned ns_magic, nb_magic;
+};
+
+// MAXL bounds L; T threads (tid in [0, T)); NL lines; LF selects the
+// line-fast mapping; SY the synchronisation scope; tw is the length-L
+// twiddle table (in LDS).
+template <int R, bool INV, int MAXL, int T, int NL, bool LF, int SY, class S, class D>
+__device__ __forceinline__ void stage(const StageInfo& si, int tid_in, const float2* tw, const S& src,
                                       const D& dst) {
   constexpr int MAXB = (NL * (MAXL / R) + T - 1) / T;
-  const int tid = threadIdx.x;
-  const int nb = L / R;
+  // hide the thread index from loop-invariant code motion: otherwise the
+  // per-stage index arithmetic of every radix case is hoisted out of the
+  // stage loop and stays live in registers for the whole transform
+  int tid = tid_in;
+  asm volatile("" : "+v"(tid));
+  const int nb = si.L / R;
   const int total = nb * NL;
-  const int tws = L / (Ns * R);
+  const int Ns = si.Ns;
   float2 v[MAXB][R];
   int ln[MAXB], jb[MAXB];
 #pragma unroll
@@ -176,9 +209,12 @@ __device__ __forceinline__ void stage(int L, int Ns, const float2* __restrict__ 
     if (LF) {
       line = it % NL;
       j = it / NL;
+    } else if (nb == 1) {
+      line = it;
+      j = 0;
     } else {
-      j = it % nb;
-      line = it / nb;
+      line = udiv(it, si.nb_magic);
+      j = it - line * nb;
     }
     ln[i] = line;
     jb[i] = j;
@@ -189,17 +225,18 @@ __device__ __forceinline__ void stage(int L, int Ns, const float2* __restrict__ 
   }
   // in-place stages (LDS -> LDS, or a single global -> global stage) must
   // finish every read before the first write
-  if (S::lds == D::lds) __syncthreads();
+  if (S::lds == D::lds) gsync<SY>();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int it = tid + i * T;
     if (it < total) {
       const int j = jb[i];
-      const int k = j % Ns;
+      const int k = Ns == 1 ? 0 : j - udiv(j, si.ns_magic) * Ns;
       if (Ns > 1) {
+        const int step = k * si.tws;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[k * r * tws];
+          float2 w = tw[step * r];
           if (INV) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -210,43 +247,53 @@ __device__ __forceinline__ void stage(int L, int Ns, const float2* __restrict__ 
       for (int r = 0; r < R; ++r) dst.st(ln[i], base + r * Ns, v[i][r]);
     }
   }
-  if (D::lds) __syncthreads();
+  if (D::lds) gsync<SY>();
 }
 
-template <bool INV, int MAXL, int T, int NL, bool LF, class S, class D>
-__device__ __forceinline__ void stage_rt(int R, int L, int Ns, const float2* __restrict__ tw,
+template <bool INV, int MAXL, int T, int NL, bool LF, int SY, class S, class D>
+__device__ __forceinline__ void stage_rt(int R, const StageInfo& si, int tid, const float2* tw,
                                          const S& src, const D& dst) {
   switch (R) {
-    case 8: stage<8, INV, MAXL, T, NL, LF>(L, Ns, tw, src, dst); break;
-    case 4: stage<4, INV, MAXL, T, NL, LF>(L, Ns, tw, src, dst); break;
-    case 2: stage<2, INV, MAXL, T, NL, LF>(L, Ns, tw, src, dst); break;
-    case 3: stage<3, INV, MAXL, T, NL, LF>(L, Ns, tw, src, dst); break;
-    default: stage<5, INV, MAXL, T, NL, LF>(L, Ns, tw, src, dst); break;
+    case 8: stage<8, INV, MAXL, T, NL, LF, SY>(si, tid, tw, src, dst); break;
+    case 4: stage<4, INV, MAXL, T, NL, LF, SY>(si, tid, tw, src, dst); break;
+    case 2: stage<2, INV, MAXL, T, NL, LF, SY>(si, tid, tw, src, dst); break;
+    case 3: stage<3, INV, MAXL, T, NL, LF, SY>(si, tid, tw, src, dst); break;
+    default: stage<5, INV, MAXL, T, NL, LF, SY>(si, tid, tw, src, dst); break;
   }
 }
 
 // Whole transform of NL lines: first stage src -> mid, middle stages
 // mid -> mid, last stage mid -> dst (a single stage goes src -> dst).
-// `mid` must be an LDS accessor.
-template <bool INV, int MAXL, int T, int NL, bool LF, class S, class M, class D>
-__device__ __forceinline__ void fft_lines(const FftPlan& pl, const float2* __restrict__ twpool,
+// `mid` must be an LDS accessor; tw the plan's twiddle table in LDS.
+template <bool INV, int MAXL, int T, int NL, bool LF, int SY, class S, class M, class D>
+__device__ __forceinline__ void fft_lines(const FftPlan* __restrict__ pl, const float2* tw, int tid,
                                           const S& src, const M& mid, const D& dst) {
-  const float2* tw = twpool + pl.tw;
-  const int L = pl.L;
-  int Ns = 1;
-  for (int s = 0; s < pl.nst; ++s) {
-    const int R = pl.radix[s];
-    const bool first = s == 0, last = s == pl.nst - 1;
+  const int nst = pl->nst;
+  StageInfo si;
+  si.L = pl->L;
+  for (int s = 0; s < nst; ++s) {
+    const int R = pl->radix[s];
+    si.Ns = pl->ns[s];
+    si.tws = pl->tws[s];
+    si.ns_magic = pl->ns_magic[s];
+    si.nb_magic = pl->nb_magic[s];
+    const bool first = s == 0, last = s == nst - 1;
     if (first && last)
-      stage_rt<INV, MAXL, T, NL, LF>(R, L, Ns, tw, src, dst);
+      stage_rt<INV, MAXL, T, NL, LF, SY>(R, si, tid, tw, src, dst);
     else if (first)
-      stage_rt<INV, MAXL, T, NL, LF>(R, L, Ns, tw, src, mid);
+      stage_rt<INV, MAXL, T, NL, LF, SY>(R, si, tid, tw, src, mid);
     else if (last)
-      stage_rt<INV, MAXL, T, NL, LF>(R, L, Ns, tw, mid, dst);
+      stage_rt<INV, MAXL, T, NL, LF, SY>(R, si, tid, tw, mid, dst);
     else
-      stage_rt<INV, MAXL, T, NL, LF>(R, L, Ns, tw, mid, mid);
-    Ns *= R;
+      stage_rt<INV, MAXL, T, NL, LF, SY>(R, si, tid, tw, mid, mid);
   }
+}
+
+// Cooperative copy of n table entries into LDS (all T threads), followed by
+// a workgroup barrier.
+template <int T>
+__device__ __forceinline__ void load_table(float2* dst, const float2* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
 }
 
 }  // namespace mvdk

@@ -82,19 +82,27 @@ __device__ __forceinline__ float tikhonov(float u, float lamp) {
 // i x[2n+1]; the half spectrum follows from the M-point transform Z by
 //   X[k] = (Z[k] + conj Z[M-k])/2 - i e^{-2 pi i k/nx} (Z[k] - conj Z[M-k])/2
 // and the inverse rebuilds Z from X before an M-point inverse transform.
-template <int MODE, int T, int RW, int MAXM>
-__global__ void __launch_bounds__(T)
+// Each wave owns RPW whole rows and its own LDS region, so after the table
+// load the transforms synchronise per wave only.
+template <int MODE, int WPB, int RPW, int MAXM>
+__global__ void __launch_bounds__(64 * WPB)
     k_xpass(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
             const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
             int write_spec) {
+  constexpr int T = 64 * WPB;
+  constexpr int RW = WPB * RPW;
+  constexpr int EPT = (RPW * MAXM + 63) / 64;
+  constexpr int NPIT = (RPW * (MAXM / 2 + 1) + 63) / 64;
   __shared__ float2 lds[RW * MAXM];
-  __shared__ double rf[T / 64];
-  __shared__ unsigned ra[T / 64], rb[T / 64];
+  __shared__ float2 s_tw[MAXM];
+  __shared__ float2 s_pp[MAXM];
+  __shared__ double rf[WPB];
+  __shared__ unsigned ra[WPB], rb[WPB];
   int local;
   const int jid = find_job(jobs, njobs, PASS_X, RW, local);
   if (jid < 0) return;
   const JobDesc& J = jobs[jid];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (MODE != 0 && v >= J.nviews) {
     if (tid == 0 && parts) {
       if (MODE == 2) {
@@ -107,29 +115,30 @@ __global__ void __launch_bounds__(T)
     return;
   }
   const int M = J.M, nx = J.nx;
-  const int row0 = local * RW;
-  const int nrows = min(RW, J.ny * J.nz - row0);
+  const FftPlan* pl = plans + J.plan_x;
+  load_table<T>(s_tw, twp + pl->tw, M);
+  load_table<T>(s_pp, twp + J.pp, M);
+  const int wrow0 = local * RW + wave * RPW;
+  const int nrw = max(0, min(RPW, J.ny * J.nz - wrow0));
   float2* spec = reinterpret_cast<float2*>(J.spec);
   float2* nyq = spec + J.spec_main;
-  const float2* pp = twp + J.pp;
-  const FftPlan pl = plans[J.plan_x];
-  const LdsRow<MAXM> L{lds};
-  constexpr int EPT = (RW * MAXM + T - 1) / T;
-  constexpr int NPIT = (RW * (MAXM / 2 + 1) + T - 1) / T;
+  const LdsRow<MAXM> L{lds + wave * RPW * MAXM};
   const int npair = M / 2 + 1;
+  const unsigned mM = mvd_magic(M), mP = mvd_magic(npair);
   const int64_t vo = (int64_t)v * J.V;
   const float eps = J.eps, lamp = J.lamp;
   const float* wv = J.w ? J.w + vo : nullptr;
 
-  // prefetch the pointwise operands of this thread's elements
+  // prefetch the pointwise operands of this lane's elements
   float2 pa[EPT], pb[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int it = tid + i * T;
-    const int r = it / M, p = it - r * M;
+    const int it = lane + i * 64;
+    const int r = RPW == 1 ? 0 : udiv(it, mM);
+    const int p = it - r * M;
     pa[i] = pb[i] = make_float2(0.f, 0.f);
-    if (r < nrows) {
-      const int64_t g = (int64_t)(row0 + r) * nx + 2 * p;
+    if (r < nrw && p < M) {
+      const int64_t g = (int64_t)(wrow0 + r) * nx + 2 * p;
       if (MODE == 1) pa[i] = *reinterpret_cast<const float2*>(J.phi + vo + g);
       if (MODE != 1) pa[i] = *reinterpret_cast<const float2*>(J.psi + g);
       if (MODE == 2 && wv) pb[i] = *reinterpret_cast<const float2*>(wv + g);
@@ -142,30 +151,34 @@ __global__ void __launch_bounds__(T)
   if (MODE == 0) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int it = tid + i * T;
-      const int r = it / M, p = it - r * M;
-      if (r < nrows) L.st(r, p, pa[i]);
+      const int it = lane + i * 64;
+      const int r = RPW == 1 ? 0 : udiv(it, mM);
+      const int p = it - r * M;
+      if (r < nrw && p < M) L.st(r, p, pa[i]);
     }
-    __syncthreads();
+    __syncthreads();  // twiddle tables and this wave's rows
   } else {
-    // rebuild the M-point spectrum Z of this row from its half spectrum X
+    // rebuild the M-point spectrum Z of these rows from their half spectrum X
     float2 xa[NPIT], xb[NPIT];
 #pragma unroll
     for (int i = 0; i < NPIT; ++i) {
-      const int it = tid + i * T;
-      const int r = it / npair, k = it - r * npair;
-      if (r < nrows) {
-        const int64_t rbase = (int64_t)(row0 + r) * M;
+      const int it = lane + i * 64;
+      const int r = RPW == 1 ? 0 : udiv(it, mP);
+      const int k = it - r * npair;
+      if (r < nrw && k < npair) {
+        const int64_t rbase = (int64_t)(wrow0 + r) * M;
         xa[i] = spec[rbase + k];
-        xb[i] = (k == 0) ? nyq[row0 + r] : spec[rbase + M - k];
+        xb[i] = (k == 0) ? nyq[wrow0 + r] : spec[rbase + M - k];
       }
     }
+    __syncthreads();  // twiddle tables
 #pragma unroll
     for (int i = 0; i < NPIT; ++i) {
-      const int it = tid + i * T;
-      const int r = it / npair, k = it - r * npair;
-      if (r < nrows) {
-        const float2 a = xa[i], b = xb[i], t = pp[k];
+      const int it = lane + i * 64;
+      const int r = RPW == 1 ? 0 : udiv(it, mP);
+      const int k = it - r * npair;
+      if (r < nrw && k < npair) {
+        const float2 a = xa[i], b = xb[i], t = s_pp[k];
         // Z[k] = (a + conj b) + i conj(t) (a - conj b)
         const float2 s = make_float2(a.x + b.x, a.y - b.y);
         const float2 d = make_float2(a.x - b.x, a.y + b.y);
@@ -180,15 +193,16 @@ __global__ void __launch_bounds__(T)
         }
       }
     }
-    __syncthreads();
-    fft_lines<true, MAXM, T, RW, false>(pl, twp, L, L, L);
+    gsync<SYNC_WAVE>();
+    fft_lines<true, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
 
     // pointwise step on the real values held two per complex entry
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int it = tid + i * T;
-      const int r = it / M, p = it - r * M;
-      if (r < nrows) {
+      const int it = lane + i * 64;
+      const int r = RPW == 1 ? 0 : udiv(it, mM);
+      const int p = it - r * M;
+      if (r < nrw && p < M) {
         const float2 z = L.ld(r, p);
         float2 o;
         if (MODE == 1) {
@@ -204,32 +218,33 @@ __global__ void __launch_bounds__(T)
           } else {
             o = make_float2(tx, ty);
           }
-          *reinterpret_cast<float2*>(J.psi + (int64_t)(row0 + r) * nx + 2 * p) = o;
+          *reinterpret_cast<float2*>(J.psi + (int64_t)(wrow0 + r) * nx + 2 * p) = o;
           flux += (double)o.x + (double)o.y;
           bad |= !(isfinite(o.x) && isfinite(o.y));
         }
         L.st(r, p, o);
       }
     }
-    __syncthreads();
+    gsync<SYNC_WAVE>();
   }
 
   if (MODE == 0 || write_spec) {
-    fft_lines<false, MAXM, T, RW, false>(pl, twp, L, L, L);
-    // half spectrum of the row from the M-point transform
+    fft_lines<false, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
+    // half spectrum of the rows from the M-point transform
 #pragma unroll
     for (int i = 0; i < NPIT; ++i) {
-      const int it = tid + i * T;
-      const int r = it / npair, k = it - r * npair;
-      if (r < nrows) {
-        const int64_t rbase = (int64_t)(row0 + r) * M;
+      const int it = lane + i * 64;
+      const int r = RPW == 1 ? 0 : udiv(it, mP);
+      const int k = it - r * npair;
+      if (r < nrw && k < npair) {
+        const int64_t rbase = (int64_t)(wrow0 + r) * M;
         const float2 zk = L.ld(r, k);
         if (k == 0) {
           spec[rbase] = make_float2(zk.x + zk.y, 0.f);
-          nyq[row0 + r] = make_float2(zk.x - zk.y, 0.f);
+          nyq[wrow0 + r] = make_float2(zk.x - zk.y, 0.f);
         } else {
           const float2 zm = L.ld(r, M - k);
-          const float2 t = pp[k];
+          const float2 t = s_pp[k];
           const float2 s = make_float2(zk.x + zm.x, zk.y - zm.y);
           const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
           const float2 e = cmul(t, d);
@@ -269,6 +284,7 @@ __global__ void __launch_bounds__(T)
     k_ypass(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
             const float2* __restrict__ twp, int v) {
   __shared__ float2 lds[MAXL * TX];
+  __shared__ float2 s_tw[MAXL];
   int local;
   const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
   if (jid < 0) return;
@@ -291,8 +307,10 @@ __global__ void __launch_bounds__(T)
     g.ps = 1;
     g.nl = min(TX, nz - t2 * TX);
   }
-  const FftPlan pl = plans[J.plan_y];
-  fft_lines<INV, MAXL, T, TX, true>(pl, twp, g, LdsCol<TX>{lds}, g);
+  const FftPlan* pl = plans + J.plan_y;
+  // the table is read from the second stage on, after the first stage's barrier
+  load_table<T>(s_tw, twp + pl->tw, ny);
+  fft_lines<INV, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, threadIdx.x, g, LdsCol<TX>{lds}, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,6 +322,7 @@ __global__ void __launch_bounds__(T)
     k_zconv(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
             const float2* __restrict__ twp, int v, int role, int conjH) {
   __shared__ float2 lds[MAXL * TX];
+  __shared__ float2 s_tw[MAXL];
   int local;
   const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
   if (jid < 0) return;
@@ -311,12 +330,12 @@ __global__ void __launch_bounds__(T)
   if (v >= J.nviews) return;
   const int M = J.M, ny = J.ny, nz = J.nz;
   const int nxt = mvd_cdiv(M, TX);
-  int64_t off, ps;
-  int nl;
+  int64_t off;
+  int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
     off = (int64_t)y * M + xt * TX;
-    ps = (int64_t)ny * M;
+    ps = ny * M;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
@@ -335,9 +354,11 @@ __global__ void __launch_bounds__(T)
     const int line = e % TX, pos = e / TX;
     h[i] = (pos < nz && line < nl) ? H[line + pos * ps] : make_float2(0.f, 0.f);
   }
-  const FftPlan pl = plans[J.plan_z];
+  const FftPlan* pl = plans + J.plan_z;
+  load_table<T>(s_tw, twp + pl->tw, nz);
   const LdsCol<TX> S{lds};
-  fft_lines<false, MAXL, T, TX, true>(pl, twp, g, S, S);
+  if (pl->nst == 1) __syncthreads();
+  fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, g, S, S);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * T;
@@ -348,7 +369,7 @@ __global__ void __launch_bounds__(T)
     }
   }
   __syncthreads();
-  fft_lines<true, MAXL, T, TX, true>(pl, twp, S, S, g);
+  fft_lines<true, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, S, S, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,14 +490,14 @@ __global__ void __launch_bounds__(256)
   X(8, 256, 8, 256)
 
 #define MVD_ROW_CFGS(X) \
-  X(0, 256, 32, 32)     \
-  X(1, 256, 16, 64)     \
-  X(2, 256, 8, 128)     \
-  X(3, 256, 4, 256)     \
-  X(4, 256, 2, 512)     \
-  X(5, 256, 8, 256)     \
-  X(6, 256, 4, 512)     \
-  X(7, 128, 4, 128)
+  X(0, 4, 4, 32)        \
+  X(1, 4, 2, 64)        \
+  X(2, 4, 2, 128)       \
+  X(3, 4, 1, 256)       \
+  X(4, 4, 1, 512)       \
+  X(5, 2, 1, 256)       \
+  X(6, 8, 1, 256)       \
+  X(7, 4, 1, 128)
 
 static const int kColCfg[][3] = {
 #define X(i, t, tx, l) {t, tx, l},
@@ -484,7 +505,7 @@ static const int kColCfg[][3] = {
 #undef X
 };
 static const int kRowCfg[][3] = {
-#define X(i, t, rw, m) {t, rw, m},
+#define X(i, wpb, rpw, m) {64 * wpb, wpb * rpw, m},
     MVD_ROW_CFGS(X)
 #undef X
 };
@@ -500,17 +521,17 @@ int mvd_cfg_maxlen(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][2] 
 hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
                         int write_spec) {
   switch (cfg) {
-#define X(i, t, rw, m)                                                                              \
-  case i:                                                                                           \
-    if (mode == 0)                                                                                  \
-      k_xpass<0, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
-                                                       flags, write_spec);                         \
-    else if (mode == 1)                                                                             \
-      k_xpass<1, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
-                                                       flags, write_spec);                         \
-    else                                                                                            \
-      k_xpass<2, t, rw, m><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts,   \
-                                                       flags, write_spec);                         \
+#define X(i, wpb, rpw, m)                                                                        \
+  case i:                                                                                        \
+    if (mode == 0)                                                                               \
+      k_xpass<0, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
+                                                                 v, parts, flags, write_spec);   \
+    else if (mode == 1)                                                                          \
+      k_xpass<1, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
+                                                                 v, parts, flags, write_spec);   \
+    else                                                                                         \
+      k_xpass<2, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
+                                                                 v, parts, flags, write_spec);   \
     break;
     MVD_ROW_CFGS(X)
 #undef X

@@ -81,6 +81,8 @@ struct mvd_handle {
   std::map<int, int> pp_of_nx;
   int cfg_x = 0, cfg_y = 0, cfg_z = 0;
   int grid_x = 0, grid_y = 0, grid_z = 0;
+  int max_len[3] = {0, 0, 0};
+  size_t parts_cap = 0;
   bool spec_valid = false;
   bool built[N_ROLES] = {true, false, false, false};
   int64_t iterations = 0;
@@ -209,7 +211,16 @@ int plan_for(mvd_handle* h, int L, std::vector<FftPlan>& plans, std::vector<floa
   pl.L = L;
   const auto r = mvdh::factorize(L);
   pl.nst = (int)r.size();
-  for (int i = 0; i < pl.nst; ++i) pl.radix[i] = r[i];
+  if (pl.nst > MVD_MAX_STAGES) bad("too many FFT stages");
+  int ns = 1;
+  for (int i = 0; i < pl.nst; ++i) {
+    pl.radix[i] = r[i];
+    pl.ns[i] = ns;
+    pl.tws[i] = L / (ns * r[i]);
+    pl.ns_magic[i] = mvd_magic((unsigned)ns);
+    pl.nb_magic[i] = mvd_magic((unsigned)(L / r[i]));
+    ns *= r[i];
+  }
   pl.tw = (int)tw.size();
   for (const auto& c : mvdh::twiddles(L)) tw.push_back(make_float2((float)c.real(), (float)c.imag()));
   plans.push_back(pl);
@@ -299,6 +310,36 @@ void build_jobs(mvd_handle* h) {
   HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                           h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+// Select the launch shapes of the three pass kinds; recomputes the grids,
+// grows the partials buffer and drops the cached graphs.
+void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
+  const int c[3] = {cx, cy, cz};
+  for (int k = 0; k < 3; ++k) {
+    if (c[k] < 0 || c[k] >= mvd_num_cfgs(k)) bad("tile configuration index out of range");
+    if (mvd_cfg_maxlen(k, c[k]) < h->max_len[k]) bad("tile configuration too small for this volume");
+  }
+  const int gx = total_tiles(h, PASS_X, mvd_cfg_param(PASS_X, cx));
+  const int gy = total_tiles(h, PASS_Y, mvd_cfg_param(PASS_Y, cy));
+  const int gz = total_tiles(h, PASS_Z, mvd_cfg_param(PASS_Z, cz));
+  if ((size_t)h->nviews * gx > h->parts_cap) {
+    h->d_parts = (Partial*)h->dalloc((size_t)h->nviews * gx * sizeof(Partial));
+    h->parts_cap = (size_t)h->nviews * gx;
+    HIPCHECK(hipMemsetAsync(h->d_parts, 0, h->parts_cap * sizeof(Partial), h->stream));
+  }
+  for (auto& g : h->exec)
+    if (g) {
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  h->cfg_x = cx;
+  h->cfg_y = cy;
+  h->cfg_z = cz;
+  h->grid_x = gx;
+  h->grid_y = gy;
+  h->grid_z = gz;
 }
 
 void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options* o) {
@@ -419,18 +460,15 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     maxZ = std::max(maxZ, B.nz);
   }
   build_jobs(h);
-  h->cfg_x = pick_cfg(PASS_X, maxM, h->force_cfg);
-  h->cfg_y = pick_cfg(PASS_Y, maxY, h->force_cfg);
-  h->cfg_z = pick_cfg(PASS_Z, maxZ, h->force_cfg);
-  h->grid_x = total_tiles(h, PASS_X, mvd_cfg_param(PASS_X, h->cfg_x));
-  h->grid_y = total_tiles(h, PASS_Y, mvd_cfg_param(PASS_Y, h->cfg_y));
-  h->grid_z = total_tiles(h, PASS_Z, mvd_cfg_param(PASS_Z, h->cfg_z));
-  h->d_parts = (Partial*)h->dalloc((size_t)N * h->grid_x * sizeof(Partial));
+  h->max_len[PASS_X] = maxM;
+  h->max_len[PASS_Y] = maxY;
+  h->max_len[PASS_Z] = maxZ;
+  set_tiles(h, pick_cfg(PASS_X, maxM, h->force_cfg), pick_cfg(PASS_Y, maxY, h->force_cfg),
+            pick_cfg(PASS_Z, maxZ, h->force_cfg));
   h->d_flags = (int*)h->dalloc(sizeof(int));
   h->d_flux = (double*)h->dalloc(N * sizeof(double));
   h->d_ratio = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
   h->d_neg = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
-  HIPCHECK(hipMemsetAsync(h->d_parts, 0, (size_t)N * h->grid_x * sizeof(Partial), h->stream));
   HIPCHECK(hipMemsetAsync(h->d_flux, 0, N * sizeof(double), h->stream));
   HIPCHECK(hipMemsetAsync(h->d_ratio, 0, N * sizeof(unsigned long long), h->stream));
   HIPCHECK(hipMemsetAsync(h->d_neg, 0, N * sizeof(unsigned long long), h->stream));
@@ -776,6 +814,50 @@ int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls) {
     }
     h->iterations += n;
   });
+}
+
+int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { set_tiles(h, cfg_x, cfg_y, cfg_z); });
+}
+
+int mvd_get_tiles(const mvd_handle* h, int* cfg) {
+  if (!h || !cfg) {
+    g_err = "NULL argument";
+    return MVD_EINVAL;
+  }
+  cfg[0] = h->cfg_x;
+  cfg[1] = h->cfg_y;
+  cfg[2] = h->cfg_z;
+  return MVD_OK;
+}
+
+int mvd_tile_candidates(int kind, int max_len, int* out, int cap) {
+  if (kind < 0 || kind > 2) {
+    g_err = "kind must be 0 (x), 1 (y) or 2 (z)";
+    return MVD_EINVAL;
+  }
+  int n = 0;
+  for (int c = 0; c < mvd_num_cfgs(kind); ++c)
+    if (mvd_cfg_maxlen(kind, c) >= max_len) {
+      if (out && n < cap) out[n] = c;
+      ++n;
+    }
+  return n;
+}
+
+int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len) {
+  if (kind < 0 || kind > 2 || cfg < 0 || cfg >= mvd_num_cfgs(kind)) {
+    g_err = "no such tile configuration";
+    return MVD_EINVAL;
+  }
+  if (threads) *threads = mvd_cfg_threads(kind, cfg);
+  if (per_tile) *per_tile = mvd_cfg_param(kind, cfg);
+  if (max_len) *max_len = mvd_cfg_maxlen(kind, cfg);
+  return MVD_OK;
 }
 
 int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_dims, int v, int variant,

@@ -4,13 +4,22 @@
 
 #define MVD_MAX_STAGES 12
 
-// Mixed-radix plan of one 1-D complex FFT length (radices 2, 3, 4, 5, 8).
-// tw is the offset of the length-L twiddle table exp(-2 pi i m / L) in the pool.
+// Mixed-radix Stockham plan of one 1-D complex FFT length (radices 2, 3, 4,
+// 5, 8).  Per stage s: the radix, Ns (product of the earlier radices), the
+// twiddle stride L / (Ns R), and multipliers m with floor(j / d) =
+// umulhi(j, m) for the divisions by Ns and by L / R (exact for j, d < 2^16;
+// unused when the divisor is 1).  tw is the offset of the length-L table
+// exp(-2 pi i m / L) in the twiddle pool.
 struct FftPlan {
   int L;
   int nst;
   int tw;
+  int pad;
   int radix[MVD_MAX_STAGES];
+  int ns[MVD_MAX_STAGES];
+  int tws[MVD_MAX_STAGES];
+  unsigned ns_magic[MVD_MAX_STAGES];
+  unsigned nb_magic[MVD_MAX_STAGES];
 };
 
 // Spectrum roles: which kernel spectrum a convolution pass multiplies by.
@@ -61,4 +70,9 @@ MVD_HD inline int mvd_tiles(const JobDesc& j, int kind, int param) {
   if (kind == PASS_X) return mvd_cdiv(j.ny * j.nz, param);
   if (kind == PASS_Y) return mvd_cdiv(j.M, param) * j.nz + mvd_cdiv(j.nz, param);
   return mvd_cdiv(j.M, param) * j.ny + mvd_cdiv(j.ny, param);
+}
+
+// Multiplier for floor(j / d) = umulhi(j, m), d >= 2, j, d < 2^16.
+MVD_HD inline unsigned mvd_magic(unsigned d) {
+  return d < 2 ? 0u : (unsigned)((0x100000000ull + d - 1) / d);
 }

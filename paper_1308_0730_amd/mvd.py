@@ -69,6 +69,10 @@ def lib():
     L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
     L.mvd_view_update.argtypes = [H, C.c_int, C.c_int]
+    L.mvd_set_tiles.argtypes = [H, C.c_int, C.c_int, C.c_int]
+    L.mvd_get_tiles.argtypes = [H, C.POINTER(C.c_int)]
+    L.mvd_tile_candidates.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int]
+    L.mvd_tile_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.mvd_profile.argtypes = [H, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.mvd_synchronize.argtypes = [H]
     L.mvd_destroy.argtypes = [H]
@@ -80,7 +84,8 @@ def lib():
     L.mvd_version.restype = C.c_char_p
     for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_get_estimate", "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
-                 "mvd_view_update", "mvd_profile"):
+                 "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
+                 "mvd_tile_shape"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -214,6 +219,20 @@ class Deconvolver:
         _check(lib().mvd_profile(self._h, int(n), _variant(variant), ms, calls), self._h)
         return {k: (ms[i], calls[i]) for i, k in enumerate(self.PASS_NAMES)}
 
+    def tiles(self):
+        """Current launch-shape candidates (x, y, z)."""
+        c = (C.c_int * 3)()
+        _check(lib().mvd_get_tiles(self._h, c), self._h)
+        return tuple(c)
+
+    def set_tiles(self, cx, cy, cz):
+        _check(lib().mvd_set_tiles(self._h, int(cx), int(cy), int(cz)), self._h)
+        return self
+
+    def max_lengths(self):
+        """Longest transform of each pass kind over the blocks: (nx/2, ny, nz)."""
+        return (max(d[0] // 2 for d in self.dims), max(d[1] for d in self.dims), max(d[2] for d in self.dims))
+
     def estimate(self, block=0, out=None):
         """The current estimate as a CUDA tensor (nz, ny, nx)."""
         nx, ny, nz = self.dims[block]
@@ -272,6 +291,19 @@ def create_raw(blocks, options=None):
     rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, None if options is None else C.byref(options))
     msg = lib().mvd_last_error(None).decode()
     return rc, (h if h.value else None), msg
+
+
+def tile_candidates(kind, max_len):
+    n = lib().mvd_tile_candidates(kind, max_len, None, 0)
+    out = (C.c_int * max(n, 1))()
+    lib().mvd_tile_candidates(kind, max_len, out, n)
+    return list(out[:n])
+
+
+def tile_shape(kind, cfg):
+    t, p, m = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().mvd_tile_shape(kind, cfg, C.byref(t), C.byref(p), C.byref(m)))
+    return dict(threads=t.value, per_tile=p.value, max_len=m.value)
 
 
 def compound_kernel(psfs, v, variant):
