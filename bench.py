@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU form",
@@ -135,6 +137,15 @@ def main():
 
     import torch
     from paper_1308_0730_amd import mvd
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        print("[bench] copy calibration: 2 x 1 GiB device copies", file=sys.stderr, flush=True)
 
     t0 = time.time()
     blocks, meta = workload(args.config)

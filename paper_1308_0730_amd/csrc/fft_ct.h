@@ -1,0 +1,187 @@
+// Compile-time specialised Stockham transforms for the hot power-of-two
+// lengths.  Same stage algebra as the runtime engine, but the length, the
+// radix sequence and the tile shape are template parameters, so every
+// index, stride and twiddle offset folds to a constant, the stage loop
+// unrolls, and radix 16 halves the number of LDS round trips.
+//
+// Accessors used as the last stage's destination receive the butterfly slot
+// i and the output index r as well, so a fused epilogue (spectral product,
+// ratio, update) can use operands prefetched into registers in that order.
+#pragma once
+#include "fft_engine.h"
+
+namespace mvdk {
+
+// Multiply by W16^M = exp(-+2 pi i M / 16) with the cheap forms spelled out.
+template <bool INV, int M>
+__device__ __forceinline__ float2 w16mul(float2 a) {
+  constexpr int m = M & 15;
+  constexpr float r = 0.70710678118654752440f;
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi / 8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi / 8)
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 4) {
+    return mul_mi<INV>(a);
+  } else if constexpr (m == 8) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (m == 2 || m == 6 || m == 10 || m == 14) {
+    // (+-1 +- i) / sqrt 2
+    constexpr float cr = (m == 2 || m == 14) ? r : -r;
+    constexpr float si = (m == 2 || m == 6) ? -r : r;  // forward sign
+    constexpr float sv = INV ? -si : si;
+    return make_float2(cr * a.x - sv * a.y, cr * a.y + sv * a.x);
+  } else {
+    constexpr float cs[16] = {1.f, c1, r, s1, 0.f, -s1, -r, -c1, -1.f, -c1, -r, -s1, 0.f, s1, r, c1};
+    constexpr float sn[16] = {0.f, s1, r, c1, 1.f, c1, r, s1, 0.f, -s1, -r, -c1, -1.f, -c1, -r, -s1};
+    constexpr float c = cs[m];
+    constexpr float s = INV ? sn[m] : -sn[m];
+    return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+  }
+}
+
+template <bool INV, int N2, int K1>
+__device__ __forceinline__ void tw16_apply(float2 (&a)[4][4]) {
+  a[N2][K1] = w16mul<INV, N2 * K1>(a[N2][K1]);
+}
+
+// 16-point DFT as 4 x 4: X[k1 + 4 k2] = sum_n2 W16^{n2 k1} W4^{n2 k2}
+// sum_n1 x[4 n1 + n2] W4^{n1 k1}.
+template <bool INV>
+struct Dft<16, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+    }
+    tw16_apply<INV, 1, 1>(a);
+    tw16_apply<INV, 1, 2>(a);
+    tw16_apply<INV, 1, 3>(a);
+    tw16_apply<INV, 2, 1>(a);
+    tw16_apply<INV, 2, 2>(a);
+    tw16_apply<INV, 2, 3>(a);
+    tw16_apply<INV, 3, 1>(a);
+    tw16_apply<INV, 3, 2>(a);
+    tw16_apply<INV, 3, 3>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
+// Accessor adaptors: the five-argument store used by the compile-time stages.
+template <class A>
+struct Plain {
+  const A& a;
+  static constexpr bool lds = A::lds;
+  __device__ __forceinline__ float2 ld(int line, int pos) const { return a.ld(line, pos); }
+  __device__ __forceinline__ void st(int line, int pos, float2 v, int, int) const { a.st(line, pos, v); }
+};
+
+// One stage of a compile-time plan: radix R, length L, NS = product of the
+// earlier radices, T threads, NL lines, line-fast (LF) or position-fast.
+template <int R, bool INV, int L, int NS, int T, int NL, bool LF, int SY, class S, class D>
+__device__ __forceinline__ void ct_stage(int tid_in, const float2* tw, const S& src, D& dst) {
+  constexpr int NB = L / R;
+  constexpr int TOTAL = NB * NL;
+  constexpr int MAXB = (TOTAL + T - 1) / T;
+  constexpr int TWS = L / (NS * R);
+  constexpr bool FULL = TOTAL % T == 0;
+  int tid = tid_in;
+  asm volatile("" : "+v"(tid));
+  float2 v[MAXB][R];
+  int ln[MAXB], jb[MAXB];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int it = tid + i * T;
+    const int line = LF ? it % NL : it / NB;
+    const int j = LF ? it / NL : it % NB;
+    ln[i] = line;
+    jb[i] = j;
+    if (FULL || it < TOTAL) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src.ld(line, j + r * NB);
+    }
+  }
+  if (S::lds == D::lds) gsync<SY>();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int it = tid + i * T;
+    if (FULL || it < TOTAL) {
+      const int j = jb[i];
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[k * r * TWS];
+          if (INV) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      Dft<R, INV>::run(v[i]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst.st(ln[i], base + r * NS, v[i][r], i, r);
+    }
+  }
+  if (D::lds) gsync<SY>();
+}
+
+// The radix sequence Rs... applied in order: first stage src -> mid (or dst
+// when it is the only one), then mid -> mid, last stage mid -> dst.
+template <bool INV, int L, int T, int NL, bool LF, int SY, int NS, bool FIRST, int R, int... Rest>
+struct CtRun {
+  template <class S, class M, class D>
+  static __device__ __forceinline__ void run(int tid, const float2* tw, const S& src, const M& mid, D& dst) {
+    if constexpr (sizeof...(Rest) == 0) {
+      if constexpr (FIRST) {
+        ct_stage<R, INV, L, NS, T, NL, LF, SY>(tid, tw, src, dst);
+      } else {
+        ct_stage<R, INV, L, NS, T, NL, LF, SY>(tid, tw, mid, dst);
+      }
+    } else {
+      Plain<M> m{mid};
+      if constexpr (FIRST) {
+        ct_stage<R, INV, L, NS, T, NL, LF, SY>(tid, tw, src, m);
+      } else {
+        ct_stage<R, INV, L, NS, T, NL, LF, SY>(tid, tw, mid, m);
+      }
+      CtRun<INV, L, T, NL, LF, SY, NS * R, false, Rest...>::run(tid, tw, src, mid, dst);
+    }
+  }
+};
+
+template <int R, int... Rest>
+struct LastRadix {
+  static constexpr int value = LastRadix<Rest...>::value;
+};
+template <int R>
+struct LastRadix<R> {
+  static constexpr int value = R;
+};
+
+// Output positions of the last stage: butterfly slot i of this thread writes
+// output r to position j + r * (L / RL) of line `line` (the last stage's
+// butterflies have j < L / RL = NS, so k = j).
+template <int L, int RL, int T, int NL, bool LF>
+struct LastMap {
+  static constexpr int NB = L / RL;
+  static constexpr int TOTAL = NB * NL;
+  static constexpr int MAXB = (TOTAL + T - 1) / T;
+  static __device__ __forceinline__ bool at(int tid, int i, int& line, int& j) {
+    const int it = tid + i * T;
+    line = LF ? it % NL : it / NB;
+    j = LF ? it / NL : it % NB;
+    return (TOTAL % T == 0) || it < TOTAL;
+  }
+};
+
+}  // namespace mvdk

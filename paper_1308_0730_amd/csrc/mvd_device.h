@@ -1,0 +1,61 @@
+// Device helpers shared by the pass kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mvd_types.h"
+
+namespace mvdk {
+
+// Map this workgroup to (job, tile within the job) by walking the jobs'
+// tile counts for the pass kind.
+__device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int njobs, int kind,
+                                        int param, int& local) {
+  int t = blockIdx.x;
+  for (int j = 0; j < njobs; ++j) {
+    const int c = mvd_tiles(jobs[j], kind, param);
+    if (t < c) {
+      local = t;
+      return j;
+    }
+    t -= c;
+  }
+  local = 0;
+  return -1;
+}
+
+// Workgroup sum of an FP64 value and two counters; the result is valid in
+// thread 0.
+template <int T>
+__device__ __forceinline__ void block_reduce(double& f, unsigned& a, unsigned& b, double* sf,
+                                             unsigned* sa, unsigned* sb) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    f += __shfl_xor(f, o);
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sf[w] = f;
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    f = 0.0;
+    a = b = 0;
+    for (int i = 0; i < T / 64; ++i) {
+      f += sf[i];
+      a += sa[i];
+      b += sb[i];
+    }
+  }
+}
+
+// Tikhonov MAP step: the t >= 0 solving lamp t^2 + t = u, in the form
+// without cancellation.
+__device__ __forceinline__ float tikhonov(float u, float lamp) {
+  return lamp > 0.f ? 2.f * u / (1.f + sqrtf(1.f + 4.f * lamp * u)) : u;
+}
+
+}  // namespace mvdk

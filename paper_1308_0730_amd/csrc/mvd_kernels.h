@@ -17,6 +17,15 @@ int mvd_num_cfgs(int kind);
 int mvd_cfg_threads(int kind, int cfg);
 int mvd_cfg_param(int kind, int cfg);   // rows (x) or lines (y, z) per tile
 int mvd_cfg_maxlen(int kind, int cfg);  // largest transform length it accepts
+int mvd_cfg_exact(int kind, int cfg);   // > 0: compile-time plan for exactly this length
+
+// compile-time candidates (mvd_kernels_ct.hip), indexed from 0
+int mvd_ct_num_cfgs(int kind);
+int mvd_ct_cfg(int kind, int cfg, int field);
+hipError_t mvd_launch_x_ct(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
+                           int write_spec);
+hipError_t mvd_launch_y_ct(const LaunchArgs& a, int cfg, int inv, int v);
+hipError_t mvd_launch_z_ct(const LaunchArgs& a, int cfg, int v, int role, int conjH);
 
 // mode 0: R2C of psi; 1: blur -> ratio -> R2C; 2: back-projection -> update -> R2C
 hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,

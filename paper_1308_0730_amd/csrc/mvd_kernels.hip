@@ -17,60 +17,11 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_engine.h"
+#include "mvd_device.h"
 #include "mvd_kernels.h"
 
 using namespace mvdk;
 
-namespace {
-
-__device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int njobs, int kind,
-                                        int param, int& local) {
-  int t = blockIdx.x;
-  for (int j = 0; j < njobs; ++j) {
-    const int c = mvd_tiles(jobs[j], kind, param);
-    if (t < c) {
-      local = t;
-      return j;
-    }
-    t -= c;
-  }
-  local = 0;
-  return -1;
-}
-
-template <int T>
-__device__ __forceinline__ void block_reduce(double& f, unsigned& a, unsigned& b, double* sf,
-                                             unsigned* sa, unsigned* sb) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    f += __shfl_xor(f, o);
-    a += __shfl_xor(a, o);
-    b += __shfl_xor(b, o);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    sf[w] = f;
-    sa[w] = a;
-    sb[w] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    f = 0.0;
-    a = b = 0;
-    for (int i = 0; i < T / 64; ++i) {
-      f += sf[i];
-      a += sa[i];
-      b += sb[i];
-    }
-  }
-}
-
-__device__ __forceinline__ float tikhonov(float u, float lamp) {
-  // solves lamp t^2 + t = u for t >= 0 in the form without cancellation
-  return lamp > 0.f ? 2.f * u / (1.f + sqrtf(1.f + 4.f * lamp * u)) : u;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // x pass.  MODE 0: forward real-to-complex of psi.  MODE 1: inverse x of the
@@ -510,16 +461,26 @@ static const int kRowCfg[][3] = {
 #undef X
 };
 
-int mvd_num_cfgs(int kind) {
+// Candidate indices: the runtime-plan shapes first, then the compile-time
+// ones (exact length only).
+static int rt_num(int kind) {
   return kind == PASS_X ? (int)(sizeof(kRowCfg) / sizeof(kRowCfg[0]))
                         : (int)(sizeof(kColCfg) / sizeof(kColCfg[0]));
 }
-int mvd_cfg_threads(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][0] : kColCfg[cfg][0]; }
-int mvd_cfg_param(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][1] : kColCfg[cfg][1]; }
-int mvd_cfg_maxlen(int kind, int cfg) { return kind == PASS_X ? kRowCfg[cfg][2] : kColCfg[cfg][2]; }
+int mvd_num_cfgs(int kind) { return rt_num(kind) + mvd_ct_num_cfgs(kind); }
+static int cfg_field(int kind, int cfg, int f) {
+  const int n = rt_num(kind);
+  if (cfg >= n) return mvd_ct_cfg(kind, cfg - n, f);
+  return kind == PASS_X ? kRowCfg[cfg][f] : kColCfg[cfg][f];
+}
+int mvd_cfg_threads(int kind, int cfg) { return cfg_field(kind, cfg, 0); }
+int mvd_cfg_param(int kind, int cfg) { return cfg_field(kind, cfg, 1); }
+int mvd_cfg_maxlen(int kind, int cfg) { return cfg_field(kind, cfg, 2); }
+int mvd_cfg_exact(int kind, int cfg) { return cfg >= rt_num(kind) ? cfg_field(kind, cfg, 2) : 0; }
 
 hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
                         int write_spec) {
+  if (cfg >= rt_num(PASS_X)) return mvd_launch_x_ct(a, cfg - rt_num(PASS_X), mode, v, parts, flags, write_spec);
   switch (cfg) {
 #define X(i, wpb, rpw, m)                                                                        \
   case i:                                                                                        \
@@ -542,6 +503,7 @@ hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* 
 }
 
 hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v) {
+  if (cfg >= rt_num(PASS_Y)) return mvd_launch_y_ct(a, cfg - rt_num(PASS_Y), inv, v);
   switch (cfg) {
 #define X(i, t, tx, l)                                                                          \
   case i:                                                                                       \
@@ -559,6 +521,7 @@ hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v) {
 }
 
 hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH) {
+  if (cfg >= rt_num(PASS_Z)) return mvd_launch_z_ct(a, cfg - rt_num(PASS_Z), v, role, conjH);
   switch (cfg) {
 #define X(i, t, tx, l)                                                                              \
   case i:                                                                                           \

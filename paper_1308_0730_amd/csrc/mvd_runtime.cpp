@@ -82,6 +82,7 @@ struct mvd_handle {
   int cfg_x = 0, cfg_y = 0, cfg_z = 0;
   int grid_x = 0, grid_y = 0, grid_z = 0;
   int max_len[3] = {0, 0, 0};
+  int uniform_len[3] = {0, 0, 0};  // the common length of a pass kind, 0 if the blocks differ
   size_t parts_cap = 0;
   bool spec_valid = false;
   bool built[N_ROLES] = {true, false, false, false};
@@ -256,23 +257,29 @@ void upload_spectrum(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* 
   (void)hipFree(dT);
 }
 
-int pick_cfg(int kind, int maxlen, int force) {
-  const int n = mvd_num_cfgs(kind);
-  if (force > 0) {
-    const int c = force - 1;
-    if (c < n && mvd_cfg_maxlen(kind, c) >= maxlen) return c;
-  }
-  // default: the smallest tile family that holds the longest line
-  static const int xo[] = {0, 1, 2, 3, 4};
-  static const int co[] = {0, 1, 2, 3};
+bool cfg_fits(const mvd_handle* h, int kind, int c);
+
+// Default launch shape of a pass kind: a forced candidate if it fits, else
+// the first fitting entry of a preference list (compile-time plans for the
+// common power-of-two lengths, then the smallest runtime-plan family).
+int pick_cfg(const mvd_handle* h, int kind) {
+  if (h->force_cfg > 0 && cfg_fits(h, kind, h->force_cfg - 1)) return h->force_cfg - 1;
+  const int nrt = mvd_num_cfgs(kind) - mvd_ct_num_cfgs(kind);
+  // compile-time candidates in order of preference
+  static const int ct_x[] = {0, 3, 4, 5, 6};
+  static const int ct_c[] = {0, 3, 6, 7};
   if (kind == PASS_X) {
-    for (int c : xo)
-      if (mvd_cfg_maxlen(kind, c) >= maxlen) return c;
+    for (int c : ct_x)
+      if (cfg_fits(h, kind, nrt + c)) return nrt + c;
+    for (int c : {0, 1, 2, 3, 4})
+      if (cfg_fits(h, kind, c)) return c;
   } else {
-    for (int c : co)
-      if (mvd_cfg_maxlen(kind, c) >= maxlen) return c;
+    for (int c : ct_c)
+      if (cfg_fits(h, kind, nrt + c)) return nrt + c;
+    for (int c : {0, 1, 2, 3})
+      if (cfg_fits(h, kind, c)) return c;
   }
-  bad("no launch shape holds length " + std::to_string(maxlen));
+  bad("no launch shape holds length " + std::to_string(h->max_len[kind]));
 }
 
 int total_tiles(const mvd_handle* h, int kind, int param) {
@@ -314,11 +321,18 @@ void build_jobs(mvd_handle* h) {
 
 // Select the launch shapes of the three pass kinds; recomputes the grids,
 // grows the partials buffer and drops the cached graphs.
+bool cfg_fits(const mvd_handle* h, int kind, int c) {
+  if (c < 0 || c >= mvd_num_cfgs(kind)) return false;
+  const int ex = mvd_cfg_exact(kind, c);
+  if (ex > 0) return h->uniform_len[kind] == ex;
+  return mvd_cfg_maxlen(kind, c) >= h->max_len[kind];
+}
+
 void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
   const int c[3] = {cx, cy, cz};
   for (int k = 0; k < 3; ++k) {
     if (c[k] < 0 || c[k] >= mvd_num_cfgs(k)) bad("tile configuration index out of range");
-    if (mvd_cfg_maxlen(k, c[k]) < h->max_len[k]) bad("tile configuration too small for this volume");
+    if (!cfg_fits(h, k, c[k])) bad("tile configuration does not fit the transform lengths of this handle");
   }
   const int gx = total_tiles(h, PASS_X, mvd_cfg_param(PASS_X, cx));
   const int gy = total_tiles(h, PASS_Y, mvd_cfg_param(PASS_Y, cy));
@@ -463,8 +477,15 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
   h->max_len[PASS_X] = maxM;
   h->max_len[PASS_Y] = maxY;
   h->max_len[PASS_Z] = maxZ;
-  set_tiles(h, pick_cfg(PASS_X, maxM, h->force_cfg), pick_cfg(PASS_Y, maxY, h->force_cfg),
-            pick_cfg(PASS_Z, maxZ, h->force_cfg));
+  h->uniform_len[PASS_X] = maxM;
+  h->uniform_len[PASS_Y] = maxY;
+  h->uniform_len[PASS_Z] = maxZ;
+  for (auto& B : h->blocks) {
+    if (B.M != maxM) h->uniform_len[PASS_X] = 0;
+    if (B.ny != maxY) h->uniform_len[PASS_Y] = 0;
+    if (B.nz != maxZ) h->uniform_len[PASS_Z] = 0;
+  }
+  set_tiles(h, pick_cfg(h, PASS_X), pick_cfg(h, PASS_Y), pick_cfg(h, PASS_Z));
   h->d_flags = (int*)h->dalloc(sizeof(int));
   h->d_flux = (double*)h->dalloc(N * sizeof(double));
   h->d_ratio = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
@@ -841,11 +862,13 @@ int mvd_tile_candidates(int kind, int max_len, int* out, int cap) {
     return MVD_EINVAL;
   }
   int n = 0;
-  for (int c = 0; c < mvd_num_cfgs(kind); ++c)
-    if (mvd_cfg_maxlen(kind, c) >= max_len) {
+  for (int c = 0; c < mvd_num_cfgs(kind); ++c) {
+    const int ex = mvd_cfg_exact(kind, c);
+    if (ex > 0 ? ex == max_len : mvd_cfg_maxlen(kind, c) >= max_len) {
       if (out && n < cap) out[n] = c;
       ++n;
     }
+  }
   return n;
 }
 

@@ -51,7 +51,10 @@ def autotune(d, variant="eff", iters=1, cache_path=DEFAULT_CACHE, use_cache=True
         for c in mvd.tile_candidates(kind, lens[kind]):
             cfg = list(best)
             cfg[kind] = c
-            d.set_tiles(*cfg)
+            try:
+                d.set_tiles(*cfg)
+            except mvd.MVDError:
+                continue  # a compile-time plan whose length not every block has
             prof = d.profile(iters, variant)
             res[c] = sum(prof[p][0] for p in KIND_PASSES[kind])
             if verbose:

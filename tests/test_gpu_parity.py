@@ -189,3 +189,33 @@ def test_device_value_checks(mvd):
     with pytest.raises(mvd.MVDError) as e:
         mvd.Deconvolver(dv, psfs)
     assert e.value.code == mvd.MVD_EINVAL
+
+
+SHAPE_DIMS = [(64, 64, 64), (512, 64, 32), (32, 512, 64), (32, 64, 256), (64, 128, 512), (150, 96, 100)]
+
+
+@pytest.mark.parametrize("dims", SHAPE_DIMS)
+def test_every_launch_shape(mvd, dims):
+    """Every launch-shape candidate of every pass kind (runtime-plan and
+    compile-time-plan) gives the oracle's iteration: the autotuner may pick
+    any of them."""
+    views, psfs, w = problem(dims, 2, 21, weights=True, psf_shape=(5, 5, 5))
+    pb = O.Problem(views, psfs, w, 0.01)
+    psi_r = pb.iterate(pb.psi0(), 1, O.OPT1).astype(np.float32)
+    ref = pb.iterate(psi_r.astype(np.float64), 1, O.OPT1)
+    with mvd.Deconvolver(views, psfs, w, lam=0.01) as d:
+        base = d.tiles()
+        lens = d.max_lengths()
+        tried = 0
+        for kind in range(3):
+            for c in mvd.tile_candidates(kind, lens[kind]):
+                cfg = list(base)
+                cfg[kind] = c
+                d.set_tiles(*cfg)
+                d.set_estimate(psi_r)
+                d.iterate(1, O.OPT1)
+                e = rel(d.estimate().cpu().numpy(), ref)
+                print(f"kind {kind} candidate {c} {mvd.tile_shape(kind, c)}: rel_l2={e:.3e}")
+                assert e <= ONE_STEP, (kind, c, e)
+                tried += 1
+    assert tried >= 3
