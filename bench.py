@@ -116,6 +116,57 @@ def cpu_baseline(blocks, meta, budget_s=25.0):
                       f"{el:.1f} s"}
 
 
+def batched_form(steps, warmup):
+    """The 48-block batched workload: one handle for all blocks (every pass of
+    an iteration one launch over all blocks, one HIP graph per iteration)
+    against the same blocks looped through one plain handle each."""
+    import torch
+    from paper_1308_0730_amd import mvd, tune
+    t0 = time.time()
+    blocks, meta = workload(4)
+    print(f"[bench] batched workload generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    its, var = meta["iterations"], meta["variant"]
+    vox = sum(int(np.prod(b.dims)) for b in blocks) * len(blocks[0].views) * its
+    b = mvd.Deconvolver.batch([(x.views, x.psfs, x.weights) for x in blocks])
+    b.iterate(1, var)
+    tune.autotune(b, var, iters=1, cache_path=None)
+    for _ in range(warmup):
+        b.iterate(its, var)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.iterate(its, var)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    tiles = b.tiles()
+    b.close()
+    del b
+    plains = [mvd.Deconvolver(x.views, x.psfs, x.weights) for x in blocks]
+    for d in plains:
+        d.iterate(1, var)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        for d in plains:
+            d.iterate(its, var)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        for d in plains:
+            d.iterate(its, var)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / steps
+    for d in plains:
+        d.close()
+    return {"workload": meta["workload"], "blocks": len(blocks), "voxel_view_updates_per_step": vox,
+            "batched": {"ms_per_step": round(ms_b, 3), "value": round(vox / ms_b / 1e6, 3), "unit": "Gvox/s",
+                        "tiles": list(tiles)},
+            "plain_loop": {"ms_per_step": round(ms_p, 3), "value": round(vox / ms_p / 1e6, 3), "unit": "Gvox/s"},
+            "batched_speedup": round(ms_p / ms_b, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +178,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
+    ap.add_argument("--forms", action="store_true",
+                    help="also measure the batched form (48 blocks) against looping the plain form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -212,6 +265,10 @@ def main():
         torch.cuda.empty_cache()
         cpu = cpu_baseline(blocks, meta, args.cpu_budget)
 
+    forms = None
+    if args.forms:
+        forms = {"batched": batched_form(max(1, args.steps // 2), 1)}
+
     dims = [list(b.dims) for b in blocks]
     out = {
         "metric": "voxel-view updates/s", "value": round(value, 3), "unit": "Gvox/s", "n_gpus": 1,
@@ -221,7 +278,7 @@ def main():
                    "views": n_views, "iterations": its,
                    "variant": meta["variant"], "lambda": meta["lam"], "weights": weighted,
                    "voxel_view_updates_per_step": vox_updates},
-        "roofline": roof, "passes": passes, "launch": launch, "cpu_baseline": cpu,
+        "roofline": roof, "passes": passes, "launch": launch, "cpu_baseline": cpu, "forms": forms,
         "stats": {"flux_last_iteration": st["flux"], "ratio_clamps": st["ratio_clamps"],
                   "neg_clamps": st["neg_clamps"], "nonfinite": st["nonfinite"]},
     }

@@ -160,13 +160,16 @@ int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
 
 /* Launch shapes (the autotuner's knobs).  Pass kinds: 0 x (rows), 1 y,
  * 2 z (columns).  Candidate c of a kind has a thread count, a tile size
- * (rows or columns per workgroup) and the longest transform it accepts.
- * mvd_tile_candidates lists, into out[0..cap), the candidates that hold
- * max_len and returns how many exist.  mvd_set_tiles selects one candidate
- * per kind for a handle (MVD_EINVAL if one is too small for its volumes);
- * later iterations use them.  mvd_get_tiles reports the current choice. */
+ * (rows or columns per workgroup), the longest transform it accepts and,
+ * for compile-time plans, the one length it is built for (exact_len > 0;
+ * usable only when every block has that length; 0 = runtime plan, any
+ * 5-smooth length up to max_len).  mvd_tile_candidates lists, into
+ * out[0..cap), the candidates for transforms of length max_len and returns
+ * how many exist.  mvd_set_tiles selects one candidate per kind for a handle
+ * (MVD_EINVAL if one does not fit its volumes); later iterations use them.
+ * mvd_get_tiles reports the current choice. */
 int mvd_tile_candidates(int kind, int max_len, int* out, int cap);
-int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len);
+int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len, int* exact_len);
 int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z);
 int mvd_get_tiles(const mvd_handle* h, int* cfg);
 

@@ -872,7 +872,7 @@ int mvd_tile_candidates(int kind, int max_len, int* out, int cap) {
   return n;
 }
 
-int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len) {
+int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len, int* exact_len) {
   if (kind < 0 || kind > 2 || cfg < 0 || cfg >= mvd_num_cfgs(kind)) {
     g_err = "no such tile configuration";
     return MVD_EINVAL;
@@ -880,6 +880,7 @@ int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len)
   if (threads) *threads = mvd_cfg_threads(kind, cfg);
   if (per_tile) *per_tile = mvd_cfg_param(kind, cfg);
   if (max_len) *max_len = mvd_cfg_maxlen(kind, cfg);
+  if (exact_len) *exact_len = mvd_cfg_exact(kind, cfg);
   return MVD_OK;
 }
 

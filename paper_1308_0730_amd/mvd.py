@@ -72,7 +72,8 @@ def lib():
     L.mvd_set_tiles.argtypes = [H, C.c_int, C.c_int, C.c_int]
     L.mvd_get_tiles.argtypes = [H, C.POINTER(C.c_int)]
     L.mvd_tile_candidates.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int]
-    L.mvd_tile_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.mvd_tile_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)]
     L.mvd_profile.argtypes = [H, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.mvd_synchronize.argtypes = [H]
     L.mvd_destroy.argtypes = [H]
@@ -301,9 +302,9 @@ def tile_candidates(kind, max_len):
 
 
 def tile_shape(kind, cfg):
-    t, p, m = C.c_int(), C.c_int(), C.c_int()
-    _check(lib().mvd_tile_shape(kind, cfg, C.byref(t), C.byref(p), C.byref(m)))
-    return dict(threads=t.value, per_tile=p.value, max_len=m.value)
+    t, p, m, e = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    _check(lib().mvd_tile_shape(kind, cfg, C.byref(t), C.byref(p), C.byref(m), C.byref(e)))
+    return dict(threads=t.value, per_tile=p.value, max_len=m.value, exact_len=e.value)
 
 
 def compound_kernel(psfs, v, variant):

@@ -1,0 +1,93 @@
+"""Batched form: blocks of different sizes deconvolved together equal the
+plain form run on each block alone, and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mvd_oracle as O
+from paper_1308_0730_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(40, 36, 30), (48, 40, 36), (64, 64, 48), (60, 54, 50), (32, 32, 32), (96, 24, 20)]
+
+
+@pytest.fixture(scope="module")
+def mvd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1308_0730_amd import mvd as m
+    return m
+
+
+def block(dims, seed):
+    s = synth.make_problem(dims, max(4, int(40 * np.prod(dims) / 64 ** 3)), [0.0, 45.0, 90.0, 135.0],
+                           (7, 7, 9), 1.0 * (1 + 0.05 * (seed % 3)), 2.5, seed, weights=False)
+    rng = np.random.default_rng(seed)
+    w = [np.clip(rng.uniform(-0.2, 1.2, size=s.views[0].shape), 0, 1).astype(np.float32) for _ in range(4)]
+    return s.views, s.psfs, w
+
+
+def runtime_tiles(mvd, lens):
+    """The first runtime-plan candidate of each pass kind (any length)."""
+    out = []
+    for kind in range(3):
+        for c in mvd.tile_candidates(kind, lens[kind]):
+            if mvd.tile_shape(kind, c)["exact_len"] == 0:
+                out.append(c)
+                break
+    return out
+
+
+@pytest.mark.parametrize("variant", [O.RL, O.EFF])
+def test_batched_equals_plain_per_block(mvd, variant):
+    blocks = [block(d, 100 + i) for i, d in enumerate(DIMS)]
+    with mvd.Deconvolver.batch(blocks, lam=0.01) as b:
+        b.iterate(3, variant)
+        got = [b.estimate(i).cpu().numpy() for i in range(len(DIMS))]
+        st = b.stats()
+    assert st["n_blocks"] == len(DIMS) and not st["nonfinite"]
+    for i, (v, p, w) in enumerate(blocks):
+        with mvd.Deconvolver(v, p, w, lam=0.01) as d:
+            d.set_tiles(*runtime_tiles(mvd, d.max_lengths()))
+            d.iterate(3, variant)
+            ref = d.estimate().cpu().numpy()
+        # same per-line arithmetic (runtime plans of the same lengths): bitwise
+        np.testing.assert_array_equal(got[i], ref)
+
+
+def test_batched_matches_oracle(mvd):
+    blocks = [block(d, 200 + i) for i, d in enumerate(DIMS[:4])]
+    with mvd.Deconvolver.batch(blocks) as b:
+        b.iterate(2, O.OPT1)
+        got = [b.estimate(i).cpu().numpy() for i in range(4)]
+    for i, (v, p, w) in enumerate(blocks):
+        ref = O.run(v, p, 2, O.OPT1, weights=w)
+        e = O.rel_l2(got[i], ref)
+        print(f"block {i} {DIMS[i]}: rel_l2={e:.3e}")
+        assert e <= 1e-5
+
+
+def test_batched_every_launch_shape(mvd):
+    """Every runtime-plan shape of every kind, on blocks of unequal lengths."""
+    blocks = [block(d, 300 + i) for i, d in enumerate(DIMS[:3])]
+    with mvd.Deconvolver.batch(blocks) as b:
+        base = b.tiles()
+        b.iterate(1, O.EFF)
+        ref = [b.estimate(i).cpu().numpy() for i in range(3)]
+        psi1 = [r.copy() for r in ref]
+        b.iterate(1, O.EFF)
+        ref2 = [b.estimate(i).cpu().numpy() for i in range(3)]
+        lens = b.max_lengths()
+        for kind in range(3):
+            for c in mvd.tile_candidates(kind, lens[kind]):
+                if mvd.tile_shape(kind, c)["exact_len"]:
+                    continue
+                cfg = list(base)
+                cfg[kind] = c
+                b.set_tiles(*cfg)
+                for i in range(3):
+                    b.set_estimate(psi1[i], block=i)
+                b.iterate(1, O.EFF)
+                for i in range(3):
+                    np.testing.assert_array_equal(b.estimate(i).cpu().numpy(), ref2[i])
