@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PASS_NAMES = ("y_forward", "y_inverse", "z_product", "x_ratio", "x_update")
-KERNEL_SOURCES = ("paper_1308_0730_amd/csrc/mvd_kernels.hip", "paper_1308_0730_amd/csrc/fft_engine.h")
+KERNEL_SOURCES = ("paper_1308_0730_amd/csrc/mvd_kernels.hip", "paper_1308_0730_amd/csrc/mvd_kernels_ct.hip",
+                  "paper_1308_0730_amd/csrc/fft_engine.h", "paper_1308_0730_amd/csrc/fft_ct.h",
+                  "paper_1308_0730_amd/csrc/mvd_device.h", "paper_1308_0730_amd/csrc/mvd_types.h")
 
 
 def workload(cfg):
