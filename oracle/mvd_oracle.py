@@ -264,3 +264,90 @@ def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# ------------------------------------------------------ differentiated form --
+#
+# Loss of the unrolled run: L = sum_v sum_x (psi^T (x) P_v - phi_v)^2, with
+# psi^T after n_iter sequential iterations of the RL update from psi^0.
+# Gradients with respect to psi^0 and to the raw PSF inputs (through the
+# normalisation of eq. 3) by reverse-mode differentiation of every step; the
+# clamps max(b, eps) and max(c, 0) contribute zero derivative where active.
+# Pinned by central finite differences and adjoint dot-product tests.
+
+def circ_corr_window(f, g, shape):
+    """r[c + d] = sum_x f(x) g(x - d) for d in the centred window `shape`
+    (odd extents): the adjoint of f = g (x) K with respect to K."""
+    F = sfft.rfftn(np.asarray(f, dtype=np.float64), workers=-1)
+    G = sfft.rfftn(np.asarray(g, dtype=np.float64), workers=-1)
+    r = sfft.irfftn(F * np.conj(G), s=f.shape, workers=-1)
+    kz, ky, kx = shape
+    iz = (np.arange(kz) - (kz - 1) // 2) % f.shape[0]
+    iy = (np.arange(ky) - (ky - 1) // 2) % f.shape[1]
+    ix = (np.arange(kx) - (kx - 1) // 2) % f.shape[2]
+    return r[np.ix_(iz, iy, ix)]
+
+
+def loss_value(psi, views, P):
+    return float(sum(np.sum((circ_conv(psi, p) - np.asarray(phi, np.float64)) ** 2) for p, phi in zip(P, views)))
+
+
+def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
+    """Loss and its gradients for the sequential RL update (K_v = P_v*).
+
+    Returns (L, dL/dpsi0, [dL/dpsf_v]) with each PSF gradient on the raw
+    input extents of psfs[v]."""
+    pb = Problem(views, psfs, weights, lam)
+    P = pb.P
+    N = pb.n
+    psi = np.asarray(psi0, dtype=np.float64).copy()
+    tape = []
+    for _ in range(n_iter):
+        for v in range(N):
+            w = None if pb.weights is None else pb.weights[v]
+            b = circ_conv(psi, P[v])
+            q = pb.views[v] / np.maximum(b, pb.eps)
+            c = circ_conv(q, mirror(P[v]))
+            u = psi * np.maximum(c, 0.0)
+            t = tikhonov(u, pb.lam_p)
+            new = t if w is None else psi + w * (t - psi)
+            tape.append((v, psi, b, q, c, u, w))
+            psi = new
+    L = 0.0
+    gpsi = np.zeros_like(psi)
+    gP = [np.zeros_like(p) for p in P]
+    for v in range(N):
+        r = circ_conv(psi, P[v]) - pb.views[v]
+        L += float(np.sum(r * r))
+        gpsi += circ_conv(2.0 * r, mirror(P[v]))
+        gP[v] += circ_corr_window(2.0 * r, psi, P[v].shape)
+    for (v, psi_in, b, q, c, u, w) in reversed(tape):
+        g = gpsi
+        tbar = g if w is None else w * g
+        dT = 1.0 if pb.lam_p == 0.0 else 1.0 / np.sqrt(1.0 + 4.0 * pb.lam_p * u)
+        ubar = tbar * dT
+        gdirect = ubar * np.maximum(c, 0.0) + (0.0 if w is None else (1.0 - w) * g)
+        cbar = ubar * psi_in * (c > 0)
+        # c = q (x) P_v*: adjoint in q is a convolution with P_v; in the kernel
+        # K = P_v*, K[c + j] gets sum_x cbar(x) q(x - j), i.e. P_v[c - j]
+        qbar = circ_conv(cbar, P[v])
+        gP[v] += mirror(circ_corr_window(cbar, q, P[v].shape))
+        bbar = np.where(b > pb.eps, -qbar * q / b, 0.0)
+        gP[v] += circ_corr_window(bbar, psi_in, P[v].shape)
+        gpsi = gdirect + circ_conv(bbar, mirror(P[v]))
+    # through the normalisation P = G / sum(G) and the odd padding
+    out = []
+    for v in range(N):
+        G = np.asarray(psfs[v], dtype=np.float64)
+        S = G.sum()
+        gpad = gP[v]
+        gn = (gpad - np.sum(gpad * P[v])) / S
+        out.append(gn[:G.shape[0], :G.shape[1], :G.shape[2]])
+    return L, gpsi, out
+
+
+def loss_of(views, psfs, n_iter, psi0, weights=None, lam=0.0):
+    """The loss alone (forward), for finite differences."""
+    pb = Problem(views, psfs, weights, lam)
+    psi = pb.iterate(np.asarray(psi0, dtype=np.float64), n_iter, RL)
+    return loss_value(psi, pb.views, pb.P)
