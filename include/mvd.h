@@ -158,6 +158,27 @@ int mvd_view_update(mvd_handle* h, int view, int variant);
 #define MVD_PASS_KINDS 5
 int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
 
+/* Differentiated form (single-block handles, MVD_RL).  Runs n iterations
+ * from psi0 (NULL: the flat start s; psi0_kind host or device), keeping one
+ * checkpoint per iteration, and returns the loss
+ *   L = sum_v sum_x (psi_n (x) P_v - phi_v)^2
+ * in *loss.  If grad_psf is not NULL, grad_psf[v] (host, the raw extents of
+ * PSF v, may be NULL for some v) receives dL/dG_v with respect to the raw
+ * PSF values G_v as given (through the normalisation P = G / sum G of eq. 3);
+ * if grad_psi0 is not NULL it receives dL/dpsi0 (nx*ny*nz floats,
+ * grad_kind host or device).  Gradients come from hand-written adjoint passes
+ * run in reverse over each iteration recomputed from its checkpoint; the
+ * PSF cross-spectra are accumulated in FP64.  The clamps max(b, eps) and
+ * max(c, 0) contribute zero derivative where active.  Leaves psi at the end
+ * of the run; synchronises.  MVD_ESTATE for batched handles. */
+int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
+                  double* const* grad_psf, float* grad_psi0, int grad_kind);
+
+/* Replace the PSFs of a single-block handle (same count; extents may change
+ * within the volume): recomputes their spectra; compound kernels are rebuilt
+ * on their next use.  For PSF refinement loops. */
+int mvd_set_psfs(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind);
+
 /* Launch shapes (the autotuner's knobs).  Pass kinds: 0 x (rows), 1 y,
  * 2 z (columns).  Candidate c of a kind has a thread count, a tile size
  * (rows or columns per workgroup), the longest transform it accepts and,

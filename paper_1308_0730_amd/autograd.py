@@ -1,0 +1,62 @@
+"""Differentiable loss of the unrolled sequential RL deconvolution.
+
+MVDLoss is a torch.autograd.Function around the library's hand-written
+adjoint passes: forward runs n iterations from psi0 with the given PSFs and
+returns L = sum_v |psi_n (x) P_v - phi_v|^2; its gradients with respect to
+the PSF values and psi0 come from the same library call.  psf_from_theta
+builds the anisotropic Gaussian PSF of a view from (sigma_xy, sigma_z) in
+torch, so gradients reach the PSF parameters through autograd.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import mvd
+
+
+class MVDLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, handle, n_iter, psi0, *psfs):
+        handle.set_psfs([p.detach().to("cpu", torch.float32).numpy() for p in psfs])
+        want_p = any(ctx.needs_input_grad[3:])
+        want_psi = ctx.needs_input_grad[2]
+        loss, gp, gpsi = handle.loss_grad(n_iter, psi0, grad_psf=want_p, grad_psi0=want_psi)
+        ctx.gp = None if gp is None else [torch.from_numpy(g).to(p.dtype) for g, p in zip(gp, psfs)]
+        ctx.gpsi = gpsi
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gout):
+        gpsi = None if ctx.gpsi is None else (ctx.gpsi * float(gout)).to(torch.float32)
+        n_psf = len(ctx.needs_input_grad) - 3
+        gps = (None,) * n_psf if ctx.gp is None else tuple(gout * g for g in ctx.gp)
+        return (None, None, gpsi) + gps
+
+
+def psf_from_theta(sigma_xy, sigma_z, theta_deg, extent_xyz):
+    """Unnormalised anisotropic Gaussian exp(-d^T C^-1 d / 2) with C =
+    R_y(theta) diag(sxy^2, sxy^2, sz^2) R_y(theta)^T on an odd box, as a torch
+    float64 tensor (kz, ky, kx) differentiable in (sigma_xy, sigma_z)."""
+    kx, ky, kz = extent_xyz
+    t = math.radians(theta_deg)
+    c, s = math.cos(t), math.sin(t)
+    z, y, x = torch.meshgrid(torch.arange(kz, dtype=torch.float64) - (kz - 1) / 2,
+                             torch.arange(ky, dtype=torch.float64) - (ky - 1) / 2,
+                             torch.arange(kx, dtype=torch.float64) - (kx - 1) / 2, indexing="ij")
+    # coordinates in the PSF's own frame: R^T d
+    u = c * x - s * z
+    w = s * x + c * z
+    q = (u * u + y * y) / (sigma_xy * sigma_xy) + (w * w) / (sigma_z * sigma_z)
+    return torch.exp(-0.5 * q)
+
+
+def loss_and_theta_grad(handle, n_iter, psi0, theta, angles, extent_xyz):
+    """Loss and d loss / d theta for theta = [[sigma_xy, sigma_z] per view]."""
+    th = torch.as_tensor(np.asarray(theta, np.float64)).clone().requires_grad_(True)
+    psfs = [psf_from_theta(th[v, 0], th[v, 1], angles[v], extent_xyz) for v in range(len(angles))]
+    L = MVDLoss.apply(handle, n_iter, psi0, *psfs)
+    L.backward()
+    return float(L), th.grad.numpy().copy()

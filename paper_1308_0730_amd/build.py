@@ -26,6 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 SOURCES = [
     ("mvd_kernels.hip", True),
     ("mvd_kernels_ct.hip", True),
+    ("mvd_adjoint.hip", True),
     ("mvd_runtime.cpp", True),
     ("mvd_host.cpp", False),
 ]

@@ -43,4 +43,10 @@ std::vector<cd> twiddles(int n);
 // the main part [kz][ky][kx < nx/2] and the Nyquist plane [kz][ky].
 void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float* nyq_out);
 
+// Inverse DFT of a real volume's half spectrum (main part [kz][ky][kx < nx/2]
+// and the kx = nx/2 plane [kz][ky]), divided by V, evaluated only at the
+// offsets d of a centred odd window (wx, wy, wz): out[dz][dy][dx].
+void window_idft_half(const cd* main, const cd* nyq, int nx, int ny, int nz, int wx, int wy, int wz,
+                      double* out);
+
 }  // namespace mvdh

@@ -13,6 +13,17 @@ struct LaunchArgs {
   int grid;              // total tiles of the pass over all jobs
 };
 
+// Extra operands of the differentiated form's x passes (block 0 only).
+struct AdjPtrs {
+  float* b;            // blur stored by the forward (ratio) pass
+  float* q;            // ratio stored by the forward pass
+  float* c;            // back-projection stored by the forward (update) pass
+  float* psi_in;       // estimate before the view-update
+  const float* gbar;   // dL/dpsi' (input of the update's adjoint)
+  float* part;         // direct part of dL/dpsi
+  float* out;          // dL/dpsi written by the finishing pass
+};
+
 int mvd_num_cfgs(int kind);
 int mvd_cfg_threads(int kind, int cfg);
 int mvd_cfg_param(int kind, int cfg);   // rows (x) or lines (y, z) per tile
@@ -41,3 +52,9 @@ hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s);
 hipError_t mvd_launch_spec_z(const double* A2, int kz, int cz, int M, int ny, int nz,
                              const double* twz, double invV, float* main_out, float* nyq_out,
                              hipStream_t s);
+
+// differentiated form (mvd_adjoint.hip); cfg indexes the runtime-plan shapes
+hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
+                           const AdjPtrs& ap);
+hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int conjH, float2* s_out,
+                           const float2* s_in, double2* acc, int acc_mode);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -46,6 +47,8 @@ struct Block {
   float* w = nullptr;
   float* H[N_ROLES] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<mvdh::Kern> P;  // prepared PSFs
+  std::vector<double> psf_sum;     // sums of the raw PSF inputs
+  std::vector<std::array<int, 3>> psf_dims;  // raw extents {kx, ky, kz}
   double s = 0;
   float eps = 0, lamp = 0;
 };
@@ -88,6 +91,18 @@ struct mvd_handle {
   bool built[N_ROLES] = {true, false, false, false};
   int64_t iterations = 0;
   hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  // differentiated form: runtime-plan shapes, grids and buffers (block 0)
+  int rt_cfg[3] = {-1, -1, -1};
+  int rt_grid[3] = {0, 0, 0};
+  int grad_ckpt_cap = 0;
+  float* g_ckpt = nullptr;                 // checkpoints, one volume per iteration
+  float *g_b = nullptr, *g_q = nullptr, *g_c = nullptr, *g_psi = nullptr;  // [view][V]
+  float2 *g_spsi = nullptr, *g_sq = nullptr, *g_sT = nullptr;  // spectra [view][spec]
+  double2* g_acc = nullptr;                // PSF cross-spectra [view][spec], FP64
+  float *g_gbar = nullptr, *g_part = nullptr, *g_psiT = nullptr;
+  Partial* g_parts = nullptr;              // [view][x tiles]
+  double* g_loss = nullptr;
+  unsigned long long *g_lr = nullptr, *g_ln = nullptr;
   std::string err;
 
   void* dalloc(size_t bytes) {
@@ -126,7 +141,11 @@ struct mvd_handle {
   }
 };
 
+extern "C" int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block);
+
 namespace {
+
+int read_flag(mvd_handle* h);
 
 int64_t vox(const int* d) { return (int64_t)d[0] * d[1] * d[2]; }
 
@@ -450,6 +469,25 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
       }
     }
     B.P = std::move(prepared[b]);
+    for (int v = 0; v < N; ++v) {
+      const int* k = p.psf_dims + 3 * v;
+      B.psf_dims.push_back({k[0], k[1], k[2]});
+    }
+    if (p.mem_kind == MVD_MEM_HOST) {
+      for (int v = 0; v < N; ++v) {
+        const int* k = p.psf_dims + 3 * v;
+        double sum = 0;
+        for (size_t i = 0; i < (size_t)k[0] * k[1] * k[2]; ++i) sum += p.psfs[v][i];
+        B.psf_sum.push_back(sum);
+      }
+    } else {
+      for (int v = 0; v < N; ++v) {
+        const auto hp = fetch_psf(&p, v);
+        double sum = 0;
+        for (float x : hp) sum += x;
+        B.psf_sum.push_back(sum);
+      }
+    }
     for (int v = 0; v < N; ++v) upload_spectrum(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.spec_elems * 2);
     plan_for(h, B.M, plans, tw);
     plan_for(h, B.ny, plans, tw);
@@ -502,7 +540,7 @@ void ensure_role(mvd_handle* h, int role) {
   if (h->built[role]) return;
   const int variant = role;  // ROLE_EFF == MVD_EFF etc.
   for (auto& B : h->blocks) {
-    B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.spec_elems * 2 * sizeof(float));
+    if (!B.H[role]) B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.spec_elems * 2 * sizeof(float));
     for (int v = 0; v < h->nviews; ++v) {
       const mvdh::Kern K = mvdh::compound_kernel(B.P, v, variant);
       upload_spectrum(h, B, K, B.H[role] + (size_t)v * B.spec_elems * 2);
@@ -625,6 +663,238 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
   }
   HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, h->stream));
   h->iterations += n;
+}
+
+// ---- differentiated form -------------------------------------------------
+
+void grad_setup(mvd_handle* h, int n) {
+  const Block& B = h->blocks[0];
+  if (h->rt_cfg[0] < 0) {
+    const int lens[3] = {B.M, B.ny, B.nz};
+    const int nrt[3] = {5, 4, 4};
+    for (int k = 0; k < 3; ++k) {
+      for (int c = 0; c < nrt[k]; ++c)
+        if (mvd_cfg_maxlen(k, c) >= lens[k]) {
+          h->rt_cfg[k] = c;
+          break;
+        }
+      if (h->rt_cfg[k] < 0) bad("no runtime launch shape for the differentiated form");
+      h->rt_grid[k] = total_tiles(h, k, mvd_cfg_param(k, h->rt_cfg[k]));
+    }
+    const size_t N = h->nviews, V = B.V, S = B.spec_elems;
+    h->g_b = (float*)h->dalloc(N * V * sizeof(float));
+    h->g_q = (float*)h->dalloc(N * V * sizeof(float));
+    h->g_c = (float*)h->dalloc(N * V * sizeof(float));
+    h->g_psi = (float*)h->dalloc(N * V * sizeof(float));
+    h->g_spsi = (float2*)h->dalloc(N * S * sizeof(float2));
+    h->g_sq = (float2*)h->dalloc(N * S * sizeof(float2));
+    h->g_sT = (float2*)h->dalloc(S * sizeof(float2));
+    h->g_acc = (double2*)h->dalloc(N * S * sizeof(double2));
+    h->g_gbar = (float*)h->dalloc(V * sizeof(float));
+    h->g_part = (float*)h->dalloc(V * sizeof(float));
+    h->g_psiT = (float*)h->dalloc(V * sizeof(float));
+    h->g_parts = (Partial*)h->dalloc(N * h->rt_grid[0] * sizeof(Partial));
+    h->g_loss = (double*)h->dalloc(N * sizeof(double));
+    h->g_lr = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+    h->g_ln = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+  }
+  if (n > h->grad_ckpt_cap) {
+    h->g_ckpt = (float*)h->dalloc((size_t)n * B.V * sizeof(float));
+    h->grad_ckpt_cap = n;
+  }
+}
+
+AdjPtrs adj_ptrs(mvd_handle* h, int v) {
+  const size_t V = h->blocks[0].V;
+  AdjPtrs a{};
+  a.b = h->g_b + v * V;
+  a.q = h->g_q + v * V;
+  a.c = h->g_c + v * V;
+  a.psi_in = h->g_psi + v * V;
+  a.gbar = h->g_gbar;
+  a.part = h->g_part;
+  a.out = h->g_gbar;
+  return a;
+}
+
+// Forward view-update v with its intermediates stored (b, q, c, the input
+// psi and the spectra of psi and q).
+void grad_forward_view(mvd_handle* h, int v) {
+  const Block& B = h->blocks[0];
+  hipStream_t s = h->stream;
+  const LaunchArgs ax = args(h, s, h->rt_grid[0]), ay = args(h, s, h->rt_grid[1]), az = args(h, s, h->rt_grid[2]);
+  const AdjPtrs ap = adj_ptrs(h, v);
+  Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, h->g_spsi + (size_t)v * B.spec_elems, nullptr, nullptr, 0));
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 3, v, parts, h->d_flags, ap));
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0));
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 4, v, parts, h->d_flags, ap));
+}
+
+// Adjoint of view-update v: g_gbar holds dL/dpsi' on entry and dL/dpsi on exit.
+void grad_adjoint_view(mvd_handle* h, int v) {
+  const Block& B = h->blocks[0];
+  hipStream_t s = h->stream;
+  const LaunchArgs ax = args(h, s, h->rt_grid[0]), ay = args(h, s, h->rt_grid[1]), az = args(h, s, h->rt_grid[2]);
+  const AdjPtrs ap = adj_ptrs(h, v);
+  double2* acc = h->g_acc + (size_t)v * B.spec_elems;
+  // cbar and the direct part of psibar
+  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 5, v, nullptr, h->d_flags, ap));
+  // qbar = cbar (x) P_v, with A_v += conj(Cbar) Q
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, nullptr, h->g_sq + (size_t)v * B.spec_elems, acc, 1));
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  // bbar
+  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 6, v, nullptr, h->d_flags, ap));
+  // bbar (x) P_v*, with A_v += Bbar conj(Psi)
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, nullptr, h->g_spsi + (size_t)v * B.spec_elems, acc, 0));
+  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
+}
+
+void x_init_rt(mvd_handle* h) {
+  HIPCHECK(mvd_launch_x(args(h, h->stream, h->rt_grid[0]), h->rt_cfg[0], 0, 0, nullptr, h->d_flags, 1));
+}
+
+void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
+                    double* const* grad_psf, float* grad_psi0, int grad_kind) {
+  if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
+  if (variant != MVD_RL) bad("gradients are available for MVD_RL");
+  if (n < 0) bad("n must be >= 0");
+  if (!loss) bad("loss is NULL");
+  if (grad_psi0 && grad_kind != MVD_MEM_HOST && grad_kind != MVD_MEM_DEVICE) bad("grad_kind must be host or device");
+  Block& B = h->blocks[0];
+  const int N = h->nviews;
+  const size_t V = B.V, S = B.spec_elems;
+  hipStream_t st = h->stream;
+  grad_setup(h, std::max(n, 1));
+  if (psi0) {
+    HIPCHECK(hipStreamSynchronize(st));
+    const int rc = mvd_set_estimate(h, psi0, psi0_kind, 0);
+    if (rc != MVD_OK) throw Error(rc, h->err);
+  } else {
+    HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, st));
+  }
+  HIPCHECK(mvd_launch_set_int(h->d_flags, 0, st));
+  const bool want_grad = grad_psf || grad_psi0;
+  // forward with one checkpoint per iteration
+  x_init_rt(h);
+  for (int i = 0; i < n; ++i) {
+    HIPCHECK(hipMemcpyAsync(h->g_ckpt + (size_t)i * V, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+    for (int v = 0; v < N; ++v) grad_forward_view(h, v);
+  }
+  HIPCHECK(hipMemcpyAsync(h->g_psiT, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed
+  HIPCHECK(hipMemsetAsync(h->g_gbar, 0, V * sizeof(float), st));
+  HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)N * S * sizeof(double2), st));
+  const LaunchArgs ax = args(h, st, h->rt_grid[0]), ay = args(h, st, h->rt_grid[1]), az = args(h, st, h->rt_grid[2]);
+  for (int v = 0; v < N; ++v) {
+    Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
+    AdjPtrs ap = adj_ptrs(h, v);
+    ap.part = h->g_gbar;
+    x_init_rt(h);
+    HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+    HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, h->g_sT, nullptr, nullptr, 0));
+    HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+    HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 8, v, parts, h->d_flags, ap));
+    if (want_grad) {
+      HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
+      HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, nullptr, h->g_sT, h->g_acc + (size_t)v * S, 0));
+      HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+      HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
+    }
+  }
+  HIPCHECK(mvd_launch_reduce(h->g_parts, h->rt_grid[0], N, h->g_loss, h->g_lr, h->g_ln, st));
+  std::vector<double> lv(N);
+  HIPCHECK(hipMemcpyAsync(lv.data(), h->g_loss, N * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (want_grad) {
+    // reverse sweep: recompute each iteration from its checkpoint, then the
+    // adjoints of its view-updates in reverse order
+    for (int i = n - 1; i >= 0; --i) {
+      HIPCHECK(hipMemcpyAsync(B.psi, h->g_ckpt + (size_t)i * V, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+      x_init_rt(h);
+      for (int v = 0; v < N; ++v) grad_forward_view(h, v);
+      for (int v = N - 1; v >= 0; --v) grad_adjoint_view(h, v);
+    }
+    if (grad_psi0)
+      HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
+                              grad_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    if (grad_psf) {
+      std::vector<mvdh::cd> A(S);
+      for (int v = 0; v < N; ++v) {
+        if (!grad_psf[v]) continue;
+        HIPCHECK(hipMemcpyAsync(A.data(), h->g_acc + (size_t)v * S, S * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        const mvdh::Kern& P = B.P[v];
+        std::vector<double> g((size_t)P.kx * P.ky * P.kz);
+        mvdh::window_idft_half(A.data(), A.data() + B.spec_main, B.nx, B.ny, B.nz, P.kx, P.ky, P.kz, g.data());
+        // through the normalisation P = G / sum G, then drop the odd padding
+        double dot = 0;
+        for (size_t j = 0; j < g.size(); ++j) dot += g[j] * P.a[j];
+        const auto& d = B.psf_dims[v];
+        for (int z = 0; z < d[2]; ++z)
+          for (int y = 0; y < d[1]; ++y)
+            for (int x = 0; x < d[0]; ++x)
+              grad_psf[v][((size_t)z * d[1] + y) * d[0] + x] =
+                  (g[((size_t)z * P.ky + y) * P.kx + x] - dot) / B.psf_sum[v];
+      }
+    }
+  }
+  // leave psi at the end of the run
+  HIPCHECK(hipMemcpyAsync(B.psi, h->g_psiT, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  double L = 0;
+  for (double x : lv) L += x;
+  *loss = L;
+  h->spec_valid = false;
+  h->iterations = n;
+  if (read_flag(h)) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
+}
+
+void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {
+  if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "mvd_set_psfs takes a single-block handle");
+  if (!psfs || !psf_dims) bad("psfs and psf_dims are required");
+  if (mem_kind != MVD_MEM_HOST && mem_kind != MVD_MEM_DEVICE) bad("mem_kind must be host or device");
+  Block& B = h->blocks[0];
+  const int N = h->nviews;
+  std::vector<mvdh::Kern> P;
+  std::vector<double> sums;
+  std::vector<std::array<int, 3>> dims;
+  for (int v = 0; v < N; ++v) {
+    if (!psfs[v]) bad("PSF pointer is NULL");
+    const int* k = psf_dims + 3 * v;
+    const int vd[3] = {B.nx, B.ny, B.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (k[a] < 1) bad("PSF extents must be >= 1");
+      if ((k[a] | 1) > vd[a]) bad("PSF (odd-padded) is larger than the volume");
+    }
+    const size_t n = (size_t)k[0] * k[1] * k[2];
+    std::vector<float> hp(n);
+    if (mem_kind == MVD_MEM_HOST)
+      std::memcpy(hp.data(), psfs[v], n * sizeof(float));
+    else
+      HIPCHECK(hipMemcpy(hp.data(), psfs[v], n * sizeof(float), hipMemcpyDeviceToHost));
+    try {
+      P.push_back(mvdh::prepare_psf(hp.data(), k[0], k[1], k[2]));
+    } catch (const std::invalid_argument& e) {
+      bad(std::string("PSF ") + std::to_string(v) + ": " + e.what());
+    }
+    double sum = 0;
+    for (float x : hp) sum += x;
+    sums.push_back(sum);
+    dims.push_back({k[0], k[1], k[2]});
+  }
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  B.P = std::move(P);
+  B.psf_sum = std::move(sums);
+  B.psf_dims = std::move(dims);
+  for (int v = 0; v < N; ++v) upload_spectrum(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.spec_elems * 2);
+  for (int r = 1; r < N_ROLES; ++r) h->built[r] = false;
 }
 
 int read_flag(mvd_handle* h) {
@@ -835,6 +1105,23 @@ int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls) {
     }
     h->iterations += n;
   });
+}
+
+int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
+                  double* const* grad_psf, float* grad_psi0, int grad_kind) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { loss_grad_impl(h, n, variant, psi0, psi0_kind, loss, grad_psf, grad_psi0, grad_kind); });
+}
+
+int mvd_set_psfs(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { set_psfs_impl(h, psfs, psf_dims, mem_kind); });
 }
 
 int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z) {

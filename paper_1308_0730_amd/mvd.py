@@ -69,6 +69,9 @@ def lib():
     L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
     L.mvd_view_update.argtypes = [H, C.c_int, C.c_int]
+    L.mvd_loss_grad.argtypes = [H, C.c_int, C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                C.POINTER(C.c_void_p), C.c_void_p, C.c_int]
+    L.mvd_set_psfs.argtypes = [H, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int]
     L.mvd_set_tiles.argtypes = [H, C.c_int, C.c_int, C.c_int]
     L.mvd_get_tiles.argtypes = [H, C.POINTER(C.c_int)]
     L.mvd_tile_candidates.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int]
@@ -86,7 +89,7 @@ def lib():
     for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_get_estimate", "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
-                 "mvd_tile_shape"):
+                 "mvd_tile_shape", "mvd_loss_grad", "mvd_set_psfs"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -193,6 +196,7 @@ class Deconvolver:
             self._h = None
             raise MVDError(rc, lib().mvd_last_error(None).decode())
         self._h = h
+        self._psf_shapes = [tuple(p.shape) for p in ms[0].psfs]
         self.dims = [m.dims for m in ms]
         self.n_views = len(ms[0].views)
         self.n_blocks = len(ms)
@@ -219,6 +223,42 @@ class Deconvolver:
         calls = (C.c_int * 5)()
         _check(lib().mvd_profile(self._h, int(n), _variant(variant), ms, calls), self._h)
         return {k: (ms[i], calls[i]) for i, k in enumerate(self.PASS_NAMES)}
+
+    def set_psfs(self, psfs):
+        """Replace the PSFs (host arrays); their spectra are recomputed."""
+        ps = [np.ascontiguousarray(np.asarray(p.detach().cpu() if isinstance(p, torch.Tensor) else p,
+                                              np.float32)) for p in psfs]
+        ptrs = (C.c_void_p * len(ps))(*[p.ctypes.data for p in ps])
+        dims = (C.c_int * (3 * len(ps)))(*sum([[p.shape[2], p.shape[1], p.shape[0]] for p in ps], []))
+        _check(lib().mvd_set_psfs(self._h, C.cast(ptrs, C.POINTER(C.c_void_p)), dims, MEM_HOST), self._h)
+        self._psf_shapes = [p.shape for p in ps]
+        return self
+
+    def loss_grad(self, n, psi0=None, grad_psf=True, grad_psi0=True, psf_shapes=None):
+        """Loss sum_v |psi_n (x) P_v - phi_v|^2 after n RL iterations from psi0
+        (None: flat start) and, optionally, its gradients: a list of float64
+        arrays shaped like the PSFs, and a CUDA tensor shaped like the volume.
+        Returns (loss, grad_psfs or None, grad_psi0 or None)."""
+        nx, ny, nz = self.dims[0]
+        src = None
+        if psi0 is not None:
+            src = psi0.detach().to(self.device, torch.float32).contiguous() if isinstance(psi0, torch.Tensor) \
+                else torch.from_numpy(np.ascontiguousarray(np.asarray(psi0, np.float32))).to(self.device)
+        loss = C.c_double()
+        shapes = psf_shapes or getattr(self, "_psf_shapes", None)
+        gps = None
+        gp_ptrs = None
+        if grad_psf:
+            if shapes is None:
+                raise ValueError("PSF shapes unknown: pass psf_shapes or call set_psfs first")
+            gps = [np.zeros(sh, np.float64) for sh in shapes]
+            gp_ptrs = (C.c_void_p * len(gps))(*[g.ctypes.data for g in gps])
+        gpsi = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if grad_psi0 else None
+        rc = lib().mvd_loss_grad(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
+                                 C.byref(loss), None if gp_ptrs is None else C.cast(gp_ptrs, C.POINTER(C.c_void_p)),
+                                 None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
+        _check(rc, self._h)
+        return loss.value, gps, gpsi
 
     def tiles(self):
         """Current launch-shape candidates (x, y, z)."""

@@ -1,0 +1,112 @@
+"""Differentiated form on the GPU: loss and gradients through the unrolled
+sequential RL run (hand-written adjoint passes) against the FP64 oracle
+gradient, and the PSF-parameter gradient against finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mvd_oracle as O
+from paper_1308_0730_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mvd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1308_0730_amd import mvd as m
+    return m
+
+
+def asym_psf(rng, shape, off):
+    kz, ky, kx = shape
+    z, y, x = np.meshgrid(np.arange(kz) - (kz - 1) / 2, np.arange(ky) - (ky - 1) / 2,
+                          np.arange(kx) - (kx - 1) / 2, indexing="ij")
+    g = np.exp(-0.5 * ((x - off[2]) ** 2 / 1.7 + (y - off[1]) ** 2 / 1.1 + (z - off[0]) ** 2 / 3.0))
+    g += 0.3 * np.exp(-0.5 * ((x + 1.5) ** 2 + (y - 1) ** 2 + (z + 2) ** 2) / 0.8)
+    return (g / g.sum() * 3.0).astype(np.float32)  # not normalised: the gradient includes eq. 3
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("weighted,lam", [(False, 0.0), (True, 0.02)])
+def test_gradient_matches_oracle(mvd, weighted, lam):
+    dims = (40, 36, 30)
+    s = synth.make_problem(dims, 8, [0.0, 70.0, 130.0], (5, 5, 7), 1.0, 2.0, 31)
+    rng = np.random.default_rng(5)
+    psfs = [asym_psf(rng, (9, 7, 7), off) for off in ((0.6, -0.4, 0.3), (-0.5, 0.5, 0.7), (0.3, 0.2, -0.6))]
+    w = [np.clip(rng.uniform(-0.2, 1.2, size=s.views[0].shape), 0, 1).astype(np.float32) for _ in range(3)] \
+        if weighted else None
+    psi0 = rng.uniform(5, 25, size=s.views[0].shape).astype(np.float32)
+    n = 3
+    L, gpsi, gP = O.loss_and_grad(s.views, psfs, n, psi0.astype(np.float64), w, lam)
+    with mvd.Deconvolver(s.views, psfs, w, lam=lam) as d:
+        l2, gp2, gpsi2 = d.loss_grad(n, psi0)
+        gpsi2 = gpsi2.cpu().numpy()
+    print(f"loss {l2:.8e} vs {L:.8e}; psi0 grad rel {rel(gpsi2, gpsi):.2e}; "
+          f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gp2, gP)]}")
+    assert abs(l2 - L) <= 1e-5 * L
+    assert rel(gpsi2, gpsi) <= 2e-4
+    for a, b in zip(gp2, gP):
+        assert rel(a, b) <= 2e-4
+
+
+def test_forward_only_loss(mvd):
+    dims = (40, 36, 30)
+    s = synth.make_problem(dims, 8, [0.0, 90.0], (5, 5, 7), 1.0, 2.0, 32)
+    with mvd.Deconvolver(s.views, s.psfs) as d:
+        l1, g1, g2 = d.loss_grad(4, None, grad_psf=False, grad_psi0=False)
+        assert g1 is None and g2 is None
+        pb = O.Problem(s.views, s.psfs)
+        ref = O.loss_value(pb.iterate(pb.psi0(), 4, O.RL), pb.views, pb.P)
+        assert abs(l1 - ref) <= 1e-5 * ref
+        # the handle is left at the end of the run
+        e = d.estimate().cpu().numpy()
+        assert O.rel_l2(e, pb.iterate(pb.psi0(), 4, O.RL)) <= 1e-4
+
+
+def test_config5_theta_gradient(mvd):
+    """128^3, four views, 25^3 PSFs from (sigma_xy, sigma_z) per view, start
+    perturbed by U[0.8, 1.2], 8 iterations: the library's PSF-parameter
+    gradient against central finite differences (step 1e-3) of the library's
+    own loss, and its PSF gradient against the FP64 oracle gradient."""
+    from paper_1308_0730_amd.autograd import loss_and_theta_grad, psf_from_theta
+    s = synth.config5()
+    true, start = synth.config5_theta()
+    psi0 = np.full(s.views[0].shape, float(np.mean([v.mean() for v in s.views])), np.float32)
+    ext = (25, 25, 25)
+    with mvd.Deconvolver(s.views, s.psfs) as d:
+        L, g = loss_and_theta_grad(d, 8, torch.from_numpy(psi0).cuda(), start, s.angles, ext)
+
+        def loss_at(th):
+            ps = [psf_from_theta(torch.tensor(th[v, 0]), torch.tensor(th[v, 1]), s.angles[v], ext).numpy()
+                  for v in range(4)]
+            d.set_psfs(ps)
+            return d.loss_grad(8, psi0, grad_psf=False, grad_psi0=False)[0]
+
+        h = 1e-3
+        fd = np.zeros_like(g)
+        for v in range(4):
+            for k in range(2):
+                tp, tm = start.copy(), start.copy()
+                tp[v, k] += h
+                tm[v, k] -= h
+                fd[v, k] = (loss_at(tp) - loss_at(tm)) / (2 * h)
+        print("theta grad", g.ravel(), "fd", fd.ravel())
+        assert rel(g, fd) <= 5e-3
+        # PSF and psi0 gradients against the FP64 oracle at the start point
+        ps = [psf_from_theta(torch.tensor(start[v, 0]), torch.tensor(start[v, 1]), s.angles[v], ext).numpy()
+              for v in range(4)]
+        d.set_psfs(ps)
+        L2, gP2, gpsi2 = d.loss_grad(8, psi0)
+        gpsi2 = gpsi2.cpu().numpy()
+    Lo, gpsio, gPo = O.loss_and_grad(s.views, ps, 8, psi0.astype(np.float64))
+    print(f"loss {L2:.8e} vs {Lo:.8e}; psi0 grad rel {rel(gpsi2, gpsio):.2e}; "
+          f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gP2, gPo)]}")
+    assert abs(L - Lo) <= 1e-4 * Lo and abs(L2 - Lo) <= 1e-4 * Lo
+    assert rel(gpsi2, gpsio) <= 1e-3
+    for a, b in zip(gP2, gPo):
+        assert rel(a, b) <= 1e-3
