@@ -169,6 +169,38 @@ def batched_form(steps, warmup):
             "batched_speedup": round(ms_p / ms_b, 3)}
 
 
+def grad_form(steps, warmup):
+    """The differentiated workload (128^3, four views, 25^3 PSFs, 8 RL
+    iterations): forward (iterations + loss) against forward + backward
+    (checkpointed recompute and adjoint passes, PSF and psi0 gradients)."""
+    import torch
+    from paper_1308_0730_amd import mvd
+    s = synth_config5()
+    its = 8
+    vox = int(np.prod(s.dims)) * len(s.views) * its
+    d = mvd.Deconvolver(s.views, s.psfs)
+    res = {}
+    for name, grads in (("forward", False), ("forward_backward", True)):
+        for _ in range(warmup):
+            d.loss_grad(its, None, grad_psf=grads, grad_psi0=grads)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            loss, _, _ = d.loss_grad(its, None, grad_psf=grads, grad_psi0=grads)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3), "unit": "Gvox/s",
+                     "loss": loss}
+    d.close()
+    res["backward_over_forward"] = round(res["forward_backward"]["ms_per_step"] / res["forward"]["ms_per_step"], 3)
+    res["workload"] = "128^3, 4 views, 25^3 PSFs, 8 RL iterations, loss sum_v |psi_8 (x) P_v - phi_v|^2"
+    res["note"] = "host wall clock per call (each call synchronises; PSF gradients finish on the host in FP64)"
+    return res
+
+
+def synth_config5():
+    from paper_1308_0730_amd import synth
+    return synth.config5()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,8 +212,9 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
-    ap.add_argument("--forms", action="store_true",
-                    help="also measure the batched form (48 blocks) against looping the plain form")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched (48 blocks, against the plain form looped over them) and the "
+                         "differentiated (forward against forward + backward) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -268,8 +301,8 @@ def main():
         cpu = cpu_baseline(blocks, meta, args.cpu_budget)
 
     forms = None
-    if args.forms:
-        forms = {"batched": batched_form(max(1, args.steps // 2), 1)}
+    if not args.no_forms:
+        forms = {"batched": batched_form(max(1, args.steps // 2), 1), "grad": grad_form(3, 1)}
 
     dims = [list(b.dims) for b in blocks]
     out = {
