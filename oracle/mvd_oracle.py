@@ -351,3 +351,35 @@ def loss_of(views, psfs, n_iter, psi0, weights=None, lam=0.0):
     pb = Problem(views, psfs, weights, lam)
     psi = pb.iterate(np.asarray(psi0, dtype=np.float64), n_iter, RL)
     return loss_value(psi, pb.views, pb.P)
+
+
+# ------------------------------------------------- sampled view-update --------
+
+def _periodic_box(f, center, half):
+    """f on the box center +- half (per axis, periodic)."""
+    idx = [(np.arange(c - h, c + h + 1)) % n for c, h, n in zip(center, half, f.shape)]
+    return f[np.ix_(*idx)]
+
+
+def view_update_at(psi, phi, P, K, points, w=None, lam_p=0.0, eps=0.0):
+    """The result of view_update at the given voxels (z, y, x), each computed
+    on its own from the windows it depends on: c at x needs q on K's window
+    around x, which needs b = psi (x) P on that window, which needs psi on a
+    box of both windows.  Same arithmetic as view_update, evaluated locally
+    (for volumes too large for the whole-volume oracle)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    hk = [(n - 1) // 2 for n in K.shape]
+    hp = [(n - 1) // 2 for n in P.shape]
+    out = []
+    for pt in points:
+        box = _periodic_box(psi, pt, [a + b for a, b in zip(hk, hp)])
+        # b on K's window around pt: valid convolution of the box with P
+        b = signal.fftconvolve(box, P, mode="valid")
+        q = _periodic_box(np.asarray(phi, dtype=np.float64), pt, hk) / np.maximum(b, eps)
+        # c(pt) = sum_d K[c + d] q(pt - d): q's window is indexed pt + e, so K flips
+        c = float(np.sum(K[::-1, ::-1, ::-1] * q))
+        p0 = float(psi[tuple(pt)])
+        u = p0 * max(c, 0.0)
+        t = float(tikhonov(np.array(u), lam_p))
+        out.append(t if w is None else p0 + float(w[tuple(pt)]) * (t - p0))
+    return np.array(out)

@@ -281,3 +281,20 @@ def test_weights_zero_and_one():
     pb1 = O.Problem(views, psfs, [np.ones(shape)] * 2, lam=0.01)
     pbn = O.Problem(views, psfs, None, lam=0.01)
     np.testing.assert_allclose(pb1.iterate(pb1.psi0(), 2, O.EFF), pbn.iterate(pbn.psi0(), 2, O.EFF), rtol=1e-13)
+
+
+def test_sampled_view_update_equals_whole_volume_update():
+    """The local (windowed) evaluation used at full size equals the
+    whole-volume update at every sampled voxel, including voxels whose
+    windows wrap around the periodic boundary."""
+    rng = np.random.default_rng(14)
+    shape = (10, 12, 14)
+    P = O.prepare_psf(rand_kernel(rng, (3, 5, 3), offset=(0.4, -0.3, 0.2)))
+    K = O.normalize(rand_kernel(rng, (5, 3, 3), offset=(-0.2, 0.3, 0.5)))
+    psi = rand_volume(rng, shape, 1, 20)
+    phi = rng.poisson(8.0, size=shape).astype(float) + 0.5
+    w = rng.uniform(0, 1, size=shape)
+    full = O.view_update(psi, phi, P, K, w, 0.03, 1e-3)
+    pts = [(0, 0, 0), (9, 11, 13), (5, 6, 7), (1, 10, 2), (8, 0, 12)]
+    got = O.view_update_at(psi, phi, P, K, pts, w, 0.03, 1e-3)
+    np.testing.assert_allclose(got, [full[p] for p in pts], rtol=1e-12)
