@@ -310,6 +310,40 @@ __global__ void __launch_bounds__(T)
   fft_lines<true, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, S, S, g);
 }
 
+// z stage of the windowed inverse DFT of a PSF cross-spectrum (FP64):
+// T1[dz][ky][kx] = sum_kz A[kz][ky][kx] exp(+2 pi i kz (dz - cz) / nz) for kx
+// in [0, M] (the main part and the Nyquist plane), dz in the window.
+__global__ void __launch_bounds__(256)
+    k_idft_z(const double2* __restrict__ A, int M, int ny, int nz, int wz, const double2* __restrict__ twz,
+             double2* __restrict__ T1) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)(M + 1) * ny * wz;
+  if (idx >= total) return;
+  const int kx = (int)(idx % (M + 1));
+  const int64_t rest = idx / (M + 1);
+  const int ky = (int)(rest % ny);
+  const int dz = (int)(rest / ny);
+  const int d = dz - (wz - 1) / 2;
+  const int64_t main_elems = (int64_t)M * ny * nz;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double2 a = kx < M ? A[((int64_t)k * ny + ky) * M + kx] : A[main_elems + (int64_t)k * ny + ky];
+    int64_t m = ((int64_t)k * d) % nz;
+    if (m < 0) m += nz;
+    const double2 w = twz[m];  // exp(-2 pi i m / nz); conjugated below
+    sr += a.x * w.x + a.y * w.y;
+    si += a.y * w.x - a.x * w.y;
+  }
+  T1[idx] = make_double2(sr, si);
+}
+
+hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
+                             hipStream_t s) {
+  const int64_t total = (int64_t)(M + 1) * ny * wz;
+  k_idft_z<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(A, M, ny, nz, wz, twz, T1);
+  return hipGetLastError();
+}
+
 // Launch wrappers over the runtime-plan launch shapes (same candidates as
 // the forward passes).
 #define MVD_ADJ_ROW_CFGS(X) \

@@ -58,3 +58,5 @@ hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partia
                            const AdjPtrs& ap);
 hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int conjH, float2* s_out,
                            const float2* s_in, double2* acc, int acc_mode);
+hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
+                             hipStream_t s);

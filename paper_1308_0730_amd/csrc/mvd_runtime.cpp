@@ -102,6 +102,9 @@ struct mvd_handle {
   float *g_gbar = nullptr, *g_part = nullptr, *g_psiT = nullptr;
   Partial* g_parts = nullptr;              // [view][x tiles]
   double* g_loss = nullptr;
+  double2* g_twz = nullptr;                // exp(-2 pi i m / nz), FP64
+  double2* g_t1 = nullptr;                 // z stage of the PSF-gradient inverse DFT
+  size_t g_t1_cap = 0;
   unsigned long long *g_lr = nullptr, *g_ln = nullptr;
   std::string err;
 
@@ -825,14 +828,31 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
       HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
                               grad_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
     if (grad_psf) {
-      std::vector<mvdh::cd> A(S);
+      // z stage of the windowed inverse DFT on the device (FP64), y and x on the host
+      if (!h->g_twz) {
+        const auto tz = mvdh::twiddles(B.nz);
+        h->g_twz = (double2*)h->dalloc(tz.size() * sizeof(double2));
+        HIPCHECK(hipMemcpyAsync(h->g_twz, tz.data(), tz.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      }
+      int wzmax = 0;
+      for (int v = 0; v < N; ++v) wzmax = std::max(wzmax, B.P[v].kz);
+      const size_t t1n = (size_t)(B.M + 1) * B.ny * wzmax;
+      if (t1n > h->g_t1_cap) {
+        h->g_t1 = (double2*)h->dalloc(t1n * sizeof(double2));
+        h->g_t1_cap = t1n;
+      }
+      std::vector<mvdh::cd> T1(t1n);
+      const double invV = 1.0 / (double)B.V;
       for (int v = 0; v < N; ++v) {
         if (!grad_psf[v]) continue;
-        HIPCHECK(hipMemcpyAsync(A.data(), h->g_acc + (size_t)v * S, S * sizeof(double2), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
         const mvdh::Kern& P = B.P[v];
+        HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
+        const size_t n1 = (size_t)(B.M + 1) * B.ny * P.kz;
+        HIPCHECK(hipMemcpyAsync(T1.data(), h->g_t1, n1 * sizeof(double2), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
         std::vector<double> g((size_t)P.kx * P.ky * P.kz);
-        mvdh::window_idft_half(A.data(), A.data() + B.spec_main, B.nx, B.ny, B.nz, P.kx, P.ky, P.kz, g.data());
+        mvdh::window_idft_yx(T1.data(), B.nx, B.ny, P.kx, P.ky, P.kz, g.data());
+        for (double& x : g) x *= invV;
         // through the normalisation P = G / sum G, then drop the odd padding
         double dot = 0;
         for (size_t j = 0; j < g.size(); ++j) dot += g[j] * P.a[j];
