@@ -64,9 +64,12 @@ def pass_bytes(blocks, weighted):
         nx, ny, nz = b.dims
         V = nx * ny * nz
         S = ((nx // 2) * ny * nz + ny * nz) * 8.0  # half spectrum, complex float32
+        # kernel planes: x/y-stage spectrum on the common odd z window
+        kz = max(p.shape[0] | 1 for p in b.psfs)
+        Hk = ((nx // 2) * ny * kz + ny * kz) * 8.0
         out["y_forward"] += 2 * S
         out["y_inverse"] += 2 * S
-        out["z_product"] += 3 * S
+        out["z_product"] += 2 * S + Hk
         out["x_ratio"] += 2 * S + 4 * V
         out["x_update"] += 2 * S + (12 if weighted else 8) * V
     return out

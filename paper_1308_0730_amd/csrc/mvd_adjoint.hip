@@ -252,34 +252,40 @@ __global__ void __launch_bounds__(T)
   const JobDesc& J = jobs[jid];
   const int M = J.M, ny = J.ny, nz = J.nz;
   const int nxt = mvd_cdiv(M, TX);
-  int64_t off;
+  int64_t off, hoff;
   int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
     off = (int64_t)y * M + xt * TX;
+    hoff = off;
     ps = ny * M;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
     off = J.spec_main + (int64_t)t2 * TX;
+    hoff = J.h_main + (int64_t)t2 * TX;
     ps = ny;
     nl = min(TX, ny - t2 * TX);
   }
-  const float2* H = reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.spec_elems + off;
+  const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, nz,
+                 J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
   constexpr int EPT = (TX * MAXL + T - 1) / T;
   const int tid = threadIdx.x;
+  const FftPlan* pl = plans + J.plan_z;
+  load_table<T>(s_tw, twp + pl->tw, nz);
+  const LdsCol<TX> S{lds};
+  if (pl->nst == 1) __syncthreads();
+  // kernel spectrum of the tile's lines, kept in registers
+  fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, kl, S, S);
   float2 h[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * T;
     const int line = e % TX, pos = e / TX;
-    h[i] = (pos < nz && line < nl) ? H[line + pos * ps] : make_float2(0.f, 0.f);
+    h[i] = pos < nz ? S.ld(line, pos) : make_float2(0.f, 0.f);
   }
-  const FftPlan* pl = plans + J.plan_z;
-  load_table<T>(s_tw, twp + pl->tw, nz);
-  const LdsCol<TX> S{lds};
-  if (pl->nst == 1) __syncthreads();
+  __syncthreads();
   fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, g, S, S);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {

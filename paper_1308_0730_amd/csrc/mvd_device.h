@@ -23,6 +23,20 @@ __device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int nj
   return -1;
 }
 
+// Source accessor of the kernel lines of a z tile: tap d of the stored
+// kernel planes sits at position (d - cz) mod nz of a length-nz line, every
+// other position is zero.  base points at tap 0 of line 0; taps are ps apart.
+struct KLine {
+  const float2* base;
+  int ps, nl, nz, kz, cz;
+  static constexpr bool lds = false;
+  __device__ __forceinline__ float2 ld(int line, int pos) const {
+    int d = pos + cz;
+    if (d >= nz) d -= nz;
+    return (line < nl && d < kz) ? base[line + d * ps] : make_float2(0.f, 0.f);
+  }
+};
+
 // Workgroup sum of an FP64 value and two counters; the result is valid in
 // thread 0.
 template <int T>

@@ -49,9 +49,6 @@ hipError_t mvd_launch_check(const float* x, int64_t n, float lo, float hi, doubl
                             unsigned long long* pbad, int nblocks, hipStream_t s);
 hipError_t mvd_launch_fill(float* x, int64_t n, float val, hipStream_t s);
 hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s);
-hipError_t mvd_launch_spec_z(const double* A2, int kz, int cz, int M, int ny, int nz,
-                             const double* twz, double invV, float* main_out, float* nyq_out,
-                             hipStream_t s);
 
 // differentiated form (mvd_adjoint.hip); cfg indexes the runtime-plan shapes
 hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,

@@ -265,9 +265,10 @@ __global__ void __launch_bounds__(T)
 }
 
 // ---------------------------------------------------------------------------
-// z pass with the spectral product: forward z transform, multiply by the
-// kernel spectrum of view v (conjugated for the mirrored kernel P_v*), inverse
-// z transform, all while the tile stays in LDS.
+// z pass with the spectral product: forward z transform of the kernel lines
+// of view v (their x/y-stage planes placed on the length-nz line), forward z
+// transform of the data, multiply (by the conjugate for the mirrored kernel
+// P_v*), inverse z transform, all while the tile stays in LDS.
 template <int T, int TX, int MAXL>
 __global__ void __launch_bounds__(T)
     k_zconv(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
@@ -281,34 +282,40 @@ __global__ void __launch_bounds__(T)
   if (v >= J.nviews) return;
   const int M = J.M, ny = J.ny, nz = J.nz;
   const int nxt = mvd_cdiv(M, TX);
-  int64_t off;
+  int64_t off, hoff;
   int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
     off = (int64_t)y * M + xt * TX;
+    hoff = off;
     ps = ny * M;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
     off = J.spec_main + (int64_t)t2 * TX;
+    hoff = J.h_main + (int64_t)t2 * TX;
     ps = ny;
     nl = min(TX, ny - t2 * TX);
   }
-  const float2* H = reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.spec_elems + off;
+  const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, nz,
+                 J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
   constexpr int EPT = (TX * MAXL + T - 1) / T;
   const int tid = threadIdx.x;
+  const FftPlan* pl = plans + J.plan_z;
+  load_table<T>(s_tw, twp + pl->tw, nz);
+  const LdsCol<TX> S{lds};
+  if (pl->nst == 1) __syncthreads();
+  // kernel spectrum of the tile's lines, kept in registers
+  fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, kl, S, S);
   float2 h[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * T;
     const int line = e % TX, pos = e / TX;
-    h[i] = (pos < nz && line < nl) ? H[line + pos * ps] : make_float2(0.f, 0.f);
+    h[i] = pos < nz ? S.ld(line, pos) : make_float2(0.f, 0.f);
   }
-  const FftPlan* pl = plans + J.plan_z;
-  load_table<T>(s_tw, twp + pl->tw, nz);
-  const LdsCol<TX> S{lds};
-  if (pl->nst == 1) __syncthreads();
+  __syncthreads();
   fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, g, S, S);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -394,35 +401,6 @@ __global__ void __launch_bounds__(256) k_fill(float* __restrict__ x, int64_t n, 
 
 __global__ void k_set_int(int* __restrict__ p, int val) {
   if (threadIdx.x == 0) *p = val;
-}
-
-// Last stage of the kernel-spectrum build, in FP64: for every (kx, ky) the
-// z sum over the kernel's support, scaled by 1/V and rounded once to FP32.
-__global__ void __launch_bounds__(256)
-    k_spec_z(const double2* __restrict__ A2, int kz, int cz, int M, int ny, int nz,
-             const double2* __restrict__ twz, double invV, float2* __restrict__ main_out,
-             float2* __restrict__ nyq_out) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)(M + 1) * ny * nz;
-  if (idx >= total) return;
-  const int kx = (int)(idx % (M + 1));
-  const int64_t rest = idx / (M + 1);
-  const int ky = (int)(rest % ny);
-  const int kzp = (int)(rest / ny);
-  double sr = 0.0, si = 0.0;
-  for (int dz = 0; dz < kz; ++dz) {
-    const double2 a = A2[((int64_t)dz * ny + ky) * (M + 1) + kx];
-    int64_t m = ((int64_t)kzp * (dz - cz)) % nz;
-    if (m < 0) m += nz;
-    const double2 w = twz[m];
-    sr += a.x * w.x - a.y * w.y;
-    si += a.x * w.y + a.y * w.x;
-  }
-  const float2 o = make_float2((float)(sr * invV), (float)(si * invV));
-  if (kx < M)
-    main_out[((int64_t)kzp * ny + ky) * M + kx] = o;
-  else
-    nyq_out[(int64_t)kzp * ny + ky] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -560,14 +538,3 @@ hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mvd_launch_spec_z(const double* A2, int kz, int cz, int M, int ny, int nz,
-                             const double* twz, double invV, float* main_out, float* nyq_out,
-                             hipStream_t s) {
-  const int64_t total = (int64_t)(M + 1) * ny * nz;
-  const int64_t nb = (total + 255) / 256;
-  k_spec_z<<<(unsigned)nb, 256, 0, s>>>(reinterpret_cast<const double2*>(A2), kz, cz, M, ny, nz,
-                                         reinterpret_cast<const double2*>(twz), invV,
-                                         reinterpret_cast<float2*>(main_out),
-                                         reinterpret_cast<float2*>(nyq_out));
-  return hipGetLastError();
-}

@@ -46,6 +46,15 @@ struct MulH {
   }
 };
 
+// Last forward z stage of the kernel lines: keep the outputs in registers,
+// in the order the data's last forward stage produces its own.
+template <int MAXB, int R>
+struct ToRegs {
+  float2 (&h)[MAXB][R];
+  static constexpr bool lds = false;
+  __device__ __forceinline__ void st(int, int, float2 v, int i, int r) { h[i][r] = v; }
+};
+
 // Last inverse x stage: the pointwise step of the ratio (MODE 1) or of the
 // update (MODE 2) on the two real values held by each complex output; the
 // packed result goes to LDS as the input of the forward transform.
@@ -141,33 +150,32 @@ __global__ void __launch_bounds__(T)
   if (v >= J.nviews) return;
   const int M = J.M, ny = J.ny;
   const int nxt = mvd_cdiv(M, TX);
-  int64_t off;
+  int64_t off, hoff;
   int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
     off = (int64_t)y * M + xt * TX;
+    hoff = off;
     ps = ny * M;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
     off = J.spec_main + (int64_t)t2 * TX;
+    hoff = J.h_main + (int64_t)t2 * TX;
     ps = ny;
     nl = min(TX, ny - t2 * TX);
   }
-  const float2* H = reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.spec_elems + off;
+  const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, L,
+                 J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
-  // kernel spectrum in the order the last forward stage produces its outputs
-  float2 h[LM::MAXB][RL];
-#pragma unroll
-  for (int i = 0; i < LM::MAXB; ++i) {
-    int line, j;
-    const bool ok = LM::at(threadIdx.x, i, line, j);
-#pragma unroll
-    for (int r = 0; r < RL; ++r)
-      h[i][r] = (ok && line < nl) ? H[line + (j + r * LM::NB) * ps] : make_float2(0.f, 0.f);
-  }
   load_table<T>(s_tw, twp + plans[J.plan_z].tw, L);
   const LdsCol<TX> S{lds};
+  // kernel spectrum of the tile's lines, in the order the last forward stage
+  // produces its outputs
+  float2 h[LM::MAXB][RL];
+  ToRegs<LM::MAXB, RL> kreg{h};
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, kl, S, kreg);
+  __syncthreads();
   MulH<TX, LM::MAXB, RL> mul{lds, h, conjH};
   CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, g, S, mul);
   Plain<GTile> out{g};

@@ -41,6 +41,10 @@ struct Error : std::runtime_error {
 struct Block {
   int nx = 0, ny = 0, nz = 0, M = 0;
   int64_t V = 0, spec_main = 0, spec_elems = 0;
+  // common z window of the stored kernel planes (odd, centred) and the
+  // per-view size of a kernel-plane array; kz_cap is the allocated window
+  int kz = 0, cz = 0, kz_cap = 0;
+  int64_t h_main = 0, h_elems = 0;
   float* psi = nullptr;
   float* spec = nullptr;
   float* phi = nullptr;
@@ -251,32 +255,38 @@ int plan_for(mvd_handle* h, int L, std::vector<FftPlan>& plans, std::vector<floa
   return (int)plans.size() - 1;
 }
 
-// Spectrum of a centred kernel into the stored layout (main part then the
-// Nyquist plane), scaled by 1/V: x and y stages on the host, z on the device.
-void upload_spectrum(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* dst) {
-  const auto A2 = mvdh::spectrum_xy(K, B.nx, B.ny);
-  const auto tz = mvdh::twiddles(B.nz);
-  double* dA = nullptr;
-  double* dT = nullptr;
-  HIPCHECK(hipMalloc(&dA, A2.size() * sizeof(mvdh::cd)));
-  hipError_t e = hipMalloc(&dT, tz.size() * sizeof(mvdh::cd));
-  if (e != hipSuccess) {
-    (void)hipFree(dA);
-    HIPCHECK(e);
-  }
-  try {
-    HIPCHECK(hipMemcpyAsync(dA, A2.data(), A2.size() * sizeof(mvdh::cd), hipMemcpyHostToDevice, h->stream));
-    HIPCHECK(hipMemcpyAsync(dT, tz.data(), tz.size() * sizeof(mvdh::cd), hipMemcpyHostToDevice, h->stream));
-    HIPCHECK(mvd_launch_spec_z(dA, K.kz, (K.kz - 1) / 2, B.M, B.ny, B.nz, dT, 1.0 / (double)B.V, dst,
-                               dst + 2 * B.spec_main, h->stream));
-    HIPCHECK(hipStreamSynchronize(h->stream));
-  } catch (...) {
-    (void)hipFree(dA);
-    (void)hipFree(dT);
-    throw;
-  }
-  (void)hipFree(dA);
-  (void)hipFree(dT);
+// Common z window of a block's kernels: the largest z extent of its
+// prepared PSFs (every compound kernel lives in its PSF's window).
+void set_kernel_window(Block& B) {
+  int kz = 1;
+  for (const auto& K : B.P) kz = std::max(kz, K.kz);
+  B.kz = kz;
+  B.cz = (kz - 1) / 2;
+  B.h_main = (int64_t)B.M * B.ny * kz;
+  B.h_elems = B.h_main + (int64_t)B.ny * kz;
+}
+
+// Kernel planes of a centred kernel in the stored layout: the x and y
+// stages of its spectrum (FP64 on the host) on the block's z window, the
+// kernel's own planes centred in it, scaled by 1/V and rounded once to
+// FP32.  The z stage is done by the z pass.
+void upload_kernel(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* dst) {
+  if (K.kz > B.kz || (B.kz - K.kz) % 2) bad("kernel does not fit the z window");
+  const auto A2 = mvdh::spectrum_xy(K, B.nx, B.ny);  // [K.kz][ny][M + 1]
+  const int M = B.M, ny = B.ny, d0 = (B.kz - K.kz) / 2;
+  const double inv = 1.0 / (double)B.V;
+  std::vector<float> hk((size_t)B.h_elems * 2, 0.f);
+  for (int dz = 0; dz < K.kz; ++dz)
+    for (int ky = 0; ky < ny; ++ky)
+      for (int kx = 0; kx <= M; ++kx) {
+        const mvdh::cd a = A2[((size_t)dz * ny + ky) * (M + 1) + kx] * inv;
+        const size_t d = (size_t)(dz + d0);
+        const size_t o = kx < M ? (d * ny + ky) * M + kx : (size_t)B.h_main + d * ny + ky;
+        hk[2 * o] = (float)a.real();
+        hk[2 * o + 1] = (float)a.imag();
+      }
+  HIPCHECK(hipMemcpyAsync(dst, hk.data(), hk.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
 }
 
 bool cfg_fits(const mvd_handle* h, int kind, int c);
@@ -327,6 +337,10 @@ void build_jobs(mvd_handle* h) {
     j.V = B.V;
     j.spec_main = B.spec_main;
     j.spec_elems = B.spec_elems;
+    j.h_main = B.h_main;
+    j.h_elems = B.h_elems;
+    j.kz = B.kz;
+    j.cz = B.cz;
     j.psi = B.psi;
     j.spec = B.spec;
     j.phi = B.phi;
@@ -436,7 +450,6 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
     B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
     if (p.weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
-    B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.spec_elems * 2 * sizeof(float));
     const hipMemcpyKind kind = p.mem_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     for (int v = 0; v < N; ++v) {
       HIPCHECK(hipMemcpyAsync(B.phi + (size_t)v * B.V, p.views[v], B.V * sizeof(float), kind, h->stream));
@@ -491,7 +504,10 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
         B.psf_sum.push_back(sum);
       }
     }
-    for (int v = 0; v < N; ++v) upload_spectrum(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.spec_elems * 2);
+    set_kernel_window(B);
+    B.kz_cap = B.kz;
+    B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.h_elems * 2 * sizeof(float));
+    for (int v = 0; v < N; ++v) upload_kernel(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.h_elems * 2);
     plan_for(h, B.M, plans, tw);
     plan_for(h, B.ny, plans, tw);
     plan_for(h, B.nz, plans, tw);
@@ -543,10 +559,10 @@ void ensure_role(mvd_handle* h, int role) {
   if (h->built[role]) return;
   const int variant = role;  // ROLE_EFF == MVD_EFF etc.
   for (auto& B : h->blocks) {
-    if (!B.H[role]) B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.spec_elems * 2 * sizeof(float));
+    if (!B.H[role]) B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.h_elems * 2 * sizeof(float));
     for (int v = 0; v < h->nviews; ++v) {
       const mvdh::Kern K = mvdh::compound_kernel(B.P, v, variant);
-      upload_spectrum(h, B, K, B.H[role] + (size_t)v * B.spec_elems * 2);
+      upload_kernel(h, B, K, B.H[role] + (size_t)v * B.h_elems * 2);
     }
   }
   build_jobs(h);
@@ -913,8 +929,17 @@ void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims,
   B.P = std::move(P);
   B.psf_sum = std::move(sums);
   B.psf_dims = std::move(dims);
-  for (int v = 0; v < N; ++v) upload_spectrum(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.spec_elems * 2);
+  set_kernel_window(B);
+  if (B.kz > B.kz_cap) {
+    // a wider window: fresh kernel-plane arrays (the old ones are released
+    // with the handle); the compound kernels are rebuilt on next use
+    B.kz_cap = B.kz;
+    for (int r = 0; r < N_ROLES; ++r) B.H[r] = nullptr;
+    B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.h_elems * 2 * sizeof(float));
+  }
+  for (int v = 0; v < N; ++v) upload_kernel(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.h_elems * 2);
   for (int r = 1; r < N_ROLES; ++r) h->built[r] = false;
+  build_jobs(h);
 }
 
 int read_flag(mvd_handle* h) {

@@ -29,6 +29,13 @@ enum { ROLE_P = 0, ROLE_EFF = 1, ROLE_OPT1 = 2, ROLE_OPT2 = 3, N_ROLES = 4 };
 // Volumes are [z][y][x] float32; the half spectrum is kept as a main part
 // [z][y][kx < M] (M = nx/2 complex per row) followed by the kx = M
 // (Nyquist) plane [z][y], complex float32 interleaved.
+//
+// Kernels are stored as their x and y transform stages only, at the kz
+// planes of a common centred window (kz odd, centre cz = (kz - 1) / 2): the
+// same layout as a half spectrum with nz replaced by kz (main part
+// [d][ky][kx < M], then [d][ky] for kx = M), scaled by 1/V.  The z pass
+// places tap d at circular offset d - cz of each length-nz line and
+// transforms it next to the data.
 struct JobDesc {
   int nx, ny, nz, M;
   int nviews;
@@ -38,13 +45,15 @@ struct JobDesc {
   int64_t V;
   int64_t spec_main;           // M * ny * nz
   int64_t spec_elems;          // spec_main + ny * nz
+  int64_t h_main;              // M * ny * kz: start of a kernel's kx = M taps
+  int64_t h_elems;             // h_main + ny * kz: complex entries per view of H[role]
   float* psi;
   float* spec;                 // complex interleaved, spec_elems entries
   const float* phi;            // [nviews][V]
   const float* w;              // [nviews][V] or nullptr
-  const float* H[N_ROLES];     // [nviews][spec_elems] complex, scaled by 1/V; nullptr if not built
+  const float* H[N_ROLES];     // [nviews][h_elems] complex kernel planes; nullptr if not built
   float eps, lamp;
-  int pad1, pad2;
+  int kz, cz;                  // kernel window along z and its centre
 };
 
 // Per-workgroup partial results of the x passes (one entry per x tile).
