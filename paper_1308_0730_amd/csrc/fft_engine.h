@@ -20,6 +20,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "mvd_gmem.h"
 #include "mvd_types.h"
 
 namespace mvdk {
@@ -154,10 +155,10 @@ struct GTile {
   int nl;
   static constexpr bool lds = false;
   __device__ __forceinline__ float2 ld(int line, int pos) const {
-    return line < nl ? base[line * ls + pos * ps] : make_float2(0.f, 0.f);
+    return line < nl ? ldg(base + line * ls + pos * ps) : make_float2(0.f, 0.f);
   }
   __device__ __forceinline__ void st(int line, int pos, float2 v) const {
-    if (line < nl) base[line * ls + pos * ps] = v;
+    if (line < nl) stg(base + line * ls + pos * ps, v);
   }
 };
 
@@ -293,7 +294,7 @@ __device__ __forceinline__ void fft_lines(const FftPlan* __restrict__ pl, const 
 // a workgroup barrier.
 template <int T>
 __device__ __forceinline__ void load_table(float2* dst, const float2* __restrict__ src, int n) {
-  for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
+  for (int i = threadIdx.x; i < n; i += T) dst[i] = gp(src)[i];
 }
 
 }  // namespace mvdk

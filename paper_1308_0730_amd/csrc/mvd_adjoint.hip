@@ -52,8 +52,8 @@ __global__ void __launch_bounds__(64 * WPB)
   load_table<T>(s_pp, twp + J.pp, M);
   const int wrow0 = local * RW + wave * RPW;
   const int nrw = max(0, min(RPW, J.ny * J.nz - wrow0));
-  float2* spec = reinterpret_cast<float2*>(J.spec);
-  float2* nyq = spec + J.spec_main;
+  const auto spec = gp(reinterpret_cast<float2*>(J.spec));
+  const auto nyq = spec + J.spec_main;
   const LdsRow<MAXM> L{lds + wave * RPW * MAXM};
   const int npair = M / 2 + 1;
   const unsigned mM = mvd_magic(M), mP = mvd_magic(npair);
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(64 * WPB)
   const float eps = J.eps, lamp = J.lamp;
   const float* wv = J.w ? J.w + vo : nullptr;
 
-  auto f2 = [](const float* p, int64_t g) { return *reinterpret_cast<const float2*>(p + g); };
+  auto f2 = [](const float* p, int64_t g) { return ld2(p + g); };
   float2 pa[EPT], pb[EPT], pc[EPT], pd[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -145,17 +145,17 @@ __global__ void __launch_bounds__(64 * WPB)
       if (MODE == 3) {
         ncr += (z.x < eps) + (z.y < eps);
         o = make_float2(pa[i].x / fmaxf(z.x, eps), pa[i].y / fmaxf(z.y, eps));
-        *reinterpret_cast<float2*>(ap.b + g) = z;
-        *reinterpret_cast<float2*>(ap.q + g) = o;
+        st2(ap.b + g, z);
+        st2(ap.q + g, o);
       } else if (MODE == 4) {
         ncn += (z.x < 0.f) + (z.y < 0.f);
         const float2 ps = pa[i];
         const float tx = tikhonov(ps.x * (z.x > 0.f ? z.x : 0.f), lamp);
         const float ty = tikhonov(ps.y * (z.y > 0.f ? z.y : 0.f), lamp);
         o = wv ? make_float2(ps.x + pb[i].x * (tx - ps.x), ps.y + pb[i].y * (ty - ps.y)) : make_float2(tx, ty);
-        *reinterpret_cast<float2*>(ap.c + g) = z;
-        *reinterpret_cast<float2*>(ap.psi_in + g) = ps;
-        *reinterpret_cast<float2*>(J.psi + g) = o;
+        st2(ap.c + g, z);
+        st2(ap.psi_in + g, ps);
+        st2(J.psi + g, o);
         acc += (double)o.x + (double)o.y;
         bad |= !(isfinite(o.x) && isfinite(o.y));
       } else if (MODE == 5) {
@@ -172,14 +172,14 @@ __global__ void __launch_bounds__(64 * WPB)
           od[e] = ub * cp + (wv ? (1.f - ww[e]) * gg[e] : 0.f);
           cb[e] = cc[e] > 0.f ? ub * ps[e] : 0.f;
         }
-        *reinterpret_cast<float2*>(ap.part + g) = make_float2(od[0], od[1]);
+        st2(ap.part + g, make_float2(od[0], od[1]));
         o = make_float2(cb[0], cb[1]);
       } else if (MODE == 6) {
         // qbar = z, q = pa, b = pb
         o = make_float2(pb[i].x > eps ? -z.x * pa[i].x / pb[i].x : 0.f,
                         pb[i].y > eps ? -z.y * pa[i].y / pb[i].y : 0.f);
       } else if (MODE == 7) {
-        *reinterpret_cast<float2*>(ap.out + g) = make_float2(pa[i].x + z.x, pa[i].y + z.y);
+        st2(ap.out + g, make_float2(pa[i].x + z.x, pa[i].y + z.y));
       } else if (MODE == 8) {
         const float rx = z.x - pa[i].x, ry = z.y - pa[i].y;
         acc += (double)rx * rx + (double)ry * ry;
@@ -295,10 +295,10 @@ __global__ void __launch_bounds__(T)
       const float2 a = S.ld(line, pos);
       if (line < nl) {
         const int64_t idx = off + line + (int64_t)pos * ps;
-        if (s_out) s_out[idx] = a;
+        if (s_out) gp(s_out)[idx] = a;
         if (acc) {
-          const float2 s = s_in[idx];
-          double2 t = acc[idx];
+          const float2 s = gp(s_in)[idx];
+          double2 t = gp(acc)[idx];
           if (acc_mode == 0) {  // a conj(s)
             t.x += (double)a.x * s.x + (double)a.y * s.y;
             t.y += (double)a.y * s.x - (double)a.x * s.y;
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(T)
             t.x += (double)a.x * s.x + (double)a.y * s.y;
             t.y += (double)a.x * s.y - (double)a.y * s.x;
           }
-          acc[idx] = t;
+          gp(acc)[idx] = t;
         }
       }
       S.st(line, pos, cmul(a, conjH ? cconj(h[i]) : h[i]));

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "mvd_gmem.h"
 #include "mvd_types.h"
 
 namespace mvdk {
@@ -33,7 +34,7 @@ struct KLine {
   __device__ __forceinline__ float2 ld(int line, int pos) const {
     int d = pos + cz;
     if (d >= nz) d -= nz;
-    return (line < nl && d < kz) ? base[line + d * ps] : make_float2(0.f, 0.f);
+    return (line < nl && d < kz) ? ldg(base + line + d * ps) : make_float2(0.f, 0.f);
   }
 };
 

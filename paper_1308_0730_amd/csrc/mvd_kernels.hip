@@ -71,8 +71,8 @@ __global__ void __launch_bounds__(64 * WPB)
   load_table<T>(s_pp, twp + J.pp, M);
   const int wrow0 = local * RW + wave * RPW;
   const int nrw = max(0, min(RPW, J.ny * J.nz - wrow0));
-  float2* spec = reinterpret_cast<float2*>(J.spec);
-  float2* nyq = spec + J.spec_main;
+  const auto spec = gp(reinterpret_cast<float2*>(J.spec));
+  const auto nyq = spec + J.spec_main;
   const LdsRow<MAXM> L{lds + wave * RPW * MAXM};
   const int npair = M / 2 + 1;
   const unsigned mM = mvd_magic(M), mP = mvd_magic(npair);
@@ -90,9 +90,9 @@ __global__ void __launch_bounds__(64 * WPB)
     pa[i] = pb[i] = make_float2(0.f, 0.f);
     if (r < nrw && p < M) {
       const int64_t g = (int64_t)(wrow0 + r) * nx + 2 * p;
-      if (MODE == 1) pa[i] = *reinterpret_cast<const float2*>(J.phi + vo + g);
-      if (MODE != 1) pa[i] = *reinterpret_cast<const float2*>(J.psi + g);
-      if (MODE == 2 && wv) pb[i] = *reinterpret_cast<const float2*>(wv + g);
+      if (MODE == 1) pa[i] = ld2(J.phi + vo + g);
+      if (MODE != 1) pa[i] = ld2(J.psi + g);
+      if (MODE == 2 && wv) pb[i] = ld2(wv + g);
     }
   }
 
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(64 * WPB)
           } else {
             o = make_float2(tx, ty);
           }
-          *reinterpret_cast<float2*>(J.psi + (int64_t)(wrow0 + r) * nx + 2 * p) = o;
+          st2(J.psi + (int64_t)(wrow0 + r) * nx + 2 * p, o);
           flux += (double)o.x + (double)o.y;
           bad |= !(isfinite(o.x) && isfinite(o.y));
         }

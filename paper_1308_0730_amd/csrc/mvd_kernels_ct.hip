@@ -27,8 +27,7 @@ struct GRow {
   int nx, nrw;
   static constexpr bool lds = false;
   __device__ __forceinline__ float2 ld(int line, int pos) const {
-    return line < nrw ? *reinterpret_cast<const float2*>(base + (int64_t)line * nx + 2 * pos)
-                      : make_float2(0.f, 0.f);
+    return line < nrw ? ld2(base + (int64_t)line * nx + 2 * pos) : make_float2(0.f, 0.f);
   }
 };
 
@@ -87,7 +86,7 @@ struct RowOp {
       } else {
         o = make_float2(tx, ty);
       }
-      *reinterpret_cast<float2*>(psi_rows + (int64_t)line * nx + 2 * pos) = o;
+      st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
       flux += (double)o.x + (double)o.y;
       bad |= !(isfinite(o.x) && isfinite(o.y));
     }
@@ -222,8 +221,8 @@ __global__ void __launch_bounds__(64 * WPB)
   load_table<T>(s_pp, twp + J.pp, M);
   const int wrow0 = local * RW + wave * RPW;
   const int nrw = max(0, min(RPW, J.ny * J.nz - wrow0));
-  float2* spec = reinterpret_cast<float2*>(J.spec);
-  float2* nyq = spec + J.spec_main;
+  const auto spec = gp(reinterpret_cast<float2*>(J.spec));
+  const auto nyq = spec + J.spec_main;
   const LdsRow<M> L{lds + wave * RPW * M};
   const int64_t vo = (int64_t)v * J.V;
   const int64_t rowoff = (int64_t)wrow0 * nx;
@@ -249,8 +248,8 @@ __global__ void __launch_bounds__(64 * WPB)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
-        pa[i][r] = ok ? *reinterpret_cast<const float2*>(opa + g) : make_float2(0.f, 0.f);
-        pb[i][r] = (MODE == 2 && ok && opb) ? *reinterpret_cast<const float2*>(opb + g) : make_float2(0.f, 0.f);
+        pa[i][r] = ok ? ld2(opa + g) : make_float2(0.f, 0.f);
+        pb[i][r] = (MODE == 2 && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
       }
     }
     // rebuild the M-point spectrum Z of these rows from their half spectrum X
