@@ -205,6 +205,39 @@ def view_update(psi, phi, P, K, w=None, lam_p=0.0, eps=0.0, conv=circ_conv, stat
     return psi + w * (t - psi)
 
 
+GEOMETRIC, ARITHMETIC = 0, 1
+
+
+def combined_update(psi, views, P, K, mean=GEOMETRIC, lam_p=0.0, eps=0.0, conv=circ_conv, stats=None):
+    """One combined update of psi from all views at once (eq. 51).
+
+    Every view's back-projected ratio c_v = (phi_v / max(psi * P_v, eps)) * K_v
+    is taken from the same psi.  Eq. 51 multiplies them; the convergence
+    proof (section on the proof for multiple views) normalises that product
+    by the number of views with the |V|-th root, i.e. the geometric mean.
+    The additive ML-EM derivation uses the arithmetic mean of the same
+    factors instead.  Then u = psi . mean(max(c_v, 0)) and t = T_lambda(u).
+    """
+    n = len(views)
+    acc = None
+    for v in range(n):
+        b = conv(psi, P[v])
+        q = views[v] / np.maximum(b, eps)
+        c = conv(q, K[v])
+        if stats is not None:
+            stats["ratio_clamps"] = stats.get("ratio_clamps", 0) + int(np.count_nonzero(b < eps))
+            stats["neg_clamps"] = stats.get("neg_clamps", 0) + int(np.count_nonzero(c < 0))
+        c = np.maximum(c, 0.0)
+        if acc is None:
+            acc = c.copy()
+        elif mean == GEOMETRIC:
+            acc = acc * c
+        else:
+            acc = acc + c
+    g = acc ** (1.0 / n) if mean == GEOMETRIC else acc / n
+    return tikhonov(psi * g, lam_p)
+
+
 class Problem:
     """Inputs of one deconvolution: views, PSFs, optional weights, lambda."""
 
@@ -242,6 +275,21 @@ class Problem:
                                   self.eps, conv=conv, stats=stats)
                 if flux is not None:
                     flux.append(float(psi.sum()))
+        return psi
+
+
+    def iterate_combined(self, psi, n_iter, variant, mean=GEOMETRIC, conv=circ_conv, flux=None, stats=None):
+        """n_iter combined updates (eq. 51): all views contribute to one
+        update of psi per iteration.  Weights are a device of the sequential
+        scheme (a fraction of each view's step) and are not used here."""
+        if self.weights is not None:
+            raise ValueError("combined updates take no weights")
+        K = self.kernels(variant)
+        psi = np.array(psi, dtype=np.float64)
+        for _ in range(n_iter):
+            psi = combined_update(psi, self.views, self.P, K, mean, self.lam_p, self.eps, conv=conv, stats=stats)
+            if flux is not None:
+                flux.append(float(psi.sum()))
         return psi
 
 
