@@ -64,6 +64,11 @@ extern "C" {
 #define MVD_OPT1 2
 #define MVD_OPT2 3
 
+/* How mvd_iterate_combined merges the views' factors. */
+#define MVD_MEAN_GEOMETRIC 0  /* product and |V|-th root (eq. 51, normalised as in the
+                                 convergence proof for multiple views) */
+#define MVD_MEAN_ARITHMETIC 1 /* sum over |V| (additive ML-EM) */
+
 #define MVD_MEM_HOST 0
 #define MVD_MEM_DEVICE 1
 
@@ -144,6 +149,17 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
 /* Run n >= 0 iterations of `variant` (MVD_RL..MVD_OPT2).  Asynchronous.  The
  * compound-kernel spectra of a variant are built on its first use. */
 int mvd_iterate(mvd_handle* h, int n, int variant);
+
+/* Run n >= 0 combined updates (eq. 51): per iteration every view's
+ * back-projected ratio c_v = (phi_v / max(psi x P_v, eps)) x K_v is taken
+ * from the same psi, and psi <- T_lambda(psi . mean_v max(c_v, 0)) with
+ * `mean` MVD_MEAN_GEOMETRIC or MVD_MEAN_ARITHMETIC; `variant` picks K_v as in
+ * mvd_iterate (MVD_RL with the arithmetic mean is classic ML-EM).
+ * Asynchronous.  MVD_EINVAL for a handle created with weights (they apply to
+ * sequential view-updates).  The first call allocates one volume and one
+ * spectrum per block.  In the statistics, flux[n_views - 1] holds the sum of
+ * psi after the update and the other entries are 0. */
+int mvd_iterate_combined(mvd_handle* h, int n, int variant, int mean);
 
 /* Apply one view-update (view `view`, all blocks) -- the inspection hook of
  * a single line of the sequential scheme of section 7.  Asynchronous; does

@@ -34,15 +34,17 @@ int mvd_cfg_exact(int kind, int cfg);   // > 0: compile-time plan for exactly th
 int mvd_ct_num_cfgs(int kind);
 int mvd_ct_cfg(int kind, int cfg, int field);
 hipError_t mvd_launch_x_ct(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
-                           int write_spec);
+                           int opt);
 hipError_t mvd_launch_y_ct(const LaunchArgs& a, int cfg, int inv, int v);
-hipError_t mvd_launch_z_ct(const LaunchArgs& a, int cfg, int v, int role, int conjH);
+hipError_t mvd_launch_z_ct(const LaunchArgs& a, int cfg, int v, int role, int conjH, int src_saved);
 
-// mode 0: R2C of psi; 1: blur -> ratio -> R2C; 2: back-projection -> update -> R2C
-hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
-                        int write_spec);
+// mode 0: R2C of psi; 1: blur -> ratio -> R2C; 2: back-projection -> update
+// -> R2C; 3: back-projection -> fold into the combined factor; 4: the same,
+// then the combined update -> R2C.  opt: XOPT_* bits.
+hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags, int opt);
 hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v);
-hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH);
+// src_saved: read the tile from the job's saved spectrum (write to spec)
+hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH, int src_saved = 0);
 hipError_t mvd_launch_reduce(const Partial* parts, int ntiles, int nviews, double* flux,
                              unsigned long long* ratio, unsigned long long* neg, hipStream_t s);
 hipError_t mvd_launch_check(const float* x, int64_t n, float lo, float hi, double* psum,

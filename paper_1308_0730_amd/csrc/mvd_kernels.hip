@@ -27,7 +27,11 @@ using namespace mvdk;
 // x pass.  MODE 0: forward real-to-complex of psi.  MODE 1: inverse x of the
 // blurred spectrum -> b, q = phi / max(b, eps), forward x of q.  MODE 2:
 // inverse x of the back-projected spectrum -> c, update psi, forward x of the
-// new psi (skipped when write_spec == 0).
+// new psi (when opt has XOPT_SPEC).  Combined updates (eq. 51): MODE 3
+// folds max(c, 0) of one view into the factor acc (product, or sum); MODE 4
+// does the same for the last view, then psi <- T(psi . mean) with the
+// |V|-th root of the product or the sum over |V|, and the forward x of the
+// new psi (when opt has XOPT_SPEC).
 //
 // A row of nx reals is handled as M = nx/2 complex values z[n] = x[2n] +
 // i x[2n+1]; the half spectrum follows from the M-point transform Z by
@@ -39,10 +43,11 @@ template <int MODE, int WPB, int RPW, int MAXM>
 __global__ void __launch_bounds__(64 * WPB)
     k_xpass(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
             const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
-            int write_spec) {
+            int opt) {
   constexpr int T = 64 * WPB;
   constexpr int RW = WPB * RPW;
   constexpr int EPT = (RPW * MAXM + 63) / 64;
+  constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
   constexpr int NPIT = (RPW * (MAXM / 2 + 1) + 63) / 64;
   __shared__ float2 lds[RW * MAXM];
   __shared__ float2 s_tw[MAXM];
@@ -56,16 +61,18 @@ __global__ void __launch_bounds__(64 * WPB)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (MODE != 0 && v >= J.nviews) {
     if (tid == 0 && parts) {
-      if (MODE == 2) {
+      if (MODE == 1) {
+        parts[blockIdx.x].ratio_clamps = 0;
+      } else {
         parts[blockIdx.x].flux = 0.0;
         parts[blockIdx.x].neg_clamps = 0;
-      } else {
-        parts[blockIdx.x].ratio_clamps = 0;
       }
     }
     return;
   }
   const int M = J.M, nx = J.nx;
+  const bool first = opt & XOPT_FIRST, geo = opt & XOPT_GEO;
+  const float inv_n = 1.f / (float)J.nviews;
   const FftPlan* pl = plans + J.plan_x;
   load_table<T>(s_tw, twp + pl->tw, M);
   load_table<T>(s_pp, twp + J.pp, M);
@@ -91,8 +98,10 @@ __global__ void __launch_bounds__(64 * WPB)
     if (r < nrw && p < M) {
       const int64_t g = (int64_t)(wrow0 + r) * nx + 2 * p;
       if (MODE == 1) pa[i] = ld2(J.phi + vo + g);
-      if (MODE != 1) pa[i] = ld2(J.psi + g);
+      if (MODE == 0 || MODE == 2) pa[i] = ld2(J.psi + g);
       if (MODE == 2 && wv) pb[i] = ld2(wv + g);
+      if (MODE >= 3 && !first) pa[i] = ld2(J.acc + g);
+      if (MODE == 4) pb[i] = ld2(J.psi + g);
     }
   }
 
@@ -159,6 +168,26 @@ __global__ void __launch_bounds__(64 * WPB)
         if (MODE == 1) {
           ncr += (z.x < eps) + (z.y < eps);
           o = make_float2(pa[i].x / fmaxf(z.x, eps), pa[i].y / fmaxf(z.y, eps));
+        } else if (MODE >= 3) {
+          ncn += (z.x < 0.f) + (z.y < 0.f);
+          const float cx = z.x > 0.f ? z.x : 0.f, cy = z.y > 0.f ? z.y : 0.f;
+          float mx = cx, my = cy;
+          if (!first) {
+            mx = geo ? pa[i].x * cx : pa[i].x + cx;
+            my = geo ? pa[i].y * cy : pa[i].y + cy;
+          }
+          const int64_t g = (int64_t)(wrow0 + r) * nx + 2 * p;
+          if (MODE == 3) {
+            st2(J.acc + g, make_float2(mx, my));
+            o = make_float2(mx, my);
+          } else {
+            const float gx = geo ? powf(mx, inv_n) : mx * inv_n;
+            const float gy = geo ? powf(my, inv_n) : my * inv_n;
+            o = make_float2(tikhonov(pb[i].x * gx, lamp), tikhonov(pb[i].y * gy, lamp));
+            st2(J.psi + g, o);
+            flux += (double)o.x + (double)o.y;
+            bad |= !(isfinite(o.x) && isfinite(o.y));
+          }
         } else {
           ncn += (z.x < 0.f) + (z.y < 0.f);
           const float ux = pa[i].x * (z.x > 0.f ? z.x : 0.f);
@@ -179,7 +208,7 @@ __global__ void __launch_bounds__(64 * WPB)
     gsync<SYNC_WAVE>();
   }
 
-  if (MODE == 0 || write_spec) {
+  if (MODE == 0 || MODE == 1 || (UPD && (opt & XOPT_SPEC))) {
     fft_lines<false, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
     // half spectrum of the rows from the M-point transform
 #pragma unroll
@@ -212,15 +241,15 @@ __global__ void __launch_bounds__(64 * WPB)
   }
 
   if (MODE != 0) {
-    if (MODE == 2 && bad) atomicOr(flags, 1);
+    if (UPD && bad) atomicOr(flags, 1);
     if (parts) {
       block_reduce<T>(flux, ncr, ncn, rf, ra, rb);
       if (tid == 0) {
-        if (MODE == 2) {
+        if (MODE == 1) {
+          parts[blockIdx.x].ratio_clamps = ncr;
+        } else {
           parts[blockIdx.x].flux = flux;
           parts[blockIdx.x].neg_clamps = ncn;
-        } else {
-          parts[blockIdx.x].ratio_clamps = ncr;
         }
       }
     }
@@ -268,11 +297,13 @@ __global__ void __launch_bounds__(T)
 // z pass with the spectral product: forward z transform of the kernel lines
 // of view v (their x/y-stage planes placed on the length-nz line), forward z
 // transform of the data, multiply (by the conjugate for the mirrored kernel
-// P_v*), inverse z transform, all while the tile stays in LDS.
+// P_v*), inverse z transform, all while the tile stays in LDS.  With
+// src_saved the tile is read from the job's saved spectrum (combined
+// updates) and written to the work spectrum.
 template <int T, int TX, int MAXL>
 __global__ void __launch_bounds__(T)
     k_zconv(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
-            const float2* __restrict__ twp, int v, int role, int conjH) {
+            const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
   __shared__ float2 lds[MAXL * TX];
   __shared__ float2 s_tw[MAXL];
   int local;
@@ -300,6 +331,7 @@ __global__ void __launch_bounds__(T)
   const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, nz,
                  J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
+  const GTile gin{reinterpret_cast<float2*>(src_saved ? J.saved : J.spec) + off, 1, ps, nl};
   constexpr int EPT = (TX * MAXL + T - 1) / T;
   const int tid = threadIdx.x;
   const FftPlan* pl = plans + J.plan_z;
@@ -316,7 +348,7 @@ __global__ void __launch_bounds__(T)
     h[i] = pos < nz ? S.ld(line, pos) : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, g, S, S);
+  fft_lines<false, MAXL, T, TX, true, SYNC_BLOCK>(pl, s_tw, tid, gin, S, S);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * T;
@@ -456,24 +488,28 @@ int mvd_cfg_param(int kind, int cfg) { return cfg_field(kind, cfg, 1); }
 int mvd_cfg_maxlen(int kind, int cfg) { return cfg_field(kind, cfg, 2); }
 int mvd_cfg_exact(int kind, int cfg) { return cfg >= rt_num(kind) ? cfg_field(kind, cfg, 2) : 0; }
 
-hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
-                        int write_spec) {
-  if (cfg >= rt_num(PASS_X)) return mvd_launch_x_ct(a, cfg - rt_num(PASS_X), mode, v, parts, flags, write_spec);
+hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags, int opt) {
+  if (mode < 0 || mode > 4) return hipErrorInvalidValue;
+  if (cfg >= rt_num(PASS_X)) return mvd_launch_x_ct(a, cfg - rt_num(PASS_X), mode, v, parts, flags, opt);
   switch (cfg) {
-#define X(i, wpb, rpw, m)                                                                        \
-  case i:                                                                                        \
-    if (mode == 0)                                                                               \
-      k_xpass<0, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
-                                                                 v, parts, flags, write_spec);   \
-    else if (mode == 1)                                                                          \
-      k_xpass<1, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
-                                                                 v, parts, flags, write_spec);   \
-    else                                                                                         \
-      k_xpass<2, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
-                                                                 v, parts, flags, write_spec);   \
+#define XM(md, wpb, rpw, m)                                                                              \
+  case md:                                                                                               \
+    k_xpass<md, wpb, rpw, m><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, parts, \
+                                                                flags, opt);                             \
+    break;
+#define X(i, wpb, rpw, m)    \
+  case i:                    \
+    switch (mode) {          \
+      XM(0, wpb, rpw, m)     \
+      XM(1, wpb, rpw, m)     \
+      XM(2, wpb, rpw, m)     \
+      XM(3, wpb, rpw, m)     \
+      XM(4, wpb, rpw, m)     \
+    }                        \
     break;
     MVD_ROW_CFGS(X)
 #undef X
+#undef XM
     default:
       return hipErrorInvalidValue;
   }
@@ -498,12 +534,12 @@ hipError_t mvd_launch_y(const LaunchArgs& a, int cfg, int inv, int v) {
   return hipGetLastError();
 }
 
-hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH) {
-  if (cfg >= rt_num(PASS_Z)) return mvd_launch_z_ct(a, cfg - rt_num(PASS_Z), v, role, conjH);
+hipError_t mvd_launch_z(const LaunchArgs& a, int cfg, int v, int role, int conjH, int src_saved) {
+  if (cfg >= rt_num(PASS_Z)) return mvd_launch_z_ct(a, cfg - rt_num(PASS_Z), v, role, conjH, src_saved);
   switch (cfg) {
-#define X(i, t, tx, l)                                                                              \
-  case i:                                                                                           \
-    k_zconv<t, tx, l><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, role, conjH); \
+#define X(i, t, tx, l)                                                                                         \
+  case i:                                                                                                      \
+    k_zconv<t, tx, l><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, role, conjH, src_saved); \
     break;
     MVD_COL_CFGS(X)
 #undef X

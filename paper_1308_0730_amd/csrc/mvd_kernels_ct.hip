@@ -54,18 +54,21 @@ struct ToRegs {
   __device__ __forceinline__ void st(int, int, float2 v, int i, int r) { h[i][r] = v; }
 };
 
-// Last inverse x stage: the pointwise step of the ratio (MODE 1) or of the
-// update (MODE 2) on the two real values held by each complex output; the
-// packed result goes to LDS as the input of the forward transform.
+// Last inverse x stage: the pointwise step of the ratio (MODE 1), of the
+// update (MODE 2), of folding a view into the combined factor (MODE 3) or of
+// the last fold and the combined update (MODE 4), on the two real values held
+// by each complex output; the packed result goes to LDS as the input of the
+// forward transform.
 template <int MODE, int PITCH, int MAXB, int R>
 struct RowOp {
   float2* buf;
   const float2 (&pa)[MAXB][R];
   const float2 (&pb)[MAXB][R];
-  float* psi_rows;  // psi at row wrow0 (MODE 2)
+  float* psi_rows;  // psi at row wrow0 (MODES 2, 4)
+  float* acc_rows;  // the combined factor at row wrow0 (MODES 3, 4)
   int nx, nrw;
-  bool weighted;
-  float eps, lamp;
+  bool weighted, first, geo;
+  float eps, lamp, inv_n;
   double flux;
   unsigned ncr, ncn;
   bool bad;
@@ -76,7 +79,7 @@ struct RowOp {
     if (MODE == 1) {
       ncr += (z.x < eps) + (z.y < eps);
       o = make_float2(pa[i][r].x / fmaxf(z.x, eps), pa[i][r].y / fmaxf(z.y, eps));
-    } else {
+    } else if (MODE == 2) {
       ncn += (z.x < 0.f) + (z.y < 0.f);
       const float2 p = pa[i][r];
       const float tx = tikhonov(p.x * (z.x > 0.f ? z.x : 0.f), lamp);
@@ -89,6 +92,25 @@ struct RowOp {
       st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
       flux += (double)o.x + (double)o.y;
       bad |= !(isfinite(o.x) && isfinite(o.y));
+    } else {
+      ncn += (z.x < 0.f) + (z.y < 0.f);
+      const float cx = z.x > 0.f ? z.x : 0.f, cy = z.y > 0.f ? z.y : 0.f;
+      float mx = cx, my = cy;
+      if (!first) {
+        mx = geo ? pa[i][r].x * cx : pa[i][r].x + cx;
+        my = geo ? pa[i][r].y * cy : pa[i][r].y + cy;
+      }
+      if (MODE == 3) {
+        o = make_float2(mx, my);
+        st2(acc_rows + (int64_t)line * nx + 2 * pos, o);
+      } else {
+        const float gx = geo ? powf(mx, inv_n) : mx * inv_n;
+        const float gy = geo ? powf(my, inv_n) : my * inv_n;
+        o = make_float2(tikhonov(pb[i][r].x * gx, lamp), tikhonov(pb[i][r].y * gy, lamp));
+        st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
+        flux += (double)o.x + (double)o.y;
+        bad |= !(isfinite(o.x) && isfinite(o.y));
+      }
     }
     buf[line * PITCH + pos] = o;
   }
@@ -137,7 +159,7 @@ __global__ void __launch_bounds__(T)
 template <int T, int TX, int L, int... Rs>
 __global__ void __launch_bounds__(T)
     k_zconv_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
-               const float2* __restrict__ twp, int v, int role, int conjH) {
+               const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
   constexpr int RL = LastRadix<Rs...>::value;
   using LM = LastMap<L, RL, T, TX, true>;
   __shared__ float2 lds[L * TX];
@@ -167,6 +189,7 @@ __global__ void __launch_bounds__(T)
   const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, L,
                  J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
+  const GTile gin{reinterpret_cast<float2*>(src_saved ? J.saved : J.spec) + off, 1, ps, nl};
   load_table<T>(s_tw, twp + plans[J.plan_z].tw, L);
   const LdsCol<TX> S{lds};
   // kernel spectrum of the tile's lines, in the order the last forward stage
@@ -176,7 +199,7 @@ __global__ void __launch_bounds__(T)
   CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, kl, S, kreg);
   __syncthreads();
   MulH<TX, LM::MAXB, RL> mul{lds, h, conjH};
-  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, g, S, mul);
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, gin, S, mul);
   Plain<GTile> out{g};
   CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
 }
@@ -188,8 +211,9 @@ template <int MODE, int WPB, int RPW, int M, int... Rs>
 __global__ void __launch_bounds__(64 * WPB)
     k_xpass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
                const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
-               int write_spec) {
+               int opt) {
   constexpr int T = 64 * WPB;
+  constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
   constexpr int RW = WPB * RPW;
   constexpr int NPAIR = M / 2 + 1;
   constexpr int NPIT = (RPW * NPAIR + 63) / 64;
@@ -207,16 +231,17 @@ __global__ void __launch_bounds__(64 * WPB)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (MODE != 0 && v >= J.nviews) {
     if (tid == 0 && parts) {
-      if (MODE == 2) {
+      if (MODE == 1) {
+        parts[blockIdx.x].ratio_clamps = 0;
+      } else {
         parts[blockIdx.x].flux = 0.0;
         parts[blockIdx.x].neg_clamps = 0;
-      } else {
-        parts[blockIdx.x].ratio_clamps = 0;
       }
     }
     return;
   }
   const int nx = J.nx;
+  const bool first = opt & XOPT_FIRST, geo = opt & XOPT_GEO;
   load_table<T>(s_tw, twp + plans[J.plan_x].tw, M);
   load_table<T>(s_pp, twp + J.pp, M);
   const int wrow0 = local * RW + wave * RPW;
@@ -239,8 +264,8 @@ __global__ void __launch_bounds__(64 * WPB)
     // operands of the pointwise step, in the order the last inverse stage
     // produces its outputs
     float2 pa[LM::MAXB][RL], pb[LM::MAXB][RL];
-    const float* opa = MODE == 1 ? J.phi + vo + rowoff : J.psi + rowoff;
-    const float* opb = J.w ? J.w + vo + rowoff : nullptr;
+    const float* opa = MODE == 1 ? J.phi + vo + rowoff : MODE == 2 ? J.psi + rowoff : (first ? nullptr : J.acc + rowoff);
+    const float* opb = MODE == 2 ? (J.w ? J.w + vo + rowoff : nullptr) : MODE == 4 ? J.psi + rowoff : nullptr;
 #pragma unroll
     for (int i = 0; i < LM::MAXB; ++i) {
       int line, j;
@@ -248,8 +273,8 @@ __global__ void __launch_bounds__(64 * WPB)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
-        pa[i][r] = ok ? ld2(opa + g) : make_float2(0.f, 0.f);
-        pb[i][r] = (MODE == 2 && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
+        pa[i][r] = (ok && opa) ? ld2(opa + g) : make_float2(0.f, 0.f);
+        pb[i][r] = ((MODE == 2 || MODE == 4) && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
       }
     }
     // rebuild the M-point spectrum Z of these rows from their half spectrum X
@@ -286,20 +311,21 @@ __global__ void __launch_bounds__(64 * WPB)
       }
     }
     gsync<SYNC_WAVE>();
-    RowOp<MODE, M, LM::MAXB, RL> op{L.p, pa, pb, J.psi + rowoff, nx, nrw, opb != nullptr, J.eps, J.lamp,
-                                    0.0, 0u, 0u, false};
+    RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff, MODE >= 3 ? J.acc + rowoff : nullptr,
+                                    nx,    nrw,   opb != nullptr,  first, geo,
+                                    J.eps, J.lamp, 1.f / (float)J.nviews, 0.0, 0u, 0u, false};
     CtRun<true, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, op);
     flux = op.flux;
     ncr = op.ncr;
     ncn = op.ncn;
     bad = op.bad;
-    if (write_spec || MODE == 1) {
+    if (MODE == 1 || (UPD && (opt & XOPT_SPEC))) {
       Plain<LdsRow<M>> out{L};
       CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, out);
     }
   }
 
-  if (MODE != 2 || write_spec) {
+  if (MODE == 0 || MODE == 1 || (UPD && (opt & XOPT_SPEC))) {
     // half spectrum of the rows from the M-point transform
 #pragma unroll
     for (int i = 0; i < NPIT; ++i) {
@@ -330,15 +356,15 @@ __global__ void __launch_bounds__(64 * WPB)
   }
 
   if (MODE != 0) {
-    if (MODE == 2 && bad) atomicOr(flags, 1);
+    if (UPD && bad) atomicOr(flags, 1);
     if (parts) {
       block_reduce<T>(flux, ncr, ncn, rf, ra, rb);
       if (tid == 0) {
-        if (MODE == 2) {
+        if (MODE == 1) {
+          parts[blockIdx.x].ratio_clamps = ncr;
+        } else {
           parts[blockIdx.x].flux = flux;
           parts[blockIdx.x].neg_clamps = ncn;
-        } else {
-          parts[blockIdx.x].ratio_clamps = ncr;
         }
       }
     }
@@ -388,22 +414,29 @@ int mvd_ct_num_cfgs(int kind) {
 int mvd_ct_cfg(int kind, int cfg, int field) { return kind == PASS_X ? kCtRowCfg[cfg][field] : kCtColCfg[cfg][field]; }
 
 hipError_t mvd_launch_x_ct(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
-                           int write_spec) {
+                           int opt) {
   switch (cfg) {
-#define X(i, wpb, rpw, m, ...)                                                                         \
-  case i:                                                                                              \
-    if (mode == 0)                                                                                     \
-      k_xpass_ct<0, wpb, rpw, m, __VA_ARGS__><<<a.grid, 64 * wpb, 0, a.stream>>>(                      \
-          a.jobs, a.njobs, a.plans, a.tw, v, parts, flags, write_spec);                                \
-    else if (mode == 1)                                                                                \
-      k_xpass_ct<1, wpb, rpw, m, __VA_ARGS__><<<a.grid, 64 * wpb, 0, a.stream>>>(                      \
-          a.jobs, a.njobs, a.plans, a.tw, v, parts, flags, write_spec);                                \
-    else                                                                                               \
-      k_xpass_ct<2, wpb, rpw, m, __VA_ARGS__><<<a.grid, 64 * wpb, 0, a.stream>>>(                      \
-          a.jobs, a.njobs, a.plans, a.tw, v, parts, flags, write_spec);                                \
+#define XM(md, wpb, rpw, m, ...)                                                                   \
+  case md:                                                                                         \
+    k_xpass_ct<md, wpb, rpw, m, __VA_ARGS__><<<a.grid, 64 * wpb, 0, a.stream>>>(a.jobs, a.njobs,   \
+                                                                               a.plans, a.tw, v,  \
+                                                                               parts, flags, opt); \
+    break;
+#define X(i, wpb, rpw, m, ...)          \
+  case i:                               \
+    switch (mode) {                     \
+      XM(0, wpb, rpw, m, __VA_ARGS__)   \
+      XM(1, wpb, rpw, m, __VA_ARGS__)   \
+      XM(2, wpb, rpw, m, __VA_ARGS__)   \
+      XM(3, wpb, rpw, m, __VA_ARGS__)   \
+      XM(4, wpb, rpw, m, __VA_ARGS__)   \
+      default:                          \
+        return hipErrorInvalidValue;    \
+    }                                   \
     break;
     MVD_CT_ROW_CFGS(X)
 #undef X
+#undef XM
     default:
       return hipErrorInvalidValue;
   }
@@ -429,12 +462,12 @@ hipError_t mvd_launch_y_ct(const LaunchArgs& a, int cfg, int inv, int v) {
   return hipGetLastError();
 }
 
-hipError_t mvd_launch_z_ct(const LaunchArgs& a, int cfg, int v, int role, int conjH) {
+hipError_t mvd_launch_z_ct(const LaunchArgs& a, int cfg, int v, int role, int conjH, int src_saved) {
   switch (cfg) {
 #define X(i, t, tx, l, ...)                                                                            \
   case i:                                                                                              \
     k_zconv_ct<t, tx, l, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v,   \
-                                                                   role, conjH);                       \
+                                                                   role, conjH, src_saved);            \
     break;
     MVD_CT_COL_CFGS(X)
 #undef X

@@ -50,6 +50,8 @@ struct Block {
   float* phi = nullptr;
   float* w = nullptr;
   float* H[N_ROLES] = {nullptr, nullptr, nullptr, nullptr};
+  float* acc = nullptr;    // combined-update factor [V], allocated on first use
+  float* saved = nullptr;  // spectrum of psi kept over a combined iteration
   std::vector<mvdh::Kern> P;  // prepared PSFs
   std::vector<double> psf_sum;     // sums of the raw PSF inputs
   std::vector<std::array<int, 3>> psf_dims;  // raw extents {kx, ky, kz}
@@ -94,7 +96,9 @@ struct mvd_handle {
   bool spec_valid = false;
   bool built[N_ROLES] = {true, false, false, false};
   int64_t iterations = 0;
-  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  // one graph per (scheme, variant): scheme 0 sequential, 1 combined with
+  // the geometric mean, 2 combined with the arithmetic mean
+  hipGraphExec_t exec[3 * 4] = {};
   // differentiated form: runtime-plan shapes, grids and buffers (block 0)
   int rt_cfg[3] = {-1, -1, -1};
   int rt_grid[3] = {0, 0, 0};
@@ -346,6 +350,8 @@ void build_jobs(mvd_handle* h) {
     j.phi = B.phi;
     j.w = B.w;
     for (int r = 0; r < N_ROLES; ++r) j.H[r] = B.H[r];
+    j.acc = B.acc;
+    j.saved = B.saved;
     j.eps = B.eps;
     j.lamp = B.lamp;
     h->jobs.push_back(j);
@@ -639,6 +645,52 @@ void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t =
   for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, t);
 }
 
+// One combined update (eq. 51): every view's back-projected ratio is taken
+// from the same psi.  The x/y-stage spectrum of psi is computed once and
+// saved; per view the blur's z pass reads it, the ratio and the
+// back-projection follow as in a view-update, and the back-projected ratio
+// is folded into the factor acc; the last view's x pass applies the update
+// and leaves the x-stage spectrum of the new psi for the next iteration.
+void enqueue_combined_iteration(mvd_handle* h, hipStream_t s, int variant, bool geo) {
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  const int conj_back = variant == MVD_RL ? 1 : 0;
+  const int N = h->nviews;
+  const LaunchArgs ax = args(h, s, h->grid_x), ay = args(h, s, h->grid_y), az = args(h, s, h->grid_z);
+  HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, 0));
+  for (const auto& B : h->blocks)
+    HIPCHECK(hipMemcpyAsync(B.saved, B.spec, B.spec_elems * 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  const int mean = geo ? XOPT_GEO : 0;
+  for (int v = 0; v < N; ++v) {
+    Partial* parts = h->d_parts + (size_t)v * h->grid_x;
+    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, ROLE_P, 0, 1));
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
+    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 1, v, parts, h->d_flags, XOPT_SPEC));
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
+    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, role, conj_back, 0));
+    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
+    const int first = v == 0 ? XOPT_FIRST : 0;
+    if (v < N - 1)
+      HIPCHECK(mvd_launch_x(ax, h->cfg_x, 3, v, parts, h->d_flags, first | mean));
+    else
+      HIPCHECK(mvd_launch_x(ax, h->cfg_x, 4, v, parts, h->d_flags, first | mean | XOPT_SPEC));
+  }
+}
+
+void ensure_combined(mvd_handle* h) {
+  bool grown = false;
+  for (auto& B : h->blocks) {
+    if (!B.acc) {
+      B.acc = (float*)h->dalloc(B.V * sizeof(float));
+      grown = true;
+    }
+    if (!B.saved) {
+      B.saved = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
+      grown = true;
+    }
+  }
+  if (grown) build_jobs(h);
+}
+
 void prepare_run(mvd_handle* h, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   const int role = variant == MVD_RL ? ROLE_P : variant;
@@ -649,12 +701,17 @@ void prepare_run(mvd_handle* h, int variant) {
   }
 }
 
-hipGraphExec_t graph_for(mvd_handle* h, int variant) {
-  if (h->exec[variant]) return h->exec[variant];
+// scheme 0: sequential; 1, 2: combined with the geometric / arithmetic mean
+hipGraphExec_t graph_for(mvd_handle* h, int variant, int scheme = 0) {
+  hipGraphExec_t& slot = h->exec[scheme * 4 + variant];
+  if (slot) return slot;
   hipGraph_t g = nullptr;
   HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   try {
-    enqueue_iteration(h, h->cap, variant);
+    if (scheme == 0)
+      enqueue_iteration(h, h->cap, variant);
+    else
+      enqueue_combined_iteration(h, h->cap, variant, scheme == 1);
   } catch (...) {
     (void)hipStreamEndCapture(h->cap, &g);
     if (g) (void)hipGraphDestroy(g);
@@ -665,7 +722,7 @@ hipGraphExec_t graph_for(mvd_handle* h, int variant) {
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHECK(e);
-  h->exec[variant] = ex;
+  slot = ex;
   return ex;
 }
 
@@ -679,6 +736,26 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
     for (int i = 0; i < n; ++i) HIPCHECK(hipGraphLaunch(ex, h->stream));
   } else {
     for (int i = 0; i < n; ++i) enqueue_iteration(h, h->stream, variant);
+  }
+  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, h->stream));
+  h->iterations += n;
+}
+
+void iterate_combined_impl(mvd_handle* h, int n, int variant, int mean) {
+  if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
+  if (mean != MVD_MEAN_GEOMETRIC && mean != MVD_MEAN_ARITHMETIC) bad("mean must be MVD_MEAN_GEOMETRIC or MVD_MEAN_ARITHMETIC");
+  if (n < 0) bad("n must be >= 0");
+  for (const auto& B : h->blocks)
+    if (B.w) bad("combined updates take no weights (weights apply to sequential view-updates)");
+  if (n == 0) return;
+  prepare_run(h, variant);
+  ensure_combined(h);
+  const bool geo = mean == MVD_MEAN_GEOMETRIC;
+  if (h->use_graphs) {
+    hipGraphExec_t ex = graph_for(h, variant, geo ? 1 : 2);
+    for (int i = 0; i < n; ++i) HIPCHECK(hipGraphLaunch(ex, h->stream));
+  } else {
+    for (int i = 0; i < n; ++i) enqueue_combined_iteration(h, h->stream, variant, geo);
   }
   HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, h->stream));
   h->iterations += n;
@@ -1010,6 +1087,14 @@ int mvd_iterate(mvd_handle* h, int n, int variant) {
     return MVD_EINVAL;
   }
   return guard(h, [&] { iterate_impl(h, n, variant); });
+}
+
+int mvd_iterate_combined(mvd_handle* h, int n, int variant, int mean) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { iterate_combined_impl(h, n, variant, mean); });
 }
 
 int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {

@@ -54,7 +54,16 @@ struct JobDesc {
   const float* H[N_ROLES];     // [nviews][h_elems] complex kernel planes; nullptr if not built
   float eps, lamp;
   int kz, cz;                  // kernel window along z and its centre
+  float* acc;                  // [V] combined-update factor (product or sum over views), or nullptr
+  float* saved;                // spec_elems complex: x/y-stage spectrum of psi kept over a combined
+                               // iteration, or nullptr
 };
+
+// Options of the x passes (bit set).  SPEC: write the forward x transform
+// of the new psi (update modes).  FIRST: the first view of a combined
+// iteration (the factor starts from this view's value).  GEO: combine by
+// product and |V|-th root, else by sum and division by |V|.
+enum { XOPT_SPEC = 1, XOPT_FIRST = 2, XOPT_GEO = 4 };
 
 // Per-workgroup partial results of the x passes (one entry per x tile).
 struct Partial {

@@ -65,6 +65,7 @@ def lib():
     L.mvd_create.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options)]
     L.mvd_create_batch.argtypes = [C.POINTER(H), C.c_int, C.POINTER(Problem), C.POINTER(Options)]
     L.mvd_iterate.argtypes = [H, C.c_int, C.c_int]
+    L.mvd_iterate_combined.argtypes = [H, C.c_int, C.c_int, C.c_int]
     L.mvd_get_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
@@ -86,7 +87,8 @@ def lib():
                                       C.c_void_p, C.POINTER(C.c_int)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_version.restype = C.c_char_p
-    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_get_estimate", "mvd_set_estimate",
+    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_get_estimate",
+                 "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
                  "mvd_tile_shape", "mvd_loss_grad", "mvd_set_psfs"):
@@ -102,6 +104,13 @@ def _check(rc, h=None):
 
 def _variant(v):
     return VARIANTS[v.lower()] if isinstance(v, str) else int(v)
+
+
+MEANS = {"geometric": 0, "arithmetic": 1}
+
+
+def _mean(m):
+    return MEANS[m.lower()] if isinstance(m, str) else int(m)
 
 
 def _ptr(x):
@@ -207,6 +216,12 @@ class Deconvolver:
 
     def iterate(self, n, variant="eff"):
         _check(lib().mvd_iterate(self._h, int(n), _variant(variant)), self._h)
+        return self
+
+    def iterate_combined(self, n, variant="rl", mean="geometric"):
+        """n combined updates (eq. 51): every view's factor from the same psi,
+        merged by the geometric or the arithmetic mean."""
+        _check(lib().mvd_iterate_combined(self._h, int(n), _variant(variant), _mean(mean)), self._h)
         return self
 
     def view_update(self, view, variant="eff"):
