@@ -29,9 +29,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PASS_NAMES = ("y_forward", "y_inverse", "z_product", "x_ratio", "x_update")
-KERNEL_SOURCES = ("paper_1308_0730_amd/csrc/mvd_kernels.hip", "paper_1308_0730_amd/csrc/mvd_kernels_ct.hip",
-                  "paper_1308_0730_amd/csrc/fft_engine.h", "paper_1308_0730_amd/csrc/fft_ct.h",
-                  "paper_1308_0730_amd/csrc/mvd_device.h", "paper_1308_0730_amd/csrc/mvd_types.h")
+KERNEL_SOURCES = tuple("paper_1308_0730_amd/csrc/" + f for f in (
+    "mvd_kernels.hip", "mvd_kernels_ct.hip", "mvd_ct_passes.h", "mvd_exact_x.hip", "mvd_exact_x_comb.hip",
+    "mvd_exact_y.hip", "mvd_exact_z.hip", "mvd_exact_lengths.h", "fft_engine.h", "fft_ct.h", "mvd_device.h",
+    "mvd_gmem.h", "mvd_types.h"))
 
 
 def workload(cfg):
@@ -199,6 +200,18 @@ def grad_form(steps, warmup):
     return res
 
 
+def convergence_form():
+    """Iterations, updates and device time every scheme x variant needs to
+    reach the same distance from the ground truth (the distance classic
+    ML-EM has after 100 iterations) on the noise-free 128^3 four-view cube."""
+    from paper_1308_0730_amd import convergence, synth
+    s = synth.make_problem((128, 128, 128), 150, [0.0, 45.0, 90.0, 135.0], (25, 25, 25), 1.2, 4.0,
+                           synth.SEED_BASE + 1, noise="none")
+    r = convergence.compare(s, ref_iters=100, max_iter=400)
+    r["workload"] = "128^3, 4 views at 45 deg, 25^3 PSFs, noise-free views, lambda 0, flat start"
+    return r
+
+
 def synth_config5():
     from paper_1308_0730_amd import synth
     return synth.config5()
@@ -216,8 +229,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched (48 blocks, against the plain form looped over them) and the "
-                         "differentiated (forward against forward + backward) measurements")
+                    help="skip the batched (48 blocks, against the plain form looped over them), the "
+                         "differentiated (forward against forward + backward) and the convergence "
+                         "(every scheme x variant to one distance from the ground truth) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -305,7 +319,8 @@ def main():
 
     forms = None
     if not args.no_forms:
-        forms = {"batched": batched_form(max(1, args.steps // 2), 1), "grad": grad_form(3, 1)}
+        forms = {"batched": batched_form(max(1, args.steps // 2), 1), "grad": grad_form(3, 1),
+                 "convergence": convergence_form()}
 
     dims = [list(b.dims) for b in blocks]
     out = {

@@ -23,10 +23,15 @@ ARCH = os.environ.get("MVD_ARCH", "gfx950")
 GPU_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 
+# longest first: they compile in parallel
 SOURCES = [
     ("mvd_kernels.hip", True),
-    ("mvd_kernels_ct.hip", True),
     ("mvd_adjoint.hip", True),
+    ("mvd_exact_z.hip", True),
+    ("mvd_exact_x_comb.hip", True),
+    ("mvd_exact_x.hip", True),
+    ("mvd_exact_y.hip", True),
+    ("mvd_kernels_ct.hip", True),
     ("mvd_runtime.cpp", True),
     ("mvd_host.cpp", False),
 ]

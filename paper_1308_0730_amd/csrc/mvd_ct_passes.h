@@ -1,0 +1,378 @@
+// Pass kernels with compile-time transform plans: the length and the radix
+// sequence (16, 8, 4, 2, 5, 3) are template parameters, so the index math
+// folds away.
+//
+// They compute exactly what the runtime-plan passes of mvd_kernels.hip
+// compute (same algebra, same tile mapping, same pointwise steps).  A launch
+// covers jobs that all have the kernel's length.  Their fused epilogues work
+// on the last transform stage's registers:
+//   z pass: the kernel lines are transformed first and their last stage kept
+//           in registers; the spectral product is applied to the data's last
+//           forward stage outputs in the same order;
+//   x pass: the ratio, the update or the combined-update fold is applied to
+//           the last inverse stage's outputs, with phi, psi, w or the factor
+//           prefetched in the same order.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_ct.h"
+#include "mvd_device.h"
+#include "mvd_kernels.h"
+
+namespace mvdk {
+namespace ctp {
+
+// Global row accessor: element pos of row `line` is the float2 pair
+// (x[2 pos], x[2 pos + 1]) of row wrow0 + line.
+struct GRow {
+  const float* base;  // row wrow0
+  int nx, nrw;
+  static constexpr bool lds = false;
+  __device__ __forceinline__ float2 ld(int line, int pos) const {
+    return line < nrw ? ld2(base + (int64_t)line * nx + 2 * pos) : make_float2(0.f, 0.f);
+  }
+};
+
+// Last forward z stage: multiply by the prefetched kernel spectrum (its
+// conjugate for the mirrored kernel) and store to the LDS tile.
+template <int TX, int MAXB, int R>
+struct MulH {
+  float2* buf;
+  const float2 (&h)[MAXB][R];
+  int conj;
+  static constexpr bool lds = true;
+  __device__ __forceinline__ void st(int line, int pos, float2 v, int i, int r) {
+    const float2 w = h[i][r];
+    buf[pos * TX + line] = cmul(v, conj ? cconj(w) : w);
+  }
+};
+
+// Last forward z stage of the kernel lines: keep the outputs in registers,
+// in the order the data's last forward stage produces its own.
+template <int MAXB, int R>
+struct ToRegs {
+  float2 (&h)[MAXB][R];
+  static constexpr bool lds = false;
+  __device__ __forceinline__ void st(int, int, float2 v, int i, int r) { h[i][r] = v; }
+};
+
+// Last inverse x stage: the pointwise step of the ratio (MODE 1), of the
+// update (MODE 2), of folding a view into the combined factor (MODE 3) or of
+// the last fold and the combined update (MODE 4), on the two real values held
+// by each complex output; the packed result goes to LDS as the input of the
+// forward transform.
+template <int MODE, int PITCH, int MAXB, int R>
+struct RowOp {
+  float2* buf;
+  const float2 (&pa)[MAXB][R];
+  const float2 (&pb)[MAXB][R];
+  float* psi_rows;  // psi at row wrow0 (MODES 2, 4)
+  float* acc_rows;  // the combined factor at row wrow0 (MODES 3, 4)
+  int nx, nrw;
+  bool weighted, first, geo;
+  float eps, lamp, inv_n;
+  double flux;
+  unsigned ncr, ncn;
+  bool bad;
+  static constexpr bool lds = true;
+  __device__ __forceinline__ void st(int line, int pos, float2 z, int i, int r) {
+    if (line >= nrw) return;
+    float2 o;
+    if (MODE == 1) {
+      ncr += (z.x < eps) + (z.y < eps);
+      o = make_float2(pa[i][r].x / fmaxf(z.x, eps), pa[i][r].y / fmaxf(z.y, eps));
+    } else if (MODE == 2) {
+      ncn += (z.x < 0.f) + (z.y < 0.f);
+      const float2 p = pa[i][r];
+      const float tx = tikhonov(p.x * (z.x > 0.f ? z.x : 0.f), lamp);
+      const float ty = tikhonov(p.y * (z.y > 0.f ? z.y : 0.f), lamp);
+      if (weighted) {
+        o = make_float2(p.x + pb[i][r].x * (tx - p.x), p.y + pb[i][r].y * (ty - p.y));
+      } else {
+        o = make_float2(tx, ty);
+      }
+      st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
+      flux += (double)o.x + (double)o.y;
+      bad |= !(isfinite(o.x) && isfinite(o.y));
+    } else {
+      ncn += (z.x < 0.f) + (z.y < 0.f);
+      const float cx = z.x > 0.f ? z.x : 0.f, cy = z.y > 0.f ? z.y : 0.f;
+      float mx = cx, my = cy;
+      if (!first) {
+        mx = geo ? pa[i][r].x * cx : pa[i][r].x + cx;
+        my = geo ? pa[i][r].y * cy : pa[i][r].y + cy;
+      }
+      if (MODE == 3) {
+        o = make_float2(mx, my);
+        st2(acc_rows + (int64_t)line * nx + 2 * pos, o);
+      } else {
+        const float gx = geo ? powf(mx, inv_n) : mx * inv_n;
+        const float gy = geo ? powf(my, inv_n) : my * inv_n;
+        o = make_float2(tikhonov(pb[i][r].x * gx, lamp), tikhonov(pb[i][r].y * gy, lamp));
+        st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
+        flux += (double)o.x + (double)o.y;
+        bad |= !(isfinite(o.x) && isfinite(o.y));
+      }
+    }
+    buf[line * PITCH + pos] = o;
+  }
+};
+
+}  // namespace ctp
+
+using namespace ctp;
+
+// ---------------------------------------------------------------------------
+// y pass (see k_ypass): complex transform along y of TX adjacent columns.
+template <bool INV, int T, int TX, int L, int... Rs>
+__global__ void __launch_bounds__(T)
+    k_ypass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+               const float2* __restrict__ twp, int v) {
+  __shared__ float2 lds[L * TX];
+  __shared__ float2 s_tw[L];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  const int M = J.M, ny = J.ny, nz = J.nz;
+  float2* spec = reinterpret_cast<float2*>(J.spec);
+  const int nxt = mvd_cdiv(M, TX);
+  GTile g;
+  if (local < nxt * nz) {
+    const int xt = local % nxt, z = local / nxt;
+    g.base = spec + (int64_t)z * ny * M + xt * TX;
+    g.ls = 1;
+    g.ps = M;
+    g.nl = min(TX, M - xt * TX);
+  } else {
+    const int t2 = local - nxt * nz;
+    g.base = spec + J.spec_main + (int64_t)t2 * TX * ny;
+    g.ls = ny;
+    g.ps = 1;
+    g.nl = min(TX, nz - t2 * TX);
+  }
+  // the table is read from the second stage on, after the first stage's barrier
+  load_table<T>(s_tw, twp + plans[J.plan_y].tw, L);
+  Plain<GTile> out{g};
+  CtRun<INV, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, g, LdsCol<TX>{lds}, out);
+}
+
+// ---------------------------------------------------------------------------
+// z pass with the spectral product (see k_zconv).
+template <int T, int TX, int L, int... Rs>
+__global__ void __launch_bounds__(T)
+    k_zconv_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+               const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
+  constexpr int RL = LastRadix<Rs...>::value;
+  using LM = LastMap<L, RL, T, TX, true>;
+  __shared__ float2 lds[L * TX];
+  __shared__ float2 s_tw[L];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  const int M = J.M, ny = J.ny;
+  const int nxt = mvd_cdiv(M, TX);
+  int64_t off, hoff;
+  int ps, nl;
+  if (local < nxt * ny) {
+    const int xt = local % nxt, y = local / nxt;
+    off = (int64_t)y * M + xt * TX;
+    hoff = off;
+    ps = ny * M;
+    nl = min(TX, M - xt * TX);
+  } else {
+    const int t2 = local - nxt * ny;
+    off = J.spec_main + (int64_t)t2 * TX;
+    hoff = J.h_main + (int64_t)t2 * TX;
+    ps = ny;
+    nl = min(TX, ny - t2 * TX);
+  }
+  const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, L,
+                 J.kz, J.cz};
+  GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
+  const GTile gin{reinterpret_cast<float2*>(src_saved ? J.saved : J.spec) + off, 1, ps, nl};
+  load_table<T>(s_tw, twp + plans[J.plan_z].tw, L);
+  const LdsCol<TX> S{lds};
+  // kernel spectrum of the tile's lines, in the order the last forward stage
+  // produces its outputs
+  float2 h[LM::MAXB][RL];
+  ToRegs<LM::MAXB, RL> kreg{h};
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, kl, S, kreg);
+  __syncthreads();
+  MulH<TX, LM::MAXB, RL> mul{lds, h, conjH};
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, gin, S, mul);
+  Plain<GTile> out{g};
+  CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
+}
+
+// ---------------------------------------------------------------------------
+// x pass (see k_xpass): MODE 0 R2C of psi, MODE 1 blur -> ratio -> R2C,
+// MODE 2 back-projection -> update -> R2C.  One wave owns RPW rows.
+template <int MODE, int WPB, int RPW, int M, int... Rs>
+__global__ void __launch_bounds__(64 * WPB)
+    k_xpass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+               const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
+               int opt) {
+  constexpr int T = 64 * WPB;
+  constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
+  constexpr int RW = WPB * RPW;
+  constexpr int NPAIR = M / 2 + 1;
+  constexpr int NPIT = (RPW * NPAIR + 63) / 64;
+  constexpr int RL = LastRadix<Rs...>::value;
+  using LM = LastMap<M, RL, 64, RPW, false>;
+  __shared__ float2 lds[RW * M];
+  __shared__ float2 s_tw[M];
+  __shared__ float2 s_pp[M];
+  __shared__ double rf[WPB];
+  __shared__ unsigned ra[WPB], rb[WPB];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_X, RW, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (MODE != 0 && v >= J.nviews) {
+    if (tid == 0 && parts) {
+      if (MODE == 1) {
+        parts[blockIdx.x].ratio_clamps = 0;
+      } else {
+        parts[blockIdx.x].flux = 0.0;
+        parts[blockIdx.x].neg_clamps = 0;
+      }
+    }
+    return;
+  }
+  const int nx = J.nx;
+  const bool first = opt & XOPT_FIRST, geo = opt & XOPT_GEO;
+  load_table<T>(s_tw, twp + plans[J.plan_x].tw, M);
+  load_table<T>(s_pp, twp + J.pp, M);
+  const int wrow0 = local * RW + wave * RPW;
+  const int nrw = max(0, min(RPW, J.ny * J.nz - wrow0));
+  const auto spec = gp(reinterpret_cast<float2*>(J.spec));
+  const auto nyq = spec + J.spec_main;
+  const LdsRow<M> L{lds + wave * RPW * M};
+  const int64_t vo = (int64_t)v * J.V;
+  const int64_t rowoff = (int64_t)wrow0 * nx;
+  double flux = 0.0;
+  unsigned ncr = 0, ncn = 0;
+  bool bad = false;
+
+  if (MODE == 0) {
+    __syncthreads();  // twiddle tables
+    const GRow src{J.psi + rowoff, nx, nrw};
+    Plain<LdsRow<M>> out{L};
+    CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, src, L, out);
+  } else {
+    // operands of the pointwise step, in the order the last inverse stage
+    // produces its outputs
+    float2 pa[LM::MAXB][RL], pb[LM::MAXB][RL];
+    const float* opa = MODE == 1 ? J.phi + vo + rowoff : MODE == 2 ? J.psi + rowoff : (first ? nullptr : J.acc + rowoff);
+    const float* opb = MODE == 2 ? (J.w ? J.w + vo + rowoff : nullptr) : MODE == 4 ? J.psi + rowoff : nullptr;
+#pragma unroll
+    for (int i = 0; i < LM::MAXB; ++i) {
+      int line, j;
+      const bool ok = LM::at(lane, i, line, j) && line < nrw;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
+        pa[i][r] = (ok && opa) ? ld2(opa + g) : make_float2(0.f, 0.f);
+        pb[i][r] = ((MODE == 2 || MODE == 4) && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
+      }
+    }
+    // rebuild the M-point spectrum Z of these rows from their half spectrum X
+    float2 xa[NPIT], xb[NPIT];
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = lane + i * 64;
+      const int r = it / NPAIR, k = it % NPAIR;
+      if (r < nrw) {
+        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        xa[i] = spec[rbase + k];
+        xb[i] = (k == 0) ? nyq[wrow0 + r] : spec[rbase + M - k];
+      }
+    }
+    __syncthreads();  // twiddle tables
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = lane + i * 64;
+      const int r = it / NPAIR, k = it % NPAIR;
+      if (r < nrw) {
+        const float2 a = xa[i], b = xb[i], t = s_pp[k];
+        // Z[k] = (a + conj b) + i conj(t) (a - conj b)
+        const float2 s = make_float2(a.x + b.x, a.y - b.y);
+        const float2 d = make_float2(a.x - b.x, a.y + b.y);
+        const float2 e = cmul(cconj(t), d);
+        L.st(r, k, make_float2(s.x - e.y, s.y + e.x));
+        if (k != 0 && 2 * k != M) {
+          // Z[M-k] = (b + conj a) - i t (b - conj a)
+          const float2 s2 = make_float2(b.x + a.x, b.y - a.y);
+          const float2 d2 = make_float2(b.x - a.x, b.y + a.y);
+          const float2 e2 = cmul(t, d2);
+          L.st(r, M - k, make_float2(s2.x + e2.y, s2.y - e2.x));
+        }
+      }
+    }
+    gsync<SYNC_WAVE>();
+    RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff, MODE >= 3 ? J.acc + rowoff : nullptr,
+                                    nx,    nrw,   opb != nullptr,  first, geo,
+                                    J.eps, J.lamp, 1.f / (float)J.nviews, 0.0, 0u, 0u, false};
+    CtRun<true, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, op);
+    flux = op.flux;
+    ncr = op.ncr;
+    ncn = op.ncn;
+    bad = op.bad;
+    if (MODE == 1 || (UPD && (opt & XOPT_SPEC))) {
+      Plain<LdsRow<M>> out{L};
+      CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, out);
+    }
+  }
+
+  if (MODE == 0 || MODE == 1 || (UPD && (opt & XOPT_SPEC))) {
+    // half spectrum of the rows from the M-point transform
+#pragma unroll
+    for (int i = 0; i < NPIT; ++i) {
+      const int it = lane + i * 64;
+      const int r = it / NPAIR, k = it % NPAIR;
+      if (r < nrw) {
+        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        const float2 zk = L.ld(r, k);
+        if (k == 0) {
+          spec[rbase] = make_float2(zk.x + zk.y, 0.f);
+          nyq[wrow0 + r] = make_float2(zk.x - zk.y, 0.f);
+        } else {
+          const float2 zm = L.ld(r, M - k);
+          const float2 t = s_pp[k];
+          const float2 s = make_float2(zk.x + zm.x, zk.y - zm.y);
+          const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+          const float2 e = cmul(t, d);
+          spec[rbase + k] = make_float2(0.5f * (s.x + e.y), 0.5f * (s.y - e.x));
+          if (2 * k != M) {
+            const float2 s2 = make_float2(zm.x + zk.x, zm.y - zk.y);
+            const float2 d2 = make_float2(zm.x - zk.x, zm.y + zk.y);
+            const float2 e2 = cmul(cconj(t), d2);
+            spec[rbase + M - k] = make_float2(0.5f * (s2.x - e2.y), 0.5f * (s2.y + e2.x));
+          }
+        }
+      }
+    }
+  }
+
+  if (MODE != 0) {
+    if (UPD && bad) atomicOr(flags, 1);
+    if (parts) {
+      block_reduce<T>(flux, ncr, ncn, rf, ra, rb);
+      if (tid == 0) {
+        if (MODE == 1) {
+          parts[blockIdx.x].ratio_clamps = ncr;
+        } else {
+          parts[blockIdx.x].flux = flux;
+          parts[blockIdx.x].neg_clamps = ncn;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace mvdk

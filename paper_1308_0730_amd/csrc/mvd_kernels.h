@@ -28,7 +28,10 @@ int mvd_num_cfgs(int kind);
 int mvd_cfg_threads(int kind, int cfg);
 int mvd_cfg_param(int kind, int cfg);   // rows (x) or lines (y, z) per tile
 int mvd_cfg_maxlen(int kind, int cfg);  // largest transform length it accepts
-int mvd_cfg_exact(int kind, int cfg);   // > 0: compile-time plan for exactly this length
+int mvd_cfg_exact(int kind, int cfg);   // > 0: compile-time plan for exactly this length;
+                                        // -1: the per-length compile-time plans (mvd_exact_cfg)
+int mvd_exact_cfg(int kind);            // index of the per-length compile-time plans
+int mvd_exact_param(int kind, int len); // rows (x) or lines (y, z) per tile of that plan, 0 if none
 
 // compile-time candidates (mvd_kernels_ct.hip), indexed from 0
 int mvd_ct_num_cfgs(int kind);
@@ -59,3 +62,14 @@ hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int co
                            const float2* s_in, double2* acc, int acc_mode);
 hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
                              hipStream_t s);
+
+// compile-time plans for every 5-smooth length (mvd_exact_*.hip); a launch
+// covers jobs that all have length L (y: ny, z: nz) or half-row length M (x).
+// The shape queries return 0 when no plan exists for the length.
+int mvd_exact_col_shape(int L, int* threads, int* lines);
+int mvd_exact_row_shape(int M, int* waves, int* rows);
+hipError_t mvd_launch_y_exact(const LaunchArgs& a, int L, int inv, int v);
+hipError_t mvd_launch_z_exact(const LaunchArgs& a, int L, int v, int role, int conjH, int src_saved);
+hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt);
+hipError_t mvd_launch_x_exact_comb(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
+                                   int opt);

@@ -471,22 +471,34 @@ static const int kRowCfg[][3] = {
 #undef X
 };
 
-// Candidate indices: the runtime-plan shapes first, then the compile-time
-// ones (exact length only).
+// Candidate indices: the runtime-plan shapes first, then the tuned
+// compile-time ones (one exact length each), then one index for the
+// compile-time plans of every 5-smooth length, launched per group of jobs of
+// equal length (its shape depends on the length).
 static int rt_num(int kind) {
   return kind == PASS_X ? (int)(sizeof(kRowCfg) / sizeof(kRowCfg[0]))
                         : (int)(sizeof(kColCfg) / sizeof(kColCfg[0]));
 }
-int mvd_num_cfgs(int kind) { return rt_num(kind) + mvd_ct_num_cfgs(kind); }
+int mvd_exact_cfg(int kind) { return rt_num(kind) + mvd_ct_num_cfgs(kind); }
+int mvd_num_cfgs(int kind) { return mvd_exact_cfg(kind) + 1; }
 static int cfg_field(int kind, int cfg, int f) {
   const int n = rt_num(kind);
+  if (cfg == mvd_exact_cfg(kind)) return f == 2 ? (kind == PASS_X ? 256 : 512) : 0;
   if (cfg >= n) return mvd_ct_cfg(kind, cfg - n, f);
   return kind == PASS_X ? kRowCfg[cfg][f] : kColCfg[cfg][f];
 }
 int mvd_cfg_threads(int kind, int cfg) { return cfg_field(kind, cfg, 0); }
 int mvd_cfg_param(int kind, int cfg) { return cfg_field(kind, cfg, 1); }
 int mvd_cfg_maxlen(int kind, int cfg) { return cfg_field(kind, cfg, 2); }
-int mvd_cfg_exact(int kind, int cfg) { return cfg >= rt_num(kind) ? cfg_field(kind, cfg, 2) : 0; }
+int mvd_cfg_exact(int kind, int cfg) {
+  if (cfg == mvd_exact_cfg(kind)) return -1;
+  return cfg >= rt_num(kind) ? cfg_field(kind, cfg, 2) : 0;
+}
+int mvd_exact_param(int kind, int len) {
+  int a = 0, b = 0;
+  if (kind == PASS_X) return mvd_exact_row_shape(len, &a, &b) ? a * b : 0;
+  return mvd_exact_col_shape(len, &a, &b) ? b : 0;
+}
 
 hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags, int opt) {
   if (mode < 0 || mode > 4) return hipErrorInvalidValue;

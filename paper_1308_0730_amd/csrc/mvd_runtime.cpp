@@ -76,6 +76,15 @@ struct mvd_handle {
   int force_cfg = 0;
   // device tables
   JobDesc* d_jobs = nullptr;
+  // per pass kind: the job table sorted by that kind's length, and the
+  // groups of equal length launched one by one with the per-length
+  // compile-time plans
+  struct Group {
+    int len, first, njobs, grid, part_off;
+  };
+  JobDesc* d_jobs_k[3] = {nullptr, nullptr, nullptr};
+  std::vector<int> order[3];
+  std::vector<Group> groups[3];
   FftPlan* d_plans = nullptr;
   float2* d_tw = nullptr;
   Partial* d_parts = nullptr;
@@ -300,18 +309,20 @@ bool cfg_fits(const mvd_handle* h, int kind, int c);
 // common power-of-two lengths, then the smallest runtime-plan family).
 int pick_cfg(const mvd_handle* h, int kind) {
   if (h->force_cfg > 0 && cfg_fits(h, kind, h->force_cfg - 1)) return h->force_cfg - 1;
-  const int nrt = mvd_num_cfgs(kind) - mvd_ct_num_cfgs(kind);
+  const int nrt = mvd_exact_cfg(kind) - mvd_ct_num_cfgs(kind);
   // compile-time candidates in order of preference
   static const int ct_x[] = {0, 3, 4, 5, 6};
   static const int ct_c[] = {0, 3, 6, 7};
   if (kind == PASS_X) {
     for (int c : ct_x)
       if (cfg_fits(h, kind, nrt + c)) return nrt + c;
+    if (cfg_fits(h, kind, mvd_exact_cfg(kind))) return mvd_exact_cfg(kind);
     for (int c : {0, 1, 2, 3, 4})
       if (cfg_fits(h, kind, c)) return c;
   } else {
     for (int c : ct_c)
       if (cfg_fits(h, kind, nrt + c)) return nrt + c;
+    if (cfg_fits(h, kind, mvd_exact_cfg(kind))) return mvd_exact_cfg(kind);
     for (int c : {0, 1, 2, 3})
       if (cfg_fits(h, kind, c)) return c;
   }
@@ -324,6 +335,9 @@ int total_tiles(const mvd_handle* h, int kind, int param) {
   if (t > 0x7fffffff) bad("too many tiles");
   return (int)t;
 }
+
+// Transform length of a pass kind in a block: x the half-row nx/2, y ny, z nz.
+int job_len(const Block& B, int kind) { return kind == PASS_X ? B.M : kind == PASS_Y ? B.ny : B.nz; }
 
 void build_jobs(mvd_handle* h) {
   h->jobs.clear();
@@ -358,6 +372,17 @@ void build_jobs(mvd_handle* h) {
   }
   HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                           h->stream));
+  for (int k = 0; k < 3; ++k) {
+    auto& ord = h->order[k];
+    ord.resize(h->jobs.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return job_len(h->blocks[a], k) < job_len(h->blocks[b], k); });
+    std::vector<JobDesc> sorted;
+    for (int i : ord) sorted.push_back(h->jobs[i]);
+    HIPCHECK(hipMemcpyAsync(h->d_jobs_k[k], sorted.data(), sorted.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
+                            h->stream));
+  }
   HIPCHECK(hipStreamSynchronize(h->stream));
 }
 
@@ -365,6 +390,11 @@ void build_jobs(mvd_handle* h) {
 // grows the partials buffer and drops the cached graphs.
 bool cfg_fits(const mvd_handle* h, int kind, int c) {
   if (c < 0 || c >= mvd_num_cfgs(kind)) return false;
+  if (c == mvd_exact_cfg(kind)) {
+    for (const auto& B : h->blocks)
+      if (mvd_exact_param(kind, job_len(B, kind)) <= 0) return false;
+    return true;
+  }
   const int ex = mvd_cfg_exact(kind, c);
   if (ex > 0) return h->uniform_len[kind] == ex;
   return mvd_cfg_maxlen(kind, c) >= h->max_len[kind];
@@ -376,9 +406,34 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
     if (c[k] < 0 || c[k] >= mvd_num_cfgs(k)) bad("tile configuration index out of range");
     if (!cfg_fits(h, k, c[k])) bad("tile configuration does not fit the transform lengths of this handle");
   }
-  const int gx = total_tiles(h, PASS_X, mvd_cfg_param(PASS_X, cx));
-  const int gy = total_tiles(h, PASS_Y, mvd_cfg_param(PASS_Y, cy));
-  const int gz = total_tiles(h, PASS_Z, mvd_cfg_param(PASS_Z, cz));
+  int g[3];
+  for (int k = 0; k < 3; ++k) {
+    h->groups[k].clear();
+    if (c[k] != mvd_exact_cfg(k)) {
+      g[k] = total_tiles(h, k, mvd_cfg_param(k, c[k]));
+      continue;
+    }
+    // groups of equal length in the sorted job order
+    int64_t tiles = 0;
+    const auto& ord = h->order[k];
+    for (size_t i = 0; i < ord.size();) {
+      const int len = job_len(h->blocks[ord[i]], k);
+      const int param = mvd_exact_param(k, len);
+      mvd_handle::Group gr{len, (int)i, 0, 0, (int)tiles};
+      int64_t gt = 0;
+      for (; i < ord.size() && job_len(h->blocks[ord[i]], k) == len; ++i) {
+        gt += mvd_tiles(h->jobs[ord[i]], k, param);
+        ++gr.njobs;
+      }
+      if (gt > 0x7fffffff) bad("too many tiles");
+      gr.grid = (int)gt;
+      tiles += gt;
+      h->groups[k].push_back(gr);
+    }
+    if (tiles > 0x7fffffff) bad("too many tiles");
+    g[k] = (int)tiles;
+  }
+  const int gx = g[0], gy = g[1], gz = g[2];
   if ((size_t)h->nviews * gx > h->parts_cap) {
     h->d_parts = (Partial*)h->dalloc((size_t)h->nviews * gx * sizeof(Partial));
     h->parts_cap = (size_t)h->nviews * gx;
@@ -529,6 +584,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
   HIPCHECK(hipMemcpyAsync(h->d_plans, plans.data(), plans.size() * sizeof(FftPlan), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, h->stream));
   h->d_jobs = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
+  for (int k = 0; k < 3; ++k) h->d_jobs_k[k] = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
 
   int maxM = 0, maxY = 0, maxZ = 0;
   for (auto& B : h->blocks) {
@@ -586,6 +642,43 @@ LaunchArgs args(mvd_handle* h, hipStream_t s, int grid) {
   return a;
 }
 
+// One pass of each kind with the handle's launch shape: one launch over all
+// jobs, or with the per-length compile-time plans one launch per group of
+// jobs of equal length (x partials of a group start at its tile offset).
+LaunchArgs group_args(mvd_handle* h, hipStream_t s, int kind, const mvd_handle::Group& g) {
+  LaunchArgs a = args(h, s, g.grid);
+  a.jobs = h->d_jobs_k[kind] + g.first;
+  a.njobs = g.njobs;
+  return a;
+}
+
+void run_x(mvd_handle* h, hipStream_t s, int mode, int v, Partial* parts, int opt) {
+  if (h->cfg_x != mvd_exact_cfg(PASS_X)) {
+    HIPCHECK(mvd_launch_x(args(h, s, h->grid_x), h->cfg_x, mode, v, parts, h->d_flags, opt));
+    return;
+  }
+  for (const auto& g : h->groups[PASS_X])
+    HIPCHECK(mvd_launch_x_exact(group_args(h, s, PASS_X, g), g.len, mode, v, parts ? parts + g.part_off : nullptr,
+                                h->d_flags, opt));
+}
+
+void run_y(mvd_handle* h, hipStream_t s, int inv, int v) {
+  if (h->cfg_y != mvd_exact_cfg(PASS_Y)) {
+    HIPCHECK(mvd_launch_y(args(h, s, h->grid_y), h->cfg_y, inv, v));
+    return;
+  }
+  for (const auto& g : h->groups[PASS_Y]) HIPCHECK(mvd_launch_y_exact(group_args(h, s, PASS_Y, g), g.len, inv, v));
+}
+
+void run_z(mvd_handle* h, hipStream_t s, int v, int role, int conjH, int src_saved) {
+  if (h->cfg_z != mvd_exact_cfg(PASS_Z)) {
+    HIPCHECK(mvd_launch_z(args(h, s, h->grid_z), h->cfg_z, v, role, conjH, src_saved));
+    return;
+  }
+  for (const auto& g : h->groups[PASS_Z])
+    HIPCHECK(mvd_launch_z_exact(group_args(h, s, PASS_Z, g), g.len, v, role, conjH, src_saved));
+}
+
 // Per-launch event timing of the passes (profiling hook): kinds are
 // 0 y forward, 1 y inverse, 2 z product, 3 x ratio, 4 x update.
 struct PassTimer {
@@ -611,33 +704,22 @@ struct PassTimer {
 void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t = nullptr) {
   const int role = variant == MVD_RL ? ROLE_P : variant;
   const int conj_back = variant == MVD_RL ? 1 : 0;
-  const LaunchArgs ax = args(h, s, h->grid_x), ay = args(h, s, h->grid_y), az = args(h, s, h->grid_z);
   Partial* parts = h->d_parts + (size_t)v * h->grid_x;
-  auto run = [&](int kind, hipError_t (*fn)(mvd_handle*, const LaunchArgs&, int, int, int, Partial*),
-                 const LaunchArgs& a, int p0, int p1) {
+  auto timed = [&](int kind, auto&& fn) {
     if (t) t->mark(kind);
-    HIPCHECK(fn(h, a, v, p0, p1, parts));
+    fn();
     if (t) t->done();
   };
-  auto yp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int inv, int, Partial*) {
-    return mvd_launch_y(a, hh->cfg_y, inv, vv);
-  };
-  auto zp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int rl, int cj, Partial*) {
-    return mvd_launch_z(a, hh->cfg_z, vv, rl, cj);
-  };
-  auto xp = [](mvd_handle* hh, const LaunchArgs& a, int vv, int mode, int, Partial* pp) {
-    return mvd_launch_x(a, hh->cfg_x, mode, vv, pp, hh->d_flags, 1);
-  };
   // b = psi (x) P_v, then q = phi_v / max(b, eps)
-  run(0, yp, ay, 0, 0);
-  run(2, zp, az, ROLE_P, 0);
-  run(1, yp, ay, 1, 0);
-  run(3, xp, ax, 1, 0);
+  timed(0, [&] { run_y(h, s, 0, v); });
+  timed(2, [&] { run_z(h, s, v, ROLE_P, 0, 0); });
+  timed(1, [&] { run_y(h, s, 1, v); });
+  timed(3, [&] { run_x(h, s, 1, v, parts, XOPT_SPEC); });
   // c = q (x) K_v, then the update of psi
-  run(0, yp, ay, 0, 0);
-  run(2, zp, az, role, conj_back);
-  run(1, yp, ay, 1, 0);
-  run(4, xp, ax, 2, 0);
+  timed(0, [&] { run_y(h, s, 0, v); });
+  timed(2, [&] { run_z(h, s, v, role, conj_back, 0); });
+  timed(1, [&] { run_y(h, s, 1, v); });
+  timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
 }
 
 // One iteration: every view once, in index order (section 7).
@@ -655,24 +737,23 @@ void enqueue_combined_iteration(mvd_handle* h, hipStream_t s, int variant, bool 
   const int role = variant == MVD_RL ? ROLE_P : variant;
   const int conj_back = variant == MVD_RL ? 1 : 0;
   const int N = h->nviews;
-  const LaunchArgs ax = args(h, s, h->grid_x), ay = args(h, s, h->grid_y), az = args(h, s, h->grid_z);
-  HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, 0));
+  run_y(h, s, 0, 0);
   for (const auto& B : h->blocks)
     HIPCHECK(hipMemcpyAsync(B.saved, B.spec, B.spec_elems * 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
   const int mean = geo ? XOPT_GEO : 0;
   for (int v = 0; v < N; ++v) {
     Partial* parts = h->d_parts + (size_t)v * h->grid_x;
-    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, ROLE_P, 0, 1));
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
-    HIPCHECK(mvd_launch_x(ax, h->cfg_x, 1, v, parts, h->d_flags, XOPT_SPEC));
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 0, v));
-    HIPCHECK(mvd_launch_z(az, h->cfg_z, v, role, conj_back, 0));
-    HIPCHECK(mvd_launch_y(ay, h->cfg_y, 1, v));
+    run_z(h, s, v, ROLE_P, 0, 1);
+    run_y(h, s, 1, v);
+    run_x(h, s, 1, v, parts, XOPT_SPEC);
+    run_y(h, s, 0, v);
+    run_z(h, s, v, role, conj_back, 0);
+    run_y(h, s, 1, v);
     const int first = v == 0 ? XOPT_FIRST : 0;
     if (v < N - 1)
-      HIPCHECK(mvd_launch_x(ax, h->cfg_x, 3, v, parts, h->d_flags, first | mean));
+      run_x(h, s, 3, v, parts, first | mean);
     else
-      HIPCHECK(mvd_launch_x(ax, h->cfg_x, 4, v, parts, h->d_flags, first | mean | XOPT_SPEC));
+      run_x(h, s, 4, v, parts, first | mean | XOPT_SPEC);
   }
 }
 
@@ -696,7 +777,7 @@ void prepare_run(mvd_handle* h, int variant) {
   const int role = variant == MVD_RL ? ROLE_P : variant;
   ensure_role(h, role);
   if (!h->spec_valid) {
-    HIPCHECK(mvd_launch_x(args(h, h->stream, h->grid_x), h->cfg_x, 0, 0, nullptr, h->d_flags, 1));
+    run_x(h, h->stream, 0, 0, nullptr, XOPT_SPEC);
     h->spec_valid = true;
   }
 }

@@ -28,31 +28,37 @@ def block(dims, seed):
     return s.views, s.psfs, w
 
 
-def runtime_tiles(mvd, lens):
-    """The first runtime-plan candidate of each pass kind (any length)."""
+def tiles_of(mvd, lens, exact_len):
+    """The first candidate of each pass kind with the given exact_len field:
+    0 = runtime plan (any length), -1 = the per-length compile-time plans."""
     out = []
     for kind in range(3):
         for c in mvd.tile_candidates(kind, lens[kind]):
-            if mvd.tile_shape(kind, c)["exact_len"] == 0:
+            if mvd.tile_shape(kind, c)["exact_len"] == exact_len:
                 out.append(c)
                 break
     return out
 
 
+@pytest.mark.parametrize("mode", [0, -1])
 @pytest.mark.parametrize("variant", [O.RL, O.EFF])
-def test_batched_equals_plain_per_block(mvd, variant):
+def test_batched_equals_plain_per_block(mvd, variant, mode):
+    """With the same kind of plan on both sides (runtime plans, or the
+    compile-time plan of each length launched per group of equal length) the
+    batched form gives every block's plain result bitwise."""
     blocks = [block(d, 100 + i) for i, d in enumerate(DIMS)]
     with mvd.Deconvolver.batch(blocks, lam=0.01) as b:
+        b.set_tiles(*tiles_of(mvd, b.max_lengths(), mode))
         b.iterate(3, variant)
         got = [b.estimate(i).cpu().numpy() for i in range(len(DIMS))]
         st = b.stats()
     assert st["n_blocks"] == len(DIMS) and not st["nonfinite"]
     for i, (v, p, w) in enumerate(blocks):
         with mvd.Deconvolver(v, p, w, lam=0.01) as d:
-            d.set_tiles(*runtime_tiles(mvd, d.max_lengths()))
+            d.set_tiles(*tiles_of(mvd, d.max_lengths(), mode))
             d.iterate(3, variant)
             ref = d.estimate().cpu().numpy()
-        # same per-line arithmetic (runtime plans of the same lengths): bitwise
+        # same per-line arithmetic (the same plans of the same lengths): bitwise
         np.testing.assert_array_equal(got[i], ref)
 
 
@@ -69,10 +75,12 @@ def test_batched_matches_oracle(mvd):
 
 
 def test_batched_every_launch_shape(mvd):
-    """Every runtime-plan shape of every kind, on blocks of unequal lengths."""
+    """Every runtime-plan shape of every kind, on blocks of unequal lengths,
+    gives the same result bitwise (the same radix plans of the same lengths)."""
     blocks = [block(d, 300 + i) for i, d in enumerate(DIMS[:3])]
     with mvd.Deconvolver.batch(blocks) as b:
-        base = b.tiles()
+        base = tiles_of(mvd, b.max_lengths(), 0)
+        b.set_tiles(*base)
         b.iterate(1, O.EFF)
         ref = [b.estimate(i).cpu().numpy() for i in range(3)]
         psi1 = [r.copy() for r in ref]
