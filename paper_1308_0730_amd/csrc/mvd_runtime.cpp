@@ -81,7 +81,14 @@ struct mvd_handle {
   // compile-time plans
   struct Group {
     int len, first, njobs, grid, part_off;
+    int lane;  // 0: the pass's stream, 1..kSide: side stream lane - 1
   };
+  // side streams (default priority) that run groups of one pass concurrently,
+  // forked from and joined back into the pass's stream with events
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSide] = {};
   JobDesc* d_jobs_k[3] = {nullptr, nullptr, nullptr};
   std::vector<int> order[3];
   std::vector<Group> groups[3];
@@ -158,6 +165,14 @@ struct mvd_handle {
     allocs.clear();
     if (cap) (void)hipStreamDestroy(cap);
     cap = nullptr;
+    for (int i = 0; i < kSide; ++i) {
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+      if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+      side[i] = nullptr;
+      ev_join[i] = nullptr;
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    ev_fork = nullptr;
   }
 };
 
@@ -432,6 +447,18 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
     }
     if (tiles > 0x7fffffff) bad("too many tiles");
     g[k] = (int)tiles;
+    // lanes: largest group first onto the least loaded lane
+    std::vector<int> idx(h->groups[k].size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h->groups[k][a].grid > h->groups[k][b].grid; });
+    int64_t load[1 + mvd_handle::kSide] = {};
+    for (int i : idx) {
+      int best = 0;
+      for (int l = 1; l <= mvd_handle::kSide; ++l)
+        if (load[l] < load[best]) best = l;
+      h->groups[k][i].lane = best;
+      load[best] += h->groups[k][i].grid;
+    }
   }
   const int gx = g[0], gy = g[1], gz = g[2];
   if ((size_t)h->nviews * gx > h->parts_cap) {
@@ -492,6 +519,11 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
 
   HIPCHECK(hipGetDevice(&h->device));
   HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  for (int i = 0; i < mvd_handle::kSide; ++i) {
+    HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
+  }
+  HIPCHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
 
   std::vector<FftPlan> plans;
   std::vector<float2> tw;
@@ -652,14 +684,38 @@ LaunchArgs group_args(mvd_handle* h, hipStream_t s, int kind, const mvd_handle::
   return a;
 }
 
+// The groups of one pass: each on its lane's stream; side lanes are forked
+// from s by an event and joined back before the pass is complete, so the
+// next pass on s sees every group's writes.
+template <class F>
+void run_groups(mvd_handle* h, hipStream_t s, int kind, F&& launch) {
+  unsigned used = 0;
+  for (const auto& g : h->groups[kind]) used |= 1u << g.lane;
+  const bool fork = (used & ~1u) != 0;
+  if (fork) {
+    HIPCHECK(hipEventRecord(h->ev_fork, s));
+    for (int l = 1; l <= mvd_handle::kSide; ++l)
+      if (used & (1u << l)) HIPCHECK(hipStreamWaitEvent(h->side[l - 1], h->ev_fork, 0));
+  }
+  for (const auto& g : h->groups[kind]) HIPCHECK(launch(g, g.lane ? h->side[g.lane - 1] : s));
+  if (fork) {
+    for (int l = 1; l <= mvd_handle::kSide; ++l)
+      if (used & (1u << l)) {
+        HIPCHECK(hipEventRecord(h->ev_join[l - 1], h->side[l - 1]));
+        HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l - 1], 0));
+      }
+  }
+}
+
 void run_x(mvd_handle* h, hipStream_t s, int mode, int v, Partial* parts, int opt) {
   if (h->cfg_x != mvd_exact_cfg(PASS_X)) {
     HIPCHECK(mvd_launch_x(args(h, s, h->grid_x), h->cfg_x, mode, v, parts, h->d_flags, opt));
     return;
   }
-  for (const auto& g : h->groups[PASS_X])
-    HIPCHECK(mvd_launch_x_exact(group_args(h, s, PASS_X, g), g.len, mode, v, parts ? parts + g.part_off : nullptr,
-                                h->d_flags, opt));
+  run_groups(h, s, PASS_X, [&](const mvd_handle::Group& g, hipStream_t st) {
+    return mvd_launch_x_exact(group_args(h, st, PASS_X, g), g.len, mode, v, parts ? parts + g.part_off : nullptr,
+                              h->d_flags, opt);
+  });
 }
 
 void run_y(mvd_handle* h, hipStream_t s, int inv, int v) {
@@ -667,7 +723,9 @@ void run_y(mvd_handle* h, hipStream_t s, int inv, int v) {
     HIPCHECK(mvd_launch_y(args(h, s, h->grid_y), h->cfg_y, inv, v));
     return;
   }
-  for (const auto& g : h->groups[PASS_Y]) HIPCHECK(mvd_launch_y_exact(group_args(h, s, PASS_Y, g), g.len, inv, v));
+  run_groups(h, s, PASS_Y, [&](const mvd_handle::Group& g, hipStream_t st) {
+    return mvd_launch_y_exact(group_args(h, st, PASS_Y, g), g.len, inv, v);
+  });
 }
 
 void run_z(mvd_handle* h, hipStream_t s, int v, int role, int conjH, int src_saved) {
@@ -675,8 +733,9 @@ void run_z(mvd_handle* h, hipStream_t s, int v, int role, int conjH, int src_sav
     HIPCHECK(mvd_launch_z(args(h, s, h->grid_z), h->cfg_z, v, role, conjH, src_saved));
     return;
   }
-  for (const auto& g : h->groups[PASS_Z])
-    HIPCHECK(mvd_launch_z_exact(group_args(h, s, PASS_Z, g), g.len, v, role, conjH, src_saved));
+  run_groups(h, s, PASS_Z, [&](const mvd_handle::Group& g, hipStream_t st) {
+    return mvd_launch_z_exact(group_args(h, st, PASS_Z, g), g.len, v, role, conjH, src_saved);
+  });
 }
 
 // Per-launch event timing of the passes (profiling hook): kinds are
