@@ -59,4 +59,4 @@ def loss_and_theta_grad(handle, n_iter, psi0, theta, angles, extent_xyz):
     psfs = [psf_from_theta(th[v, 0], th[v, 1], angles[v], extent_xyz) for v in range(len(angles))]
     L = MVDLoss.apply(handle, n_iter, psi0, *psfs)
     L.backward()
-    return float(L), th.grad.numpy().copy()
+    return float(L.detach()), th.grad.numpy().copy()

@@ -86,6 +86,46 @@ struct Plain {
   __device__ __forceinline__ void st(int line, int pos, float2 v, int, int) const { a.st(line, pos, v); }
 };
 
+// First-stage inputs already loaded into registers (by ct_prefetch), in the
+// order the first stage reads them: a source that issues no loads.
+template <int MAXB, int R>
+struct RegSrc {
+  const float2 (&v)[MAXB][R];
+  static constexpr bool lds = false;
+};
+template <class S>
+struct IsRegSrc {
+  static constexpr bool value = false;
+};
+template <int MAXB, int R>
+struct IsRegSrc<RegSrc<MAXB, R>> {
+  static constexpr bool value = true;
+};
+
+// Butterfly slots of the first stage of a plan with first radix R.
+template <int L, int R, int T, int NL>
+struct FirstMap {
+  static constexpr int MAXB = ((L / R) * NL + T - 1) / T;
+};
+
+// Issue the loads of the first stage of a plan (first radix R) into v.
+template <int L, int R, int T, int NL, bool LF, class S>
+__device__ __forceinline__ void ct_prefetch(int tid, const S& src, float2 (&v)[FirstMap<L, R, T, NL>::MAXB][R]) {
+  constexpr int NB = L / R;
+  constexpr int TOTAL = NB * NL;
+  constexpr int MAXB = FirstMap<L, R, T, NL>::MAXB;
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int it = tid + i * T;
+    const int line = LF ? it % NL : it / NB;
+    const int j = LF ? it / NL : it % NB;
+    if ((TOTAL % T == 0) || it < TOTAL) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src.ld(line, j + r * NB);
+    }
+  }
+}
+
 // One stage of a compile-time plan: radix R, length L, NS = product of the
 // earlier radices, T threads, NL lines, line-fast (LF) or position-fast.
 template <int R, bool INV, int L, int NS, int T, int NL, bool LF, int SY, class S, class D>
@@ -107,8 +147,13 @@ __device__ __forceinline__ void ct_stage(int tid_in, const float2* tw, const S& 
     ln[i] = line;
     jb[i] = j;
     if (FULL || it < TOTAL) {
+      if constexpr (IsRegSrc<S>::value) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src.ld(line, j + r * NB);
+        for (int r = 0; r < R; ++r) v[i][r] = src.v[i][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i][r] = src.ld(line, j + r * NB);
+      }
     }
   }
   if (S::lds == D::lds) gsync<SY>();
@@ -157,6 +202,11 @@ struct CtRun {
       CtRun<INV, L, T, NL, LF, SY, NS * R, false, Rest...>::run(tid, tw, src, mid, dst);
     }
   }
+};
+
+template <int R, int... Rest>
+struct FirstRadix {
+  static constexpr int value = R;
 };
 
 template <int R, int... Rest>

@@ -47,6 +47,20 @@ struct MulH {
   }
 };
 
+// Global tile read with unconditional loads: a line past nl reads line
+// nl - 1 (a ragged tile's extra lines are transformed but never stored, and
+// their kernel lines are zero).  With no load inside a branch the compiler
+// knows how many loads follow a given one, so waiting for an earlier load
+// does not drain these.
+struct GTileU {
+  const float2* base;
+  int ls, ps, nl;
+  static constexpr bool lds = false;
+  __device__ __forceinline__ float2 ld(int line, int pos) const {
+    return ldg(base + (line < nl ? line : nl - 1) * ls + pos * ps);
+  }
+};
+
 // Last forward z stage of the kernel lines: keep the outputs in registers,
 // in the order the data's last forward stage produces its own.
 template <int MAXB, int R>
@@ -193,17 +207,39 @@ __global__ void __launch_bounds__(T)
   const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, L,
                  J.kz, J.cz};
   GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
-  const GTile gin{reinterpret_cast<float2*>(src_saved ? J.saved : J.spec) + off, 1, ps, nl};
-  load_table<T>(s_tw, twp + plans[J.plan_z].tw, L);
+  const GTileU gin{reinterpret_cast<const float2*>(src_saved ? J.saved : J.spec) + off, 1, ps, nl};
+  // both tiles' first-stage loads up front, the kernel taps first: the
+  // kernel lines' transform then waits only for its own loads and runs while
+  // the data loads are in flight
+  // (the twiddle table's loads go first and its LDS stores after, so that
+  // storing it waits for its own loads only)
+  constexpr int R1 = FirstRadix<Rs...>::value;
+  constexpr int MB1 = FirstMap<L, R1, T, TX>::MAXB;
+  constexpr int NTW = (L + T - 1) / T;
+  const float2* twsrc = twp + plans[J.plan_z].tw;
+  float2 twv[NTW];
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    const int e = threadIdx.x + i * T;
+    twv[i] = e < L ? ldg(twsrc + e) : make_float2(0.f, 0.f);
+  }
+  float2 kp[MB1][R1], dp[MB1][R1];
+  ct_prefetch<L, R1, T, TX, true>(threadIdx.x, kl, kp);
+  ct_prefetch<L, R1, T, TX, true>(threadIdx.x, gin, dp);
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    const int e = threadIdx.x + i * T;
+    if (e < L) s_tw[e] = twv[i];
+  }
   const LdsCol<TX> S{lds};
   // kernel spectrum of the tile's lines, in the order the last forward stage
   // produces its outputs
   float2 h[LM::MAXB][RL];
   ToRegs<LM::MAXB, RL> kreg{h};
-  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, kl, S, kreg);
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{kp}, S, kreg);
   __syncthreads();
   MulH<TX, LM::MAXB, RL> mul{lds, h, conjH};
-  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, gin, S, mul);
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{dp}, S, mul);
   Plain<GTile> out{g};
   CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
 }
