@@ -210,6 +210,28 @@ int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len,
 int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z);
 int mvd_get_tiles(const mvd_handle* h, int* cfg);
 
+/* Overlap numbers for mvd_normalize_weights (section on partially
+ * overlapping data). */
+#define MVD_OVERLAP_ONE 0  /* 1: the safe choice */
+#define MVD_OVERLAP_MIN 1  /* the minimal number of contributing views over the covered voxels */
+#define MVD_OVERLAP_AVG 2  /* their average number */
+#define MVD_OVERLAP_USER 3 /* `value` (> 0) */
+
+/* Limit each voxel's summed weight over the views to the overlap number m
+ * of its block: where the sum s exceeds m every view's weight there is
+ * multiplied by m / s; weights are never increased (section on partially
+ * overlapping data).  A view contributes at a voxel where its weight is > 0;
+ * "covered" voxels have at least one contributing view.  Rewrites the
+ * handle's weights in place (later iterations use them); m of every block is
+ * written to m_out[n_blocks] when it is not NULL.  MVD_ESTATE for a handle
+ * created without weights; MVD_EINVAL for a bad mode or value.  Synchronises. */
+int mvd_normalize_weights(mvd_handle* h, int mode, double value, double* m_out);
+
+/* The number of contributing views at every voxel of `block`, as floats
+ * (nx*ny*nz, host or device memory): the image the paper offers for
+ * choosing the overlap number.  MVD_ESTATE without weights.  Synchronises. */
+int mvd_contributing_views(mvd_handle* h, float* dst, int dst_kind, int block);
+
 /* Copy the estimate of `block` (0 for the plain form) into dst (nx*ny*nz
  * floats, host or device memory).  Synchronises; returns MVD_ENONFINITE if
  * the estimate became non-finite (the copy is still made). */

@@ -205,6 +205,39 @@ def view_update(psi, phi, P, K, w=None, lam_p=0.0, eps=0.0, conv=circ_conv, stat
     return psi + w * (t - psi)
 
 
+OVERLAP_ONE, OVERLAP_MIN, OVERLAP_AVG, OVERLAP_USER = 0, 1, 2, 3
+
+
+def contributing_views(weights):
+    """Number of views with a non-zero weight at every voxel (the image the
+    section on partially overlapping data offers for choosing the overlap)."""
+    return np.sum([np.asarray(w, dtype=np.float64) > 0 for w in weights], axis=0).astype(np.float64)
+
+
+def normalize_weights(weights, mode=OVERLAP_MIN, value=1.0):
+    """Limit the summed weight of every voxel to an overlap number m
+    (section on partially overlapping data): m = 1 (the safe choice), the
+    minimal or the average number of contributing views over the voxels that
+    any view covers, or a user value.  Where the sum s exceeds m every view's
+    weight is scaled by m / s; weights are never increased."""
+    w = [np.asarray(x, dtype=np.float64) for x in weights]
+    count = contributing_views(w)
+    covered = count > 0
+    if mode == OVERLAP_ONE:
+        m = 1.0
+    elif mode == OVERLAP_MIN:
+        m = float(count[covered].min()) if covered.any() else 1.0
+    elif mode == OVERLAP_AVG:
+        m = float(count[covered].mean()) if covered.any() else 1.0
+    else:
+        m = float(value)
+    s = np.sum(w, axis=0)
+    f = np.ones_like(s)
+    over = s > m
+    f[over] = m / s[over]
+    return [x * f for x in w], m
+
+
 GEOMETRIC, ARITHMETIC = 0, 1
 
 

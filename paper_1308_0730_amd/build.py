@@ -32,6 +32,7 @@ SOURCES = [
     ("mvd_exact_x.hip", True),
     ("mvd_exact_y.hip", True),
     ("mvd_kernels_ct.hip", True),
+    ("mvd_weights.hip", True),
     ("mvd_runtime.cpp", True),
     ("mvd_host.cpp", False),
 ]

@@ -73,3 +73,9 @@ hipError_t mvd_launch_z_exact(const LaunchArgs& a, int L, int v, int role, int c
 hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt);
 hipError_t mvd_launch_x_exact_comb(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
                                    int opt);
+
+// weight normalisation (mvd_weights.hip), on one block's [nviews][V] weights
+hipError_t mvd_launch_overlap_stats(const float* w, int nviews, int64_t V, unsigned* cmin,
+                                    unsigned long long* csum, unsigned long long* ncov, hipStream_t s);
+hipError_t mvd_launch_overlap_limit(float* w, int nviews, int64_t V, float m, hipStream_t s);
+hipError_t mvd_launch_overlap_count(const float* w, int nviews, int64_t V, float* out, hipStream_t s);

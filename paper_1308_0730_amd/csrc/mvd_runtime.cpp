@@ -130,6 +130,12 @@ struct mvd_handle {
   double2* g_t1 = nullptr;                 // z stage of the PSF-gradient inverse DFT
   size_t g_t1_cap = 0;
   unsigned long long *g_lr = nullptr, *g_ln = nullptr;
+  // weight normalisation: overlap statistics, and a staging volume for the
+  // count image when the caller's buffer is in host memory
+  unsigned* w_cmin = nullptr;
+  unsigned long long* w_cnt = nullptr;
+  float* w_stage = nullptr;
+  int64_t w_stage_cap = 0;
   std::string err;
 
   void* dalloc(size_t bytes) {
@@ -1159,6 +1165,63 @@ void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims,
   build_jobs(h);
 }
 
+// Limit every voxel's summed weight to the overlap number of its block (see
+// mvd_weights.hip); m per block into m_out when given.
+void normalize_weights_impl(mvd_handle* h, int mode, double value, double* m_out) {
+  if (mode < MVD_OVERLAP_ONE || mode > MVD_OVERLAP_USER) bad("mode must be one of the MVD_OVERLAP_* values");
+  if (mode == MVD_OVERLAP_USER && !(value > 0 && std::isfinite(value))) bad("the user overlap must be finite and > 0");
+  for (const auto& B : h->blocks)
+    if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
+  if (!h->w_cmin) {
+    h->w_cmin = (unsigned*)h->dalloc(sizeof(unsigned));
+    h->w_cnt = (unsigned long long*)h->dalloc(2 * sizeof(unsigned long long));
+  }
+  unsigned* cmin = h->w_cmin;
+  unsigned long long* cnt = h->w_cnt;
+  for (size_t b = 0; b < h->blocks.size(); ++b) {
+    Block& B = h->blocks[b];
+    double m = mode == MVD_OVERLAP_USER ? value : 1.0;
+    if (mode == MVD_OVERLAP_MIN || mode == MVD_OVERLAP_AVG) {
+      const unsigned init = 0xffffffffu;
+      const unsigned long long zero[2] = {0, 0};
+      HIPCHECK(hipMemcpyAsync(cmin, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
+      HIPCHECK(hipMemcpyAsync(cnt, zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+      HIPCHECK(mvd_launch_overlap_stats(B.w, h->nviews, B.V, cmin, cnt, cnt + 1, h->stream));
+      unsigned mn = 0;
+      unsigned long long c[2] = {0, 0};
+      HIPCHECK(hipMemcpyAsync(&mn, cmin, sizeof(mn), hipMemcpyDeviceToHost, h->stream));
+      HIPCHECK(hipMemcpyAsync(c, cnt, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      if (c[1] > 0) m = mode == MVD_OVERLAP_MIN ? (double)mn : (double)c[0] / (double)c[1];
+    }
+    HIPCHECK(mvd_launch_overlap_limit(B.w, h->nviews, B.V, (float)m, h->stream));
+    if (m_out) m_out[b] = m;
+  }
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+void contributing_views_impl(mvd_handle* h, float* dst, int dst_kind, int block) {
+  if (!dst) bad("dst is NULL");
+  if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
+  if (block < 0 || block >= (int)h->blocks.size()) bad("block index out of range");
+  const Block& B = h->blocks[block];
+  if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
+  if (dst_kind == MVD_MEM_DEVICE) {
+    HIPCHECK(mvd_launch_overlap_count(B.w, h->nviews, B.V, dst, h->stream));
+  } else {
+    if (h->w_stage_cap < B.V) {
+      int64_t cap = 0;
+      for (const auto& X : h->blocks) cap = std::max(cap, X.V);
+      h->w_stage = (float*)h->dalloc(cap * sizeof(float));
+      h->w_stage_cap = cap;
+    }
+    float* tmp = h->w_stage;
+    HIPCHECK(mvd_launch_overlap_count(B.w, h->nviews, B.V, tmp, h->stream));
+    HIPCHECK(hipMemcpyAsync(dst, tmp, B.V * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
 int read_flag(mvd_handle* h) {
   int f = 0;
   HIPCHECK(hipMemcpyAsync(&f, h->d_flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1235,6 +1298,22 @@ int mvd_iterate_combined(mvd_handle* h, int n, int variant, int mean) {
     return MVD_EINVAL;
   }
   return guard(h, [&] { iterate_combined_impl(h, n, variant, mean); });
+}
+
+int mvd_normalize_weights(mvd_handle* h, int mode, double value, double* m_out) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { normalize_weights_impl(h, mode, value, m_out); });
+}
+
+int mvd_contributing_views(mvd_handle* h, float* dst, int dst_kind, int block) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] { contributing_views_impl(h, dst, dst_kind, block); });
 }
 
 int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {

@@ -66,6 +66,8 @@ def lib():
     L.mvd_create_batch.argtypes = [C.POINTER(H), C.c_int, C.POINTER(Problem), C.POINTER(Options)]
     L.mvd_iterate.argtypes = [H, C.c_int, C.c_int]
     L.mvd_iterate_combined.argtypes = [H, C.c_int, C.c_int, C.c_int]
+    L.mvd_normalize_weights.argtypes = [H, C.c_int, C.c_double, C.POINTER(C.c_double)]
+    L.mvd_contributing_views.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_get_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_set_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_stats.argtypes = [H, C.POINTER(Stats)]
@@ -87,7 +89,8 @@ def lib():
                                       C.c_void_p, C.POINTER(C.c_int)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_version.restype = C.c_char_p
-    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_get_estimate",
+    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_normalize_weights",
+                 "mvd_contributing_views", "mvd_get_estimate",
                  "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
@@ -107,6 +110,7 @@ def _variant(v):
 
 
 MEANS = {"geometric": 0, "arithmetic": 1}
+OVERLAPS = {"one": 0, "min": 1, "avg": 2, "user": 3}
 
 
 def _mean(m):
@@ -223,6 +227,22 @@ class Deconvolver:
         merged by the geometric or the arithmetic mean."""
         _check(lib().mvd_iterate_combined(self._h, int(n), _variant(variant), _mean(mean)), self._h)
         return self
+
+    def normalize_weights(self, mode="min", value=0.0):
+        """Limit every voxel's summed weight to the overlap number (1, the
+        minimal or average number of contributing views, or `value`); returns
+        the number used per block."""
+        m = (C.c_double * self.n_blocks)()
+        mode = OVERLAPS[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().mvd_normalize_weights(self._h, mode, float(value), m), self._h)
+        return list(m)
+
+    def contributing_views(self, block=0):
+        """Number of views with a non-zero weight at every voxel (CUDA tensor)."""
+        nx, ny, nz = self.dims[block]
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        _check(lib().mvd_contributing_views(self._h, C.c_void_p(out.data_ptr()), MEM_DEVICE, block), self._h)
+        return out
 
     def view_update(self, view, variant="eff"):
         """One view-update (one line of the sequential scheme)."""
