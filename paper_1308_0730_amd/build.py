@@ -28,6 +28,7 @@ SOURCES = [
     ("mvd_kernels.hip", True),
     ("mvd_adjoint.hip", True),
     ("mvd_exact_z.hip", True),
+    ("mvd_exact_zext.hip", True),
     ("mvd_exact_x_comb.hip", True),
     ("mvd_exact_x.hip", True),
     ("mvd_exact_y.hip", True),

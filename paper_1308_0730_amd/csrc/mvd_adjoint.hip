@@ -343,6 +343,63 @@ __global__ void __launch_bounds__(256)
   T1[idx] = make_double2(sr, si);
 }
 
+// y stage: T2[dz][dy][kx] = sum_ky T1[dz][ky][kx] exp(+2 pi i ky (dy - cy) / ny).
+__global__ void __launch_bounds__(256)
+    k_idft_y(const double2* __restrict__ T1, int M, int ny, int wy, int wz, const double2* __restrict__ twy,
+             double2* __restrict__ T2) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)(M + 1) * wy * wz;
+  if (idx >= total) return;
+  const int kx = (int)(idx % (M + 1));
+  const int64_t rest = idx / (M + 1);
+  const int dy = (int)(rest % wy);
+  const int dz = (int)(rest / wy);
+  const int d = dy - (wy - 1) / 2;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < ny; ++k) {
+    const double2 a = T1[((int64_t)dz * ny + k) * (M + 1) + kx];
+    int64_t m = ((int64_t)k * d) % ny;
+    if (m < 0) m += ny;
+    const double2 w = twy[m];  // exp(-2 pi i m / ny); conjugated below
+    sr += a.x * w.x + a.y * w.y;
+    si += a.y * w.x - a.x * w.y;
+  }
+  T2[idx] = make_double2(sr, si);
+}
+
+// x stage of a real result: out[dz][dy][dx] = sum over the half spectrum kx
+// in [0, M], each kx in (0, M) standing for its Hermitian mirror too, of
+// Re(T2[dz][dy][kx] exp(+2 pi i kx (dx - cx) / nx)).
+__global__ void __launch_bounds__(256)
+    k_idft_x(const double2* __restrict__ T2, int M, int nx, int wx, int wy, int wz, const double2* __restrict__ twx,
+             double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)wx * wy * wz;
+  if (idx >= total) return;
+  const int dx = (int)(idx % wx);
+  const int64_t zy = idx / wx;  // dz * wy + dy
+  const int d = dx - (wx - 1) / 2;
+  const double2* t = T2 + zy * (M + 1);
+  double s = 0.0;
+  for (int k = 0; k <= M; ++k) {
+    const double2 a = t[k];
+    int64_t m = ((int64_t)k * d) % nx;
+    if (m < 0) m += nx;
+    const double2 w = twx[m];
+    const double re = a.x * w.x + a.y * w.y;  // Re(a conj(w))
+    s += (k == 0 || k == M) ? re : 2.0 * re;
+  }
+  out[idx] = s;
+}
+
+hipError_t mvd_launch_idft_yx(const double2* T1, int M, int nx, int ny, int wx, int wy, int wz, const double2* twx,
+                              const double2* twy, double2* T2, double* out, hipStream_t s) {
+  const int64_t n2 = (int64_t)(M + 1) * wy * wz, n3 = (int64_t)wx * wy * wz;
+  k_idft_y<<<(unsigned)((n2 + 255) / 256), 256, 0, s>>>(T1, M, ny, wy, wz, twy, T2);
+  k_idft_x<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(T2, M, nx, wx, wy, wz, twx, out);
+  return hipGetLastError();
+}
+
 hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
                              hipStream_t s) {
   const int64_t total = (int64_t)(M + 1) * ny * wz;

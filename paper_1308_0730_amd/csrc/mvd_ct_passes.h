@@ -61,6 +61,44 @@ struct GTileU {
   }
 };
 
+// Last forward z stage of the differentiated form's z pass: besides the
+// product (as MulH) it stores the forward spectrum (s_out) and adds the FP64
+// PSF cross-spectrum term a conj(s) (mode 0) or conj(a) s (mode 1) with s
+// read from s_in, at the tile's spectrum index off + line + pos ps.
+template <int TX, int MAXB, int R>
+struct ExtMul {
+  float2* buf;
+  const float2 (&h)[MAXB][R];
+  int conj;
+  int64_t off;
+  int ps, nl;
+  float2* s_out;
+  const float2* s_in;
+  double2* acc;
+  int acc_mode;
+  static constexpr bool lds = true;
+  __device__ __forceinline__ void st(int line, int pos, float2 a, int i, int r) {
+    if (line < nl) {
+      const int64_t idx = off + line + (int64_t)pos * ps;
+      if (s_out) stg(s_out + idx, a);
+      if (acc) {
+        const float2 s = ldg(s_in + idx);
+        double2 t = ldg(acc + idx);
+        if (acc_mode == 0) {
+          t.x += (double)a.x * s.x + (double)a.y * s.y;
+          t.y += (double)a.y * s.x - (double)a.x * s.y;
+        } else {
+          t.x += (double)a.x * s.x + (double)a.y * s.y;
+          t.y += (double)a.x * s.y - (double)a.y * s.x;
+        }
+        stg(acc + idx, t);
+      }
+    }
+    const float2 w = h[i][r];
+    buf[pos * TX + line] = cmul(a, conj ? cconj(w) : w);
+  }
+};
+
 // Last forward z stage of the kernel lines: keep the outputs in registers,
 // in the order the data's last forward stage produces its own.
 template <int MAXB, int R>
@@ -240,6 +278,73 @@ __global__ void __launch_bounds__(T)
   __syncthreads();
   MulH<TX, LM::MAXB, RL> mul{lds, h, conjH};
   CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{dp}, S, mul);
+  Plain<GTile> out{g};
+  CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
+}
+
+// ---------------------------------------------------------------------------
+// The differentiated form's z pass (see k_zext in mvd_adjoint.hip): the
+// z pass with the product, plus the forward spectrum stored and the FP64
+// PSF cross-spectrum accumulated in the product's epilogue.
+template <int T, int TX, int L, int... Rs>
+__global__ void __launch_bounds__(T)
+    k_zext_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+              const float2* __restrict__ twp, int v, int role, int conjH, float2* __restrict__ s_out,
+              const float2* __restrict__ s_in, double2* __restrict__ acc, int acc_mode) {
+  constexpr int RL = LastRadix<Rs...>::value;
+  using LM = LastMap<L, RL, T, TX, true>;
+  __shared__ float2 lds[L * TX];
+  __shared__ float2 s_tw[L];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  const int M = J.M, ny = J.ny;
+  const int nxt = mvd_cdiv(M, TX);
+  int64_t off, hoff;
+  int ps, nl;
+  if (local < nxt * ny) {
+    const int xt = local % nxt, y = local / nxt;
+    off = (int64_t)y * M + xt * TX;
+    hoff = off;
+    ps = ny * M;
+    nl = min(TX, M - xt * TX);
+  } else {
+    const int t2 = local - nxt * ny;
+    off = J.spec_main + (int64_t)t2 * TX;
+    hoff = J.h_main + (int64_t)t2 * TX;
+    ps = ny;
+    nl = min(TX, ny - t2 * TX);
+  }
+  const KLine kl{reinterpret_cast<const float2*>(J.H[role]) + (int64_t)v * J.h_elems + hoff, ps, nl, L,
+                 J.kz, J.cz};
+  GTile g{reinterpret_cast<float2*>(J.spec) + off, 1, ps, nl};
+  const GTileU gin{reinterpret_cast<const float2*>(J.spec) + off, 1, ps, nl};
+  constexpr int R1 = FirstRadix<Rs...>::value;
+  constexpr int MB1 = FirstMap<L, R1, T, TX>::MAXB;
+  constexpr int NTW = (L + T - 1) / T;
+  const float2* twsrc = twp + plans[J.plan_z].tw;
+  float2 twv[NTW];
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    const int e = threadIdx.x + i * T;
+    twv[i] = e < L ? ldg(twsrc + e) : make_float2(0.f, 0.f);
+  }
+  float2 kp[MB1][R1], dp[MB1][R1];
+  ct_prefetch<L, R1, T, TX, true>(threadIdx.x, kl, kp);
+  ct_prefetch<L, R1, T, TX, true>(threadIdx.x, gin, dp);
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    const int e = threadIdx.x + i * T;
+    if (e < L) s_tw[e] = twv[i];
+  }
+  const LdsCol<TX> S{lds};
+  float2 h[LM::MAXB][RL];
+  ToRegs<LM::MAXB, RL> kreg{h};
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{kp}, S, kreg);
+  __syncthreads();
+  ExtMul<TX, LM::MAXB, RL> ext{lds, h, conjH, off, ps, nl, s_out, s_in, acc, acc_mode};
+  CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{dp}, S, ext);
   Plain<GTile> out{g};
   CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
 }

@@ -268,58 +268,4 @@ void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float
   });
 }
 
-void window_idft_yx(const cd* T1, int nx, int ny, int wx, int wy, int wz, double* out) {
-  const int M = nx / 2;
-  const auto tx = twiddles(nx), ty = twiddles(ny);
-  const int cx = (wx - 1) / 2, cy = (wy - 1) / 2;
-  // y: T2[dz][dy][kx]
-  std::vector<cd> T2((size_t)wz * wy * (M + 1));
-  parallel_for(wz, [&](int z) {
-    for (int y = 0; y < wy; ++y) {
-      cd* t = &T2[((size_t)z * wy + y) * (M + 1)];
-      for (int k = 0; k < ny; ++k) {
-        const cd w = std::conj(ty[wrap(k, y - cy, ny)]);
-        const cd* a = &T1[((size_t)z * ny + k) * (M + 1)];
-        for (int x = 0; x <= M; ++x) t[x] += a[x] * w;
-      }
-    }
-  });
-  // x: the half spectrum stands for its Hermitian mirror, so kx in (0, M)
-  // counts twice
-  for (int z = 0; z < wz; ++z)
-    for (int y = 0; y < wy; ++y)
-      for (int x = 0; x < wx; ++x) {
-        const cd* t = &T2[((size_t)z * wy + y) * (M + 1)];
-        double s = 0;
-        for (int k = 0; k <= M; ++k) {
-          const double a = (k == 0 || k == M) ? 1.0 : 2.0;
-          s += a * (t[k] * std::conj(tx[wrap(k, x - cx, nx)])).real();
-        }
-        out[((size_t)z * wy + y) * wx + x] = s;
-      }
-}
-
-void window_idft_half(const cd* main, const cd* nyq, int nx, int ny, int nz, int wx, int wy, int wz,
-                      double* out) {
-  const int M = nx / 2;
-  const auto tz = twiddles(nz);
-  const int cz = (wz - 1) / 2;
-  // z: T1[dz][ky][kx], kx in [0, M]
-  std::vector<cd> T1((size_t)wz * ny * (M + 1));
-  parallel_for(wz, [&](int z) {
-    for (int k = 0; k < nz; ++k) {
-      const cd w = std::conj(tz[wrap(k, z - cz, nz)]);
-      for (int ky = 0; ky < ny; ++ky) {
-        cd* t = &T1[((size_t)z * ny + ky) * (M + 1)];
-        const cd* a = main + ((size_t)k * ny + ky) * M;
-        for (int x = 0; x < M; ++x) t[x] += a[x] * w;
-        t[M] += nyq[(size_t)k * ny + ky] * w;
-      }
-    }
-  });
-  window_idft_yx(T1.data(), nx, ny, wx, wy, wz, out);
-  const double inv = 1.0 / ((double)nx * ny * nz);
-  for (size_t i = 0; i < (size_t)wx * wy * wz; ++i) out[i] *= inv;
-}
-
 }  // namespace mvdh

@@ -43,13 +43,4 @@ std::vector<cd> twiddles(int n);
 // the main part [kz][ky][kx < nx/2] and the Nyquist plane [kz][ky].
 void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float* nyq_out);
 
-// Inverse DFT of a real volume's half spectrum (main part [kz][ky][kx < nx/2]
-// and the kx = nx/2 plane [kz][ky]), divided by V, evaluated only at the
-// offsets d of a centred odd window (wx, wy, wz): out[dz][dy][dx].
-void window_idft_half(const cd* main, const cd* nyq, int nx, int ny, int nz, int wx, int wy, int wz,
-                      double* out);
-// The y and x stages of the above from its z stage T1[dz][ky][kx <= nx/2]
-// (no 1/V applied).
-void window_idft_yx(const cd* T1, int nx, int ny, int wx, int wy, int wz, double* out);
-
 }  // namespace mvdh

@@ -62,6 +62,9 @@ hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int co
                            const float2* s_in, double2* acc, int acc_mode);
 hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
                              hipStream_t s);
+// y and x stages after the z stage: out[dz][dy][dx] (FP64, no 1/V)
+hipError_t mvd_launch_idft_yx(const double2* T1, int M, int nx, int ny, int wx, int wy, int wz, const double2* twx,
+                              const double2* twy, double2* T2, double* out, hipStream_t s);
 
 // compile-time plans for every 5-smooth length (mvd_exact_*.hip); a launch
 // covers jobs that all have length L (y: ny, z: nz) or half-row length M (x).
@@ -73,6 +76,8 @@ hipError_t mvd_launch_z_exact(const LaunchArgs& a, int L, int v, int role, int c
 hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt);
 hipError_t mvd_launch_x_exact_comb(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
                                    int opt);
+hipError_t mvd_launch_zext_exact(const LaunchArgs& a, int L, int v, int role, int conjH, float2* s_out,
+                                 const float2* s_in, double2* acc, int acc_mode);
 
 // weight normalisation (mvd_weights.hip), on one block's [nviews][V] weights
 hipError_t mvd_launch_overlap_stats(const float* w, int nviews, int64_t V, unsigned* cmin,

@@ -11,6 +11,7 @@
 #include <set>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mvd.h"
@@ -126,9 +127,11 @@ struct mvd_handle {
   float *g_gbar = nullptr, *g_part = nullptr, *g_psiT = nullptr;
   Partial* g_parts = nullptr;              // [view][x tiles]
   double* g_loss = nullptr;
-  double2* g_twz = nullptr;                // exp(-2 pi i m / nz), FP64
+  double2 *g_twz = nullptr, *g_twy = nullptr, *g_twx = nullptr;  // exp(-2 pi i m / n), FP64
   double2* g_t1 = nullptr;                 // z stage of the PSF-gradient inverse DFT
-  size_t g_t1_cap = 0;
+  double2* g_t2 = nullptr;                 // its y stage
+  double* g_gw = nullptr;                  // the windowed result
+  size_t g_t1_cap = 0, g_t2_cap = 0, g_gw_cap = 0;
   unsigned long long *g_lr = nullptr, *g_ln = nullptr;
   // weight normalisation: overlap statistics, and a staging volume for the
   // count image when the caller's buffer is in host memory
@@ -961,19 +964,39 @@ AdjPtrs adj_ptrs(mvd_handle* h, int v) {
 
 // Forward view-update v with its intermediates stored (b, q, c, the input
 // psi and the spectra of psi and q).
+// The differentiated form's y and z passes: the block's per-length
+// compile-time plan when its length has one, else the runtime plans.
+void grad_y(mvd_handle* h, int inv, int v) {
+  const int ny = h->blocks[0].ny, p = mvd_exact_param(PASS_Y, ny);
+  if (p > 0)
+    HIPCHECK(mvd_launch_y_exact(args(h, h->stream, mvd_tiles(h->jobs[0], PASS_Y, p)), ny, inv, v));
+  else
+    HIPCHECK(mvd_launch_y(args(h, h->stream, h->rt_grid[1]), h->rt_cfg[1], inv, v));
+}
+
+void grad_zext(mvd_handle* h, int v, int conjH, float2* s_out, const float2* s_in, double2* acc, int acc_mode) {
+  const int nz = h->blocks[0].nz, p = mvd_exact_param(PASS_Z, nz);
+  if (p > 0)
+    HIPCHECK(mvd_launch_zext_exact(args(h, h->stream, mvd_tiles(h->jobs[0], PASS_Z, p)), nz, v, ROLE_P, conjH, s_out,
+                                   s_in, acc, acc_mode));
+  else
+    HIPCHECK(mvd_launch_zext(args(h, h->stream, h->rt_grid[2]), h->rt_cfg[2], v, ROLE_P, conjH, s_out, s_in, acc,
+                             acc_mode));
+}
+
 void grad_forward_view(mvd_handle* h, int v) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
-  const LaunchArgs ax = args(h, s, h->rt_grid[0]), ay = args(h, s, h->rt_grid[1]), az = args(h, s, h->rt_grid[2]);
+  const LaunchArgs ax = args(h, s, h->rt_grid[0]);
   const AdjPtrs ap = adj_ptrs(h, v);
   Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, h->g_spsi + (size_t)v * B.spec_elems, nullptr, nullptr, 0));
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  grad_y(h, 0, v);
+  grad_zext(h, v, 0, h->g_spsi + (size_t)v * B.spec_elems, nullptr, nullptr, 0);
+  grad_y(h, 1, v);
   HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 3, v, parts, h->d_flags, ap));
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0));
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  grad_y(h, 0, v);
+  grad_zext(h, v, 1, h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0);
+  grad_y(h, 1, v);
   HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 4, v, parts, h->d_flags, ap));
 }
 
@@ -981,21 +1004,21 @@ void grad_forward_view(mvd_handle* h, int v) {
 void grad_adjoint_view(mvd_handle* h, int v) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
-  const LaunchArgs ax = args(h, s, h->rt_grid[0]), ay = args(h, s, h->rt_grid[1]), az = args(h, s, h->rt_grid[2]);
+  const LaunchArgs ax = args(h, s, h->rt_grid[0]);
   const AdjPtrs ap = adj_ptrs(h, v);
   double2* acc = h->g_acc + (size_t)v * B.spec_elems;
   // cbar and the direct part of psibar
   HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 5, v, nullptr, h->d_flags, ap));
   // qbar = cbar (x) P_v, with A_v += conj(Cbar) Q
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, nullptr, h->g_sq + (size_t)v * B.spec_elems, acc, 1));
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  grad_y(h, 0, v);
+  grad_zext(h, v, 0, nullptr, h->g_sq + (size_t)v * B.spec_elems, acc, 1);
+  grad_y(h, 1, v);
   // bbar
   HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 6, v, nullptr, h->d_flags, ap));
   // bbar (x) P_v*, with A_v += Bbar conj(Psi)
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-  HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, nullptr, h->g_spsi + (size_t)v * B.spec_elems, acc, 0));
-  HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+  grad_y(h, 0, v);
+  grad_zext(h, v, 1, nullptr, h->g_spsi + (size_t)v * B.spec_elems, acc, 0);
+  grad_y(h, 1, v);
   HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
 }
 
@@ -1034,20 +1057,20 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
   // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed
   HIPCHECK(hipMemsetAsync(h->g_gbar, 0, V * sizeof(float), st));
   HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)N * S * sizeof(double2), st));
-  const LaunchArgs ax = args(h, st, h->rt_grid[0]), ay = args(h, st, h->rt_grid[1]), az = args(h, st, h->rt_grid[2]);
+  const LaunchArgs ax = args(h, st, h->rt_grid[0]);
   for (int v = 0; v < N; ++v) {
     Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
     AdjPtrs ap = adj_ptrs(h, v);
     ap.part = h->g_gbar;
     x_init_rt(h);
-    HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-    HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 0, h->g_sT, nullptr, nullptr, 0));
-    HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+    grad_y(h, 0, v);
+    grad_zext(h, v, 0, h->g_sT, nullptr, nullptr, 0);
+    grad_y(h, 1, v);
     HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 8, v, parts, h->d_flags, ap));
     if (want_grad) {
-      HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 0, v));
-      HIPCHECK(mvd_launch_zext(az, h->rt_cfg[2], v, ROLE_P, 1, nullptr, h->g_sT, h->g_acc + (size_t)v * S, 0));
-      HIPCHECK(mvd_launch_y(ay, h->rt_cfg[1], 1, v));
+      grad_y(h, 0, v);
+      grad_zext(h, v, 1, nullptr, h->g_sT, h->g_acc + (size_t)v * S, 0);
+      grad_y(h, 1, v);
       HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
     }
   }
@@ -1067,30 +1090,42 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
       HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
                               grad_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
     if (grad_psf) {
-      // z stage of the windowed inverse DFT on the device (FP64), y and x on the host
-      if (!h->g_twz) {
-        const auto tz = mvdh::twiddles(B.nz);
-        h->g_twz = (double2*)h->dalloc(tz.size() * sizeof(double2));
-        HIPCHECK(hipMemcpyAsync(h->g_twz, tz.data(), tz.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      // the windowed inverse DFT of each view's cross-spectrum, on the device
+      // in FP64 (z, then y, then x stage); the normalisation on the host
+      auto table = [&](double2*& dst, int n) {
+        if (dst) return;
+        const auto t = mvdh::twiddles(n);
+        dst = (double2*)h->dalloc(t.size() * sizeof(double2));
+        HIPCHECK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      };
+      table(h->g_twz, B.nz);
+      table(h->g_twy, B.ny);
+      table(h->g_twx, B.nx);
+      size_t t1n = 0, t2n = 0, gn = 0;
+      for (int v = 0; v < N; ++v) {
+        const mvdh::Kern& P = B.P[v];
+        t1n = std::max(t1n, (size_t)(B.M + 1) * B.ny * P.kz);
+        t2n = std::max(t2n, (size_t)(B.M + 1) * P.ky * P.kz);
+        gn = std::max(gn, (size_t)P.kx * P.ky * P.kz);
       }
-      int wzmax = 0;
-      for (int v = 0; v < N; ++v) wzmax = std::max(wzmax, B.P[v].kz);
-      const size_t t1n = (size_t)(B.M + 1) * B.ny * wzmax;
-      if (t1n > h->g_t1_cap) {
-        h->g_t1 = (double2*)h->dalloc(t1n * sizeof(double2));
-        h->g_t1_cap = t1n;
-      }
-      std::vector<mvdh::cd> T1(t1n);
+      auto grow = [&](auto*& p, size_t& cap, size_t n, size_t elem) {
+        if (n <= cap) return;
+        p = (std::remove_reference_t<decltype(p)>)h->dalloc(n * elem);
+        cap = n;
+      };
+      grow(h->g_t1, h->g_t1_cap, t1n, sizeof(double2));
+      grow(h->g_t2, h->g_t2_cap, t2n, sizeof(double2));
+      grow(h->g_gw, h->g_gw_cap, gn, sizeof(double));
       const double invV = 1.0 / (double)B.V;
       for (int v = 0; v < N; ++v) {
         if (!grad_psf[v]) continue;
         const mvdh::Kern& P = B.P[v];
         HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
-        const size_t n1 = (size_t)(B.M + 1) * B.ny * P.kz;
-        HIPCHECK(hipMemcpyAsync(T1.data(), h->g_t1, n1 * sizeof(double2), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(mvd_launch_idft_yx(h->g_t1, B.M, B.nx, B.ny, P.kx, P.ky, P.kz, h->g_twx, h->g_twy, h->g_t2,
+                                    h->g_gw, st));
         std::vector<double> g((size_t)P.kx * P.ky * P.kz);
-        mvdh::window_idft_yx(T1.data(), B.nx, B.ny, P.kx, P.ky, P.kz, g.data());
+        HIPCHECK(hipMemcpyAsync(g.data(), h->g_gw, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
         for (double& x : g) x *= invV;
         // through the normalisation P = G / sum G, then drop the odd padding
         double dot = 0;
