@@ -196,7 +196,7 @@ def grad_form(steps, warmup):
     d.close()
     res["backward_over_forward"] = round(res["forward_backward"]["ms_per_step"] / res["forward"]["ms_per_step"], 3)
     res["workload"] = "128^3, 4 views, 25^3 PSFs, 8 RL iterations, loss sum_v |psi_8 (x) P_v - phi_v|^2"
-    res["note"] = "host wall clock per call (each call synchronises; PSF gradients finish on the host in FP64)"
+    res["note"] = "host wall clock per call (each call synchronises; the PSF gradients' normalisation Jacobian runs on the host)"
     return res
 
 
