@@ -326,6 +326,92 @@ class Problem:
         return psi
 
 
+# ------------------------------------------------------ linear boundary --
+#
+# The views are known on the volume only; light from sources up to one PSF
+# radius p outside it reaches it.  psi lives on the extended domain
+# (n + 2p per axis, the volume at offset p); b = psi * P is evaluated on the
+# volume (linear convolution), and the update divides the back-projection by
+# the view's sensitivity N = 1_volume * K (EM with the restricted system
+# matrix: psi' = psi A^T(phi / A psi) / A^T 1).  Margin voxels with
+# N < SENS_MIN are not updated.  Weights apply on the volume and are 1 in
+# the margin.
+
+SENS_MIN = 1e-6
+
+
+def margins(psfs):
+    """Per-axis radius (z, y, x) of the largest prepared PSF."""
+    shapes = [prepare_psf(p).shape for p in psfs]
+    return tuple(max(k[a] for k in shapes) // 2 for a in range(3))
+
+
+def pad_kernel(K, p):
+    """Centre an odd kernel in a (2p+1)^3 box."""
+    K = np.asarray(K, dtype=np.float64)
+    pads = [((2 * p[a] + 1 - K.shape[a]) // 2,) * 2 for a in range(3)]
+    return np.pad(K, pads)
+
+
+def lin_blur(psi_e, P, p):
+    """b on the volume: (psi * P)(x) = sum_d P[c + d] psi(x - d), psi given on
+    the extended domain."""
+    return signal.fftconvolve(psi_e, pad_kernel(P, p), mode="valid")
+
+
+def lin_back(q, K, p):
+    """Back-projection onto the extended domain: sum_x K[c + (xi - x)] q(x)."""
+    return signal.fftconvolve(q, pad_kernel(K, p), mode="full")
+
+
+def view_update_linear(psi_e, phi, P, K, p, w_e=None, lam_p=0.0, eps=0.0):
+    """One view-update with the linear boundary (see the block comment)."""
+    b = lin_blur(psi_e, P, p)
+    q = phi / np.maximum(b, eps)
+    c = np.maximum(lin_back(q, K, p), 0.0)
+    N = lin_back(np.ones_like(phi), K, p)
+    live = N >= SENS_MIN
+    u = psi_e.copy()
+    u[live] = psi_e[live] * c[live] / N[live]
+    t = tikhonov(u, lam_p)
+    t[~live] = psi_e[~live]
+    if w_e is None:
+        return t
+    return psi_e + w_e * (t - psi_e)
+
+
+class ProblemLinear(Problem):
+    """A Problem deconvolved with the linear boundary."""
+
+    def __init__(self, views, psfs, weights=None, lam=0.0):
+        super().__init__(views, psfs, weights, lam)
+        self.p = margins(self.psfs)
+        n = self.shape
+        self.shape_e = tuple(n[a] + 2 * self.p[a] for a in range(3))
+        self.weights_e = None
+        if self.weights is not None:
+            self.weights_e = [np.pad(w, [(q, q) for q in self.p], constant_values=1.0) for w in self.weights]
+
+    def psi0(self):
+        return np.full(self.shape_e, self.s, dtype=np.float64)
+
+    def interior(self, psi_e):
+        pz, py, px = self.p
+        n = self.shape
+        return psi_e[pz:pz + n[0], py:py + n[1], px:px + n[2]]
+
+    def iterate(self, psi_e, n_iter, variant, flux=None, stats=None):
+        K = self.kernels(variant)
+        psi = np.array(psi_e, dtype=np.float64)
+        for _ in range(n_iter):
+            for v in range(self.n):
+                w = None if self.weights_e is None else self.weights_e[v]
+                psi = view_update_linear(psi, self.views[v], self.P[v], K[v], self.p, w, self.lam_p, self.eps)
+                if flux is not None:
+                    flux.append(float(psi.sum()))
+        return psi
+
+
 def run(views, psfs, n_iter, variant, weights=None, lam=0.0, psi0=None, trajectory=False):
     """Deconvolve from psi0 (default: flat at the mean); optionally return
     the estimate after every iteration."""
