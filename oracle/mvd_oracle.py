@@ -334,10 +334,11 @@ class Problem:
 # volume (linear convolution), and the update divides the back-projection by
 # the view's sensitivity N = 1_volume * K (EM with the restricted system
 # matrix: psi' = psi A^T(phi / A psi) / A^T 1).  Margin voxels with
-# N < SENS_MIN are not updated.  Weights apply on the volume and are 1 in
+# N < SENS_MIN (they send less than 1 % of their light into the volume) are
+# not updated: the division would magnify the transforms' round-off there.  Weights apply on the volume and are 1 in
 # the margin.
 
-SENS_MIN = 1e-6
+SENS_MIN = 1e-2
 
 
 def margins(psfs):
