@@ -111,6 +111,21 @@ typedef void (*mvd_free_fn)(void* ptr, void* ctx);
  *   use_graphs 0 = launch kernels directly, 1 = replay one HIP graph per
  *              iteration (default when options are NULL)
  *   tile_config  0 = autotuned/default pass shapes; k > 0 forces candidate k-1
+ *   boundary   MVD_BOUNDARY_CIRCULAR (0): the volume is one period of a
+ *              periodic grid (the convolutions wrap around);
+ *              MVD_BOUNDARY_LINEAR (1): the views are known on the volume only
+ *              and psi also lives on a margin of one PSF radius around it.
+ *              The handle computes on the volume extended by the largest
+ *              PSF radius per axis, rounded up to transform lengths; each
+ *              view's blur is evaluated on the volume and the
+ *              back-projection is divided by the view's sensitivity
+ *              1_volume (x) K_v (EM with the restricted system matrix;
+ *              margin voxels that send less than 1 % of their light
+ *              into the volume (sensitivity < 0.01) are not updated).
+ *              Weights apply on the volume and are 1 in the margin.  Only
+ *              the sequential scheme (mvd_iterate, mvd_view_update) runs with
+ *              it; estimates are read and set on the volume (setting one
+ *              resets the margin to s).
  */
 typedef struct mvd_options {
   double lambda;
@@ -121,7 +136,11 @@ typedef struct mvd_options {
   void* alloc_ctx;
   int use_graphs;
   int tile_config;
+  int boundary;
 } mvd_options;
+
+#define MVD_BOUNDARY_CIRCULAR 0
+#define MVD_BOUNDARY_LINEAR 1
 
 typedef struct mvd_stats_t {
   int64_t iterations;        /* iterations run since create / set_estimate */
@@ -241,6 +260,11 @@ int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block);
  * and the non-finite flag.  Use to resume from a checkpoint or to start the
  * differentiated form from a given psi_0. */
 int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block);
+
+/* The computation grid (nx, ny, nz) of `block` into dims[3]: the volume's
+ * own dims with the circular boundary, the volume plus its PSF margin
+ * rounded up to transform lengths with the linear one. */
+int mvd_grid_dims(const mvd_handle* h, int block, int* dims);
 
 /* Synchronise and report statistics of the last mvd_iterate call. */
 int mvd_stats(mvd_handle* h, mvd_stats_t* s);

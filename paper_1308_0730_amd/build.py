@@ -34,6 +34,7 @@ SOURCES = [
     ("mvd_exact_y.hip", True),
     ("mvd_kernels_ct.hip", True),
     ("mvd_weights.hip", True),
+    ("mvd_embed.hip", True),
     ("mvd_runtime.cpp", True),
     ("mvd_host.cpp", False),
 ]

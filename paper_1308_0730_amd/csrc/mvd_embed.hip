@@ -1,0 +1,62 @@
+// Volumes of the linear boundary: the user's volume sits at an offset inside
+// a larger computation grid (the volume extended by the PSF radius and
+// rounded up to transform lengths).  Setup and copy work, not part of an
+// iteration.  Shapes are (nx, ny, nz) grids stored [z][y][x].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mvd_gmem.h"
+#include "mvd_kernels.h"
+
+using namespace mvdk;
+
+namespace {
+
+struct Box {
+  int nx, ny, nz;   // grid
+  int ux, uy, uz;   // user volume
+  int ox, oy, oz;   // its offset in the grid
+};
+
+__device__ __forceinline__ int64_t grid_index(const Box& b, int64_t i) {
+  const int x = (int)(i % b.ux);
+  const int64_t r = i / b.ux;
+  const int y = (int)(r % b.uy);
+  const int z = (int)(r / b.uy);
+  return ((int64_t)(z + b.oz) * b.ny + (y + b.oy)) * b.nx + (x + b.ox);
+}
+
+__global__ void __launch_bounds__(256) k_embed(float* __restrict__ grid, const float* __restrict__ vol, Box b) {
+  const int64_t n = (int64_t)b.ux * b.uy * b.uz;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    stg(grid + grid_index(b, i), ldg(vol + i));
+}
+
+__global__ void __launch_bounds__(256) k_extract(float* __restrict__ vol, const float* __restrict__ grid, Box b) {
+  const int64_t n = (int64_t)b.ux * b.uy * b.uz;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    stg(vol + i, ldg(grid + grid_index(b, i)));
+}
+
+int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+Box box(const int* grid, const int* user, const int* off) {
+  return Box{grid[0], grid[1], grid[2], user[0], user[1], user[2], off[0], off[1], off[2]};
+}
+
+}  // namespace
+
+hipError_t mvd_launch_embed(float* grid, const int* gdims, const float* vol, const int* udims, const int* off,
+                            hipStream_t s) {
+  const Box b = box(gdims, udims, off);
+  k_embed<<<blocks_for((int64_t)b.ux * b.uy * b.uz), 256, 0, s>>>(grid, vol, b);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_extract(float* vol, const int* udims, const float* grid, const int* gdims, const int* off,
+                              hipStream_t s) {
+  const Box b = box(gdims, udims, off);
+  k_extract<<<blocks_for((int64_t)b.ux * b.uy * b.uz), 256, 0, s>>>(vol, grid, b);
+  return hipGetLastError();
+}

@@ -84,3 +84,10 @@ hipError_t mvd_launch_overlap_stats(const float* w, int nviews, int64_t V, unsig
                                     unsigned long long* csum, unsigned long long* ncov, hipStream_t s);
 hipError_t mvd_launch_overlap_limit(float* w, int nviews, int64_t V, float m, hipStream_t s);
 hipError_t mvd_launch_overlap_count(const float* w, int nviews, int64_t V, float* out, hipStream_t s);
+
+// linear boundary (mvd_embed.hip): copy a (ux, uy, uz) volume into / out of a
+// (nx, ny, nz) grid at offset off (x, y, z); the rest of the grid is untouched
+hipError_t mvd_launch_embed(float* grid, const int* gdims, const float* vol, const int* udims, const int* off,
+                            hipStream_t s);
+hipError_t mvd_launch_extract(float* vol, const int* udims, const float* grid, const int* gdims, const int* off,
+                              hipStream_t s);

@@ -53,6 +53,12 @@ struct Block {
   float* H[N_ROLES] = {nullptr, nullptr, nullptr, nullptr};
   float* acc = nullptr;    // combined-update factor [V], allocated on first use
   float* saved = nullptr;  // spectrum of psi kept over a combined iteration
+  // linear boundary: the user's volume (ux, uy, uz) at offset (ox, oy, oz)
+  // in the computation grid (nx, ny, nz); circular: the same box, offset 0
+  int ux = 0, uy = 0, uz = 0, ox = 0, oy = 0, oz = 0;
+  int64_t UV = 0;
+  float* sens[4] = {nullptr, nullptr, nullptr, nullptr};  // [nviews][V] per variant
+  float* lin_save = nullptr;                               // psi while a sensitivity is built
   std::vector<mvdh::Kern> P;  // prepared PSFs
   std::vector<double> psf_sum;     // sums of the raw PSF inputs
   std::vector<std::array<int, 3>> psf_dims;  // raw extents {kx, ky, kz}
@@ -111,6 +117,8 @@ struct mvd_handle {
   int uniform_len[3] = {0, 0, 0};  // the common length of a pass kind, 0 if the blocks differ
   size_t parts_cap = 0;
   bool spec_valid = false;
+  bool linear = false;            // MVD_BOUNDARY_LINEAR
+  bool sens_built[4] = {false, false, false, false};
   bool built[N_ROLES] = {true, false, false, false};
   int64_t iterations = 0;
   // one graph per (scheme, variant): scheme 0 sequential, 1 combined with
@@ -390,6 +398,7 @@ void build_jobs(mvd_handle* h) {
     for (int r = 0; r < N_ROLES; ++r) j.H[r] = B.H[r];
     j.acc = B.acc;
     j.saved = B.saved;
+    for (int r = 0; r < 4; ++r) j.sens[r] = B.sens[r];
     j.eps = B.eps;
     j.lamp = B.lamp;
     h->jobs.push_back(j);
@@ -489,6 +498,39 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
   h->grid_z = gz;
 }
 
+// Smallest 5-smooth length >= n (even when asked).
+int next_smooth5(int n, bool even) {
+  for (int m = std::max(n, 1);; ++m) {
+    if (even && (m & 1)) continue;
+    int k = m;
+    for (int q : {2, 3, 5})
+      while (k % q == 0) k /= q;
+    if (k == 1) return m;
+  }
+}
+
+const int* grid_dims(const Block& B) {
+  thread_local int d[3];
+  d[0] = B.nx;
+  d[1] = B.ny;
+  d[2] = B.nz;
+  return d;
+}
+const int* user_dims(const Block& B) {
+  thread_local int d[3];
+  d[0] = B.ux;
+  d[1] = B.uy;
+  d[2] = B.uz;
+  return d;
+}
+const int* offsets(const Block& B) {
+  thread_local int d[3];
+  d[0] = B.ox;
+  d[1] = B.oy;
+  d[2] = B.oz;
+  return d;
+}
+
 void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options* o) {
   if (nb < 1) bad("n_blocks must be >= 1");
   if (!ps) bad("problem is NULL");
@@ -508,6 +550,9 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     h->actx = o->alloc_ctx;
     h->use_graphs = o->use_graphs != 0;
     h->force_cfg = o->tile_config;
+    if (o->boundary != MVD_BOUNDARY_CIRCULAR && o->boundary != MVD_BOUNDARY_LINEAR)
+      bad("boundary must be MVD_BOUNDARY_CIRCULAR or MVD_BOUNDARY_LINEAR");
+    h->linear = o->boundary == MVD_BOUNDARY_LINEAR;
   }
   h->nviews = ps[0].n_views;
   // host-memory values are checked before any device call
@@ -541,11 +586,27 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
   for (int b = 0; b < nb; ++b) {
     const mvd_problem& p = ps[b];
     Block& B = h->blocks[b];
-    B.nx = p.dims[0];
-    B.ny = p.dims[1];
-    B.nz = p.dims[2];
+    B.ux = B.nx = p.dims[0];
+    B.uy = B.ny = p.dims[1];
+    B.uz = B.nz = p.dims[2];
+    B.UV = vox(p.dims);
+    if (h->linear) {
+      // the largest PSF radius per axis (odd-padded extents), and the grid
+      // that holds the volume plus that margin on both sides
+      int r[3] = {0, 0, 0};
+      for (int v = 0; v < N; ++v)
+        for (int a = 0; a < 3; ++a) r[a] = std::max(r[a], (p.psf_dims[3 * v + a] | 1) / 2);
+      B.ox = r[0];
+      B.oy = r[1];
+      B.oz = r[2];
+      B.nx = next_smooth5(B.ux + 2 * r[0], true);
+      B.ny = next_smooth5(B.uy + 2 * r[1], false);
+      B.nz = next_smooth5(B.uz + 2 * r[2], false);
+      if (B.nx / 2 > MVD_MAX_LEN || B.ny > MVD_MAX_LEN || B.nz > MVD_MAX_LEN)
+        bad("block " + std::to_string(b) + ": the volume plus its PSF margin exceeds the largest transform length");
+    }
     B.M = B.nx / 2;
-    B.V = vox(p.dims);
+    B.V = (int64_t)B.nx * B.ny * B.nz;
     B.spec_main = (int64_t)B.M * B.ny * B.nz;
     B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
     B.psi = (float*)h->dalloc(B.V * sizeof(float));
@@ -553,10 +614,29 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
     if (p.weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
     const hipMemcpyKind kind = p.mem_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    for (int v = 0; v < N; ++v) {
-      HIPCHECK(hipMemcpyAsync(B.phi + (size_t)v * B.V, p.views[v], B.V * sizeof(float), kind, h->stream));
-      if (p.weights)
-        HIPCHECK(hipMemcpyAsync(B.w + (size_t)v * B.V, p.weights[v], B.V * sizeof(float), kind, h->stream));
+    if (!h->linear) {
+      for (int v = 0; v < N; ++v) {
+        HIPCHECK(hipMemcpyAsync(B.phi + (size_t)v * B.V, p.views[v], B.V * sizeof(float), kind, h->stream));
+        if (p.weights)
+          HIPCHECK(hipMemcpyAsync(B.w + (size_t)v * B.V, p.weights[v], B.V * sizeof(float), kind, h->stream));
+      }
+    } else {
+      // views are zero and weights one outside the volume; host inputs pass
+      // through the (not yet used) estimate buffer
+      HIPCHECK(mvd_launch_fill(B.phi, (int64_t)N * B.V, 0.f, h->stream));
+      if (p.weights) HIPCHECK(mvd_launch_fill(B.w, (int64_t)N * B.V, 1.f, h->stream));
+      auto put = [&](float* grid, const float* src) {
+        const float* from = src;
+        if (p.mem_kind == MVD_MEM_HOST) {
+          HIPCHECK(hipMemcpyAsync(B.psi, src, B.UV * sizeof(float), hipMemcpyHostToDevice, h->stream));
+          from = B.psi;
+        }
+        HIPCHECK(mvd_launch_embed(grid, grid_dims(B), from, user_dims(B), offsets(B), h->stream));
+      };
+      for (int v = 0; v < N; ++v) {
+        put(B.phi + (size_t)v * B.V, p.views[v]);
+        if (p.weights) put(B.w + (size_t)v * B.V, p.weights[v]);
+      }
     }
     // FP64 mean over all views, plus the value checks of device inputs
     double total = 0;
@@ -571,7 +651,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
         if (nbad) bad("block " + std::to_string(b) + ": weights " + std::to_string(v) + " outside [0, 1]");
       }
     }
-    B.s = total / ((double)N * (double)B.V);
+    B.s = total / ((double)N * (double)B.UV);
     if (!(B.s > 0)) bad("block " + std::to_string(b) + ": the views are all zero");
     B.eps = (float)(h->eps_scale * B.s);
     B.lamp = (float)(h->lambda / B.s);
@@ -787,7 +867,10 @@ void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t
   timed(0, [&] { run_y(h, s, 0, v); });
   timed(2, [&] { run_z(h, s, v, role, conj_back, 0); });
   timed(1, [&] { run_y(h, s, 1, v); });
-  timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
+  if (h->linear)
+    timed(4, [&] { run_x(h, s, 5, v, parts, XOPT_SPEC | (variant << XOPT_VARIANT_SHIFT)); });
+  else
+    timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
 }
 
 // One iteration: every view once, in index order (section 7).
@@ -825,6 +908,49 @@ void enqueue_combined_iteration(mvd_handle* h, hipStream_t s, int variant, bool 
   }
 }
 
+void ensure_combined(mvd_handle* h);
+
+// Linear boundary: each view's sensitivity 1_volume (x) K_v for `variant`
+// (K_v = P_v* for RL), computed with the handle's own passes: the
+// indicator of the volume goes through the forward x and y transforms once,
+// then per view through the z pass of K_v (reading the saved spectrum), the
+// inverse y and the inverse x, whose output is max(., 0).  psi is kept aside.
+void ensure_sens(mvd_handle* h, int variant) {
+  if (h->sens_built[variant]) return;
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  const int conj_back = variant == MVD_RL ? 1 : 0;
+  ensure_combined(h);
+  hipStream_t s = h->stream;
+  for (auto& B : h->blocks) {
+    if (!B.sens[variant]) B.sens[variant] = (float*)h->dalloc((size_t)h->nviews * B.V * sizeof(float));
+    if (!B.lin_save) B.lin_save = (float*)h->dalloc(B.V * sizeof(float));
+    HIPCHECK(hipMemcpyAsync(B.lin_save, B.psi, B.V * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // psi <- indicator: zero grid, ones embedded from the factor buffer
+    HIPCHECK(mvd_launch_fill(B.psi, B.V, 0.f, s));
+    HIPCHECK(mvd_launch_fill(B.acc, B.UV, 1.f, s));
+    HIPCHECK(mvd_launch_embed(B.psi, grid_dims(B), B.acc, user_dims(B), offsets(B), s));
+  }
+  build_jobs(h);
+  run_x(h, s, 0, 0, nullptr, XOPT_SPEC);
+  run_y(h, s, 0, 0);
+  for (const auto& B : h->blocks)
+    HIPCHECK(hipMemcpyAsync(B.saved, B.spec, B.spec_elems * 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  for (int v = 0; v < h->nviews; ++v) {
+    Partial* parts = h->d_parts + (size_t)v * h->grid_x;
+    run_z(h, s, v, role, conj_back, 1);
+    run_y(h, s, 1, v);
+    run_x(h, s, 3, v, parts, XOPT_FIRST);
+    for (const auto& B : h->blocks)
+      HIPCHECK(hipMemcpyAsync(B.sens[variant] + (size_t)v * B.V, B.acc, B.V * sizeof(float), hipMemcpyDeviceToDevice,
+                              s));
+  }
+  for (const auto& B : h->blocks)
+    HIPCHECK(hipMemcpyAsync(B.psi, B.lin_save, B.V * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  h->spec_valid = false;
+  h->sens_built[variant] = true;
+}
+
 void ensure_combined(mvd_handle* h) {
   bool grown = false;
   for (auto& B : h->blocks) {
@@ -844,6 +970,7 @@ void prepare_run(mvd_handle* h, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   const int role = variant == MVD_RL ? ROLE_P : variant;
   ensure_role(h, role);
+  if (h->linear) ensure_sens(h, variant);
   if (!h->spec_valid) {
     run_x(h, h->stream, 0, 0, nullptr, XOPT_SPEC);
     h->spec_valid = true;
@@ -896,6 +1023,7 @@ void iterate_combined_impl(mvd_handle* h, int n, int variant, int mean) {
   if (n < 0) bad("n must be >= 0");
   for (const auto& B : h->blocks)
     if (B.w) bad("combined updates take no weights (weights apply to sequential view-updates)");
+  if (h->linear) throw Error(MVD_ESTATE, "combined updates run with the circular boundary only");
   if (n == 0) return;
   prepare_run(h, variant);
   ensure_combined(h);
@@ -1029,6 +1157,7 @@ void x_init_rt(mvd_handle* h) {
 void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
                     double* const* grad_psf, float* grad_psi0, int grad_kind) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
+  if (h->linear) throw Error(MVD_ESTATE, "the differentiated form runs with the circular boundary only");
   if (variant != MVD_RL) bad("gradients are available for MVD_RL");
   if (n < 0) bad("n must be >= 0");
   if (!loss) bad("loss is NULL");
@@ -1152,6 +1281,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
 
 void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "mvd_set_psfs takes a single-block handle");
+  if (h->linear) throw Error(MVD_ESTATE, "mvd_set_psfs runs with the circular boundary only");
   if (!psfs || !psf_dims) bad("psfs and psf_dims are required");
   if (mem_kind != MVD_MEM_HOST && mem_kind != MVD_MEM_DEVICE) bad("mem_kind must be host or device");
   Block& B = h->blocks[0];
@@ -1207,6 +1337,7 @@ void normalize_weights_impl(mvd_handle* h, int mode, double value, double* m_out
   if (mode == MVD_OVERLAP_USER && !(value > 0 && std::isfinite(value))) bad("the user overlap must be finite and > 0");
   for (const auto& B : h->blocks)
     if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
+  if (h->linear) throw Error(MVD_ESTATE, "weight normalisation runs with the circular boundary only");
   if (!h->w_cmin) {
     h->w_cmin = (unsigned*)h->dalloc(sizeof(unsigned));
     h->w_cnt = (unsigned long long*)h->dalloc(2 * sizeof(unsigned long long));
@@ -1241,6 +1372,7 @@ void contributing_views_impl(mvd_handle* h, float* dst, int dst_kind, int block)
   if (block < 0 || block >= (int)h->blocks.size()) bad("block index out of range");
   const Block& B = h->blocks[block];
   if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
+  if (h->linear) throw Error(MVD_ESTATE, "the contributing-view image needs the circular boundary");
   if (dst_kind == MVD_MEM_DEVICE) {
     HIPCHECK(mvd_launch_overlap_count(B.w, h->nviews, B.V, dst, h->stream));
   } else {
@@ -1351,6 +1483,22 @@ int mvd_contributing_views(mvd_handle* h, float* dst, int dst_kind, int block) {
   return guard(h, [&] { contributing_views_impl(h, dst, dst_kind, block); });
 }
 
+int mvd_grid_dims(const mvd_handle* h, int block, int* dims) {
+  if (!h || !dims) {
+    g_err = "handle or dims is NULL";
+    return MVD_EINVAL;
+  }
+  if (block < 0 || block >= (int)h->blocks.size()) {
+    g_err = "block index out of range";
+    return MVD_EINVAL;
+  }
+  const Block& B = h->blocks[block];
+  dims[0] = B.nx;
+  dims[1] = B.ny;
+  dims[2] = B.nz;
+  return MVD_OK;
+}
+
 int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {
   if (!h) {
     g_err = "handle is NULL";
@@ -1361,8 +1509,20 @@ int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {
     const Block& B = block_of(h, block);
     if (!dst) bad("dst is NULL");
     if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
-    HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
-                            dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+    if (!h->linear) {
+      HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
+                              dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      // the volume out of the grid; host copies pass through the factor buffer
+      float* to = dst;
+      if (dst_kind == MVD_MEM_HOST) {
+        ensure_combined(h);
+        to = B.acc;
+      }
+      HIPCHECK(mvd_launch_extract(to, user_dims(B), B.psi, grid_dims(B), offsets(B), h->stream));
+      if (dst_kind == MVD_MEM_HOST)
+        HIPCHECK(hipMemcpyAsync(dst, to, B.UV * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    }
     nonfinite = read_flag(h);
   });
   if (rc == MVD_OK && nonfinite) {
@@ -1380,18 +1540,31 @@ int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block) {
   return guard(h, [&] {
     Block& B = const_cast<Block&>(block_of(h, block));
     if (!src) bad("src is NULL");
+    if (src_kind != MVD_MEM_HOST && src_kind != MVD_MEM_DEVICE) bad("src_kind must be host or device");
+    // with the linear boundary the volume goes into the grid (host data via
+    // the factor buffer) and the margin restarts at s
+    float* to = B.psi;
+    if (h->linear) {
+      ensure_combined(h);
+      to = B.acc;
+    }
     if (src_kind == MVD_MEM_HOST) {
-      for (int64_t i = 0; i < B.V; ++i)
+      for (int64_t i = 0; i < B.UV; ++i)
         if (!(src[i] >= 0.f) || !std::isfinite(src[i])) bad("estimate has a negative or non-finite value");
-      HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    } else if (src_kind == MVD_MEM_DEVICE) {
+      HIPCHECK(hipMemcpyAsync(to, src, B.UV * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    } else {
       double s;
       unsigned long long nb;
-      device_check(h, src, B.V, 0.f, INFINITY, &s, &nb);
+      device_check(h, src, B.UV, 0.f, INFINITY, &s, &nb);
       if (nb) bad("estimate has a negative or non-finite value");
-      HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-    } else {
-      bad("src_kind must be host or device");
+      if (h->linear)
+        to = const_cast<float*>(src);
+      else
+        HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (h->linear) {
+      HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, h->stream));
+      HIPCHECK(mvd_launch_embed(B.psi, grid_dims(B), to, user_dims(B), offsets(B), h->stream));
     }
     HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));

@@ -35,7 +35,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 class Options(C.Structure):
     _fields_ = [("lam", C.c_double), ("eps_scale", C.c_double), ("stream", C.c_void_p),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("use_graphs", C.c_int), ("tile_config", C.c_int)]
+                ("use_graphs", C.c_int), ("tile_config", C.c_int), ("boundary", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -66,6 +66,7 @@ def lib():
     L.mvd_create_batch.argtypes = [C.POINTER(H), C.c_int, C.POINTER(Problem), C.POINTER(Options)]
     L.mvd_iterate.argtypes = [H, C.c_int, C.c_int]
     L.mvd_iterate_combined.argtypes = [H, C.c_int, C.c_int, C.c_int]
+    L.mvd_grid_dims.argtypes = [H, C.c_int, C.POINTER(C.c_int)]
     L.mvd_normalize_weights.argtypes = [H, C.c_int, C.c_double, C.POINTER(C.c_double)]
     L.mvd_contributing_views.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
     L.mvd_get_estimate.argtypes = [H, C.c_void_p, C.c_int, C.c_int]
@@ -89,7 +90,8 @@ def lib():
                                       C.c_void_p, C.POINTER(C.c_int)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_version.restype = C.c_char_p
-    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_normalize_weights",
+    for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_grid_dims",
+                 "mvd_normalize_weights",
                  "mvd_contributing_views", "mvd_get_estimate",
                  "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
@@ -175,7 +177,7 @@ class Deconvolver:
     """
 
     def __init__(self, views=None, psfs=None, weights=None, lam=0.0, eps_scale=0.0, use_graphs=True,
-                 tile_config=0, device=None, _blocks=None):
+                 tile_config=0, device=None, boundary="circular", _blocks=None):
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
@@ -197,7 +199,8 @@ class Deconvolver:
         self._free_cb = FREE_FN(_free)
         self.stream = torch.cuda.current_stream(dev)
         opts = Options(float(lam), float(eps_scale), C.c_void_p(self.stream.cuda_stream), self._alloc_cb,
-                       self._free_cb, None, 1 if use_graphs else 0, int(tile_config))
+                       self._free_cb, None, 1 if use_graphs else 0, int(tile_config),
+                       {"circular": 0, "linear": 1}[boundary] if isinstance(boundary, str) else int(boundary))
         blocks = _blocks if _blocks is not None else [(views, psfs, weights)]
         on_device = any(isinstance(v, torch.Tensor) and v.is_cuda for b in blocks for v in b[0])
         with torch.cuda.device(dev):
@@ -305,9 +308,17 @@ class Deconvolver:
         _check(lib().mvd_set_tiles(self._h, int(cx), int(cy), int(cz)), self._h)
         return self
 
+    def grid_dims(self, block=0):
+        """The computation grid (nx, ny, nz) of a block (larger than the
+        volume with the linear boundary)."""
+        d = (C.c_int * 3)()
+        _check(lib().mvd_grid_dims(self._h, int(block), d), self._h)
+        return tuple(d)
+
     def max_lengths(self):
-        """Longest transform of each pass kind over the blocks: (nx/2, ny, nz)."""
-        return (max(d[0] // 2 for d in self.dims), max(d[1] for d in self.dims), max(d[2] for d in self.dims))
+        """Longest transform of each pass kind over the blocks' grids: (nx/2, ny, nz)."""
+        g = [self.grid_dims(b) for b in range(self.n_blocks)]
+        return (max(d[0] // 2 for d in g), max(d[1] for d in g), max(d[2] for d in g))
 
     def estimate(self, block=0, out=None):
         """The current estimate as a CUDA tensor (nz, ny, nx)."""
