@@ -271,7 +271,10 @@ def main():
         from paper_1308_0730_amd import tune
         tune.autotune(d, meta["variant"], iters=1, cache_path=None, verbose=True)
     tiles = d.tiles()
-    launch = {k: dict(mvd.tile_shape(i, c), candidate=c) for i, (k, c) in enumerate(zip(("x", "y", "z"), tiles))}
+    launch = {}
+    for i, (k, c) in enumerate(zip(("x", "y", "z"), tiles)):
+        sh = mvd.tile_shape(i, c)
+        launch[k] = dict(plans="per-length", candidate=c) if sh["exact_len"] < 0 else dict(sh, candidate=c)
     print(f"[bench] launch shapes {tiles} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
 
     its = meta["iterations"]

@@ -219,7 +219,10 @@ int mvd_set_psfs(mvd_handle* h, const float* const* psfs, const int* psf_dims, i
  * (rows or columns per workgroup), the longest transform it accepts and,
  * for compile-time plans, the one length it is built for (exact_len > 0;
  * usable only when every block has that length; 0 = runtime plan, any
- * 5-smooth length up to max_len).  mvd_tile_candidates lists, into
+ * 5-smooth length up to max_len; -1 = the per-length compile-time plans,
+ * one shape for each 5-smooth length up to max_len, launched per group of
+ * blocks of equal length: threads and per_tile are reported as 0 since they
+ * depend on the length).  mvd_tile_candidates lists, into
  * out[0..cap), the candidates for transforms of length max_len and returns
  * how many exist.  mvd_set_tiles selects one candidate per kind for a handle
  * (MVD_EINVAL if one does not fit its volumes); later iterations use them.

@@ -33,7 +33,8 @@ def test_header_matches_generator(tmp_path):
         assert rad == g.radices(L) and t == g.col_threads(L) and tx == 16
     for e in rows:
         M, wpb, rpw, rad = e[0], e[1], e[2], e[3:]
-        assert rad == g.radices(M) and wpb == 4 and rpw == max(1, min(16, 256 // M))
+        assert rad == g.radices(M, big=8) and wpb == 4 and rpw == g.row_rows(M)
+        assert 16 not in rad
 
 
 def test_radix_products_and_limits():
@@ -49,3 +50,7 @@ def test_radix_products_and_limits():
         L, t, tx = e[:3]
         assert t % 64 == 0 and t <= 1024
         assert tx * L * 8 + L * 8 <= 160 * 1024  # tile and twiddles fit the LDS
+    for e in _entries("MVD_EXACT_ROW"):
+        M, wpb, rpw = e[:3]
+        assert wpb * rpw * M * 8 + 2 * M * 8 <= 64 * 1024  # rows and twiddle tables in LDS
+        assert rpw * (M // max(e[3:])) >= 64 or rpw == 16  # the largest-radix stage fills a wave
