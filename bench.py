@@ -9,8 +9,9 @@ embryo-scale volume, 512x512x256 float32, six views at 60-degree steps,
 
 Prints one JSON line: voxel-view updates/s over the timed steps, the
 roofline position of the dominant pass (per-launch HIP-event durations,
-algorithmic bytes), and the FP64 CPU oracle timed on a bounded sample on this
-host.
+algorithmic bytes; against the vendor peak and against the runtime's device
+copy measured in the same run), and the FP64 CPU oracle timed on a bounded
+sample on this host.
 """
 from __future__ import annotations
 
@@ -97,6 +98,38 @@ def measured_traffic(name, kernel):
     return float(m.group(1)) if m else None
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Read + write GB/s of the runtime's device-to-device copy of nbytes,
+    best of reps (HIP events): the practical streaming ceiling measured on
+    the same GPU in the same run, beside the vendor peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        b.copy_(a)
+        e1.record(st)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best / 1e3) / 1e9
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(blocks, meta, budget_s=25.0):
     """The FP64 oracle on this host: view-updates of the same workload until
     about budget_s of work, scaled to voxel-view updates per second."""
@@ -117,7 +150,8 @@ def cpu_baseline(blocks, meta, budget_s=25.0):
         el = time.perf_counter() - t0
         if el >= budget_s or n >= pb.n * meta["iterations"]:
             break
-    return {"value": V * n / el / 1e9, "unit": "Gvox/s", "cores": os.cpu_count(), "kind": "oracle",
+    return {"value": V * n / el / 1e9, "unit": "Gvox/s", "cores": os.cpu_count(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{n} view-update(s) of block 0 of the same workload in FP64 (scipy.fft, all host cores), "
                       f"{el:.1f} s"}
 
@@ -309,6 +343,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": dom,
             "bytes_per_launch": by[dom], "avg_launch_ms": round(avg, 5)}
+    cbw = copy_bandwidth(torch)
+    roof["copy_GBps"] = round(cbw, 1)
+    roof["frac_of_copy"] = round(ach / cbw, 4)
     passes = {k: {"avg_ms": round(prof[k][0], 5), "launches": prof[k][1],
                   "GBps": round(by[k] / (prof[k][0] / 1e3) / 1e9, 1) if prof[k][0] > 0 else None}
               for k in PASS_NAMES}

@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(64 * WPB)
   __shared__ double rf[WPB];
   __shared__ unsigned ra[WPB], rb[WPB];
   int local;
-  const int jid = find_job(jobs, njobs, PASS_X, RW, local);
+  const int jid = find_job(jobs, njobs, PASS_X, RW, local, true);
   if (jid < 0) return;
   const JobDesc& J = jobs[jid];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;

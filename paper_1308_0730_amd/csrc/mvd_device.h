@@ -8,10 +8,15 @@
 namespace mvdk {
 
 // Map this workgroup to (job, tile within the job) by walking the jobs'
-// tile counts for the pass kind.
+// tile counts for the pass kind.  With reverse the last workgroup takes the
+// first tile.  The forward x passes run reversed: the y pass before them
+// writes the spectrum in ascending z and the y pass after them reads it in
+// ascending z, so each reader starts on the planes written last, which are
+// still held by the memory-side cache (the 256 MB Infinity Cache holds most
+// of an embryo-sized spectrum).
 __device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int njobs, int kind,
-                                        int param, int& local) {
-  int t = blockIdx.x;
+                                        int param, int& local, bool reverse = false) {
+  int t = reverse ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
   for (int j = 0; j < njobs; ++j) {
     const int c = mvd_tiles(jobs[j], kind, param);
     if (t < c) {
