@@ -29,6 +29,40 @@ __device__ __forceinline__ int find_job(const JobDesc* __restrict__ jobs, int nj
   return -1;
 }
 
+// Column tile `local` (< nxt * nl) of the z passes and the inverse y passes
+// -> (kx tile xt, line l): two halves of the kx tiles, the lower first, each
+// walked l-major with xt fastest.  The z pass writes the upper half last and
+// the inverse y pass after it walks its tiles backwards (see ytile_local),
+// so it starts on the half still held by the memory-side cache.  Halves
+// keep 1 KB runs along x between workgroups in flight; narrower slabs made
+// the z pass slower.
+__device__ __forceinline__ void half_tile(int local, int nxt, int nl, int& xt, int& l) {
+  const int sw = (nxt + 1) >> 1;
+  const int per = sw * nl;
+  const int s = local >= per;
+  const int r = local - s * per;
+  const int w = s ? nxt - sw : sw;
+  l = r / w;
+  xt = s * sw + r % w;
+}
+
+// Tile order of the y passes: the forward ones z-major with xt fastest (the
+// x pass before them ends on the planes of low z); the inverse ones
+// backwards over the half_tile order, the Nyquist-plane tiles (written last
+// by the z pass) first.
+template <bool INV>
+__device__ __forceinline__ void ytile(int local, int ntiles, int nxt, int nz, int& xt, int& z, int& t2) {
+  if (INV) local = ntiles - 1 - local;
+  t2 = local - nxt * nz;
+  if (t2 >= 0) return;
+  if (INV) {
+    half_tile(local, nxt, nz, xt, z);
+  } else {
+    xt = local % nxt;
+    z = local / nxt;
+  }
+}
+
 // Source accessor of the kernel lines of a z tile: tap d of the stored
 // kernel planes sits at position (d - cz) mod nz of a length-nz line, every
 // other position is zero.  base points at tap 0 of line 0; taps are ps apart.

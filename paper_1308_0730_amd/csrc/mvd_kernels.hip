@@ -285,14 +285,14 @@ __global__ void __launch_bounds__(T)
   float2* spec = reinterpret_cast<float2*>(J.spec);
   const int nxt = mvd_cdiv(M, TX);
   GTile g;
-  if (local < nxt * nz) {
-    const int xt = local % nxt, z = local / nxt;
+  int xt, z, t2;
+  ytile<INV>(local, mvd_tiles(J, PASS_Y, TX), nxt, nz, xt, z, t2);
+  if (t2 < 0) {
     g.base = spec + (int64_t)z * ny * M + xt * TX;
     g.ls = 1;
     g.ps = M;
     g.nl = min(TX, M - xt * TX);
   } else {
-    const int t2 = local - nxt * nz;
     g.base = spec + J.spec_main + (int64_t)t2 * TX * ny;
     g.ls = ny;
     g.ps = 1;
@@ -327,7 +327,8 @@ __global__ void __launch_bounds__(T)
   int64_t off, hoff;
   int ps, nl;
   if (local < nxt * ny) {
-    const int xt = local % nxt, y = local / nxt;
+    int xt, y;
+    half_tile(local, nxt, ny, xt, y);
     off = (int64_t)y * M + xt * TX;
     hoff = off;
     ps = ny * M;
