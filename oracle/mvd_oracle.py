@@ -460,18 +460,14 @@ def loss_value(psi, views, P):
     return float(sum(np.sum((circ_conv(psi, p) - np.asarray(phi, np.float64)) ** 2) for p, phi in zip(P, views)))
 
 
-def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
-    """Loss and its gradients for the sequential RL update (K_v = P_v*).
-
-    Returns (L, dL/dpsi0, [dL/dpsf_v]) with each PSF gradient on the raw
-    input extents of psfs[v]."""
-    pb = Problem(views, psfs, weights, lam)
+def _taped_run(pb, n_iter, psi0):
+    """The sequential RL run (K_v = P_v*) keeping every view-update's
+    intermediates for the reverse sweep."""
     P = pb.P
-    N = pb.n
     psi = np.asarray(psi0, dtype=np.float64).copy()
     tape = []
     for _ in range(n_iter):
-        for v in range(N):
+        for v in range(pb.n):
             w = None if pb.weights is None else pb.weights[v]
             b = circ_conv(psi, P[v])
             q = pb.views[v] / np.maximum(b, pb.eps)
@@ -481,6 +477,18 @@ def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
             new = t if w is None else psi + w * (t - psi)
             tape.append((v, psi, b, q, c, u, w))
             psi = new
+    return psi, tape
+
+
+def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
+    """Loss and its gradients for the sequential RL update (K_v = P_v*).
+
+    Returns (L, dL/dpsi0, [dL/dpsf_v]) with each PSF gradient on the raw
+    input extents of psfs[v]."""
+    pb = Problem(views, psfs, weights, lam)
+    P = pb.P
+    N = pb.n
+    psi, tape = _taped_run(pb, n_iter, psi0)
     L = 0.0
     gpsi = np.zeros_like(psi)
     gP = [np.zeros_like(p) for p in P]
@@ -489,6 +497,29 @@ def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
         L += float(np.sum(r * r))
         gpsi += circ_conv(2.0 * r, mirror(P[v]))
         gP[v] += circ_corr_window(2.0 * r, psi, P[v].shape)
+    gpsi, out = _reverse(pb, psfs, tape, gpsi, gP)
+    return L, gpsi, out
+
+
+def vjp(views, psfs, n_iter, psi0, gbar, weights=None, lam=0.0):
+    """Vector-Jacobian product of the unrolled run: for a given gbar (the
+    gradient of some scalar with respect to psi_n), the gradients of
+    <gbar, psi_n> with respect to psi0 and to the raw PSF values.
+
+    Returns (psi_n, d/dpsi0, [d/dpsf_v])."""
+    pb = Problem(views, psfs, weights, lam)
+    psi, tape = _taped_run(pb, n_iter, psi0)
+    gP = [np.zeros_like(p) for p in pb.P]
+    gpsi, out = _reverse(pb, psfs, tape, np.asarray(gbar, dtype=np.float64).copy(), gP)
+    return psi, gpsi, out
+
+
+def _reverse(pb, psfs, tape, gpsi, gP):
+    """Reverse sweep over the taped view-updates from the seed gpsi = d/dpsi_n
+    (and PSF gradients gP accumulated so far, on the padded odd boxes), then
+    through the normalisation of eq. 3 onto the raw PSF extents."""
+    P = pb.P
+    N = pb.n
     for (v, psi_in, b, q, c, u, w) in reversed(tape):
         g = gpsi
         tbar = g if w is None else w * g
@@ -511,7 +542,7 @@ def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
         gpad = gP[v]
         gn = (gpad - np.sum(gpad * P[v])) / S
         out.append(gn[:G.shape[0], :G.shape[1], :G.shape[2]])
-    return L, gpsi, out
+    return gpsi, out
 
 
 def loss_of(views, psfs, n_iter, psi0, weights=None, lam=0.0):

@@ -62,3 +62,54 @@ def test_gradient_matches_finite_differences(weights, lam):
         fd = (O.loss_of(views, p1, n, psi0, w, lam) - O.loss_of(views, p2, n, psi0, w, lam)) / (2 * hp)
         an = float(np.sum(gP[v] * dP))
         assert abs(fd - an) < 1e-5 * max(abs(an), 1e-3 * L), (v, fd, an)
+
+
+def _psi_n(views, psfs, n, psi0, w, lam):
+    pb = O.Problem(views, psfs, w, lam)
+    return pb.iterate(np.asarray(psi0, np.float64), n, O.RL)
+
+
+@pytest.mark.parametrize("weights,lam", [(False, 0.0), (True, 0.05)])
+def test_vjp_matches_finite_differences(weights, lam):
+    """The vector-Jacobian product against central differences of
+    <gbar, psi_n> computed with the forward iteration alone."""
+    rng = np.random.default_rng(3)
+    views, psfs, w, psi0 = small_case(rng, weights, lam)
+    n = 2
+    gbar = rng.normal(size=psi0.shape)
+    psi_n, gpsi, gP = O.vjp(views, psfs, n, psi0, gbar, w, lam)
+    assert O.rel_l2(psi_n, _psi_n(views, psfs, n, psi0, w, lam)) < 1e-13
+
+    def f(p, s0):
+        return float(np.sum(gbar * _psi_n(views, p, n, s0, w, lam)))
+
+    d = rng.normal(size=psi0.shape)
+    h = 1e-4
+    fd = (f(psfs, psi0 + h * d) - f(psfs, psi0 - h * d)) / (2 * h)
+    an = float(np.sum(gpsi * d))
+    assert abs(fd - an) < 1e-6 * max(abs(an), 1.0), (fd, an)
+    for v in range(3):
+        dP = rng.normal(size=psfs[v].shape)
+        hp = 1e-5 * psfs[v].max()
+        p1 = [p.copy() for p in psfs]
+        p2 = [p.copy() for p in psfs]
+        p1[v] = p1[v] + hp * dP
+        p2[v] = p2[v] - hp * dP
+        fd = (f(p1, psi0) - f(p2, psi0)) / (2 * hp)
+        an = float(np.sum(gP[v] * dP))
+        assert abs(fd - an) < 1e-5 * max(abs(an), 1.0), (v, fd, an)
+
+
+def test_vjp_is_linear_and_zero_seed_gives_zero():
+    rng = np.random.default_rng(4)
+    views, psfs, w, psi0 = small_case(rng, True, 0.05)
+    g1 = rng.normal(size=psi0.shape)
+    g2 = rng.normal(size=psi0.shape)
+    _, a1, b1 = O.vjp(views, psfs, 2, psi0, g1, w, 0.05)
+    _, a2, b2 = O.vjp(views, psfs, 2, psi0, g2, w, 0.05)
+    _, a3, b3 = O.vjp(views, psfs, 2, psi0, 2.0 * g1 - 3.0 * g2, w, 0.05)
+    assert O.rel_l2(a3, 2.0 * a1 - 3.0 * a2) < 1e-12
+    for x, y, z in zip(b1, b2, b3):
+        assert O.rel_l2(z, 2.0 * x - 3.0 * y) < 1e-12
+    _, a0, b0 = O.vjp(views, psfs, 2, psi0, np.zeros_like(g1), w, 0.05)
+    assert not a0.any() and not any(x.any() for x in b0)
