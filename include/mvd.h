@@ -209,6 +209,19 @@ int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
 int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
                   double* const* grad_psf, float* grad_psi0, int grad_kind);
 
+/* Vector-Jacobian product of the same unrolled run, for any scalar loss of
+ * the estimate: given grad_psi_n = dL/dpsi_n (nx*ny*nz floats, [z][y][x],
+ * grad_psi_n_kind host or device; not retained), returns dL/dG_v in
+ * grad_psf[v] and dL/dpsi0 in grad_psi0, exactly as mvd_loss_grad does
+ * (same arguments, same checkpointed adjoint passes, same zero derivative
+ * of active clamps), with the loss's own seed replaced by grad_psi_n: the
+ * reverse mode of the view-update of eq. 15 with weights and Tikhonov,
+ * iterated.  Recomputes the forward run from psi0 (NULL: the flat start),
+ * leaves psi = psi_n; synchronises.  MVD_EINVAL if grad_psi_n is NULL,
+ * MVD_ESTATE for batched or linear-boundary handles, MVD_RL only. */
+int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, const float* grad_psi_n,
+                 int grad_psi_n_kind, double* const* grad_psf, float* grad_psi0, int grad_kind);
+
 /* Replace the PSFs of a single-block handle (same count; extents may change
  * within the volume): recomputes their spectra; compound kernels are rebuilt
  * on their next use.  For PSF refinement loops. */

@@ -1,11 +1,16 @@
-"""Differentiable loss of the unrolled sequential RL deconvolution.
+"""Differentiable unrolled sequential RL deconvolution.
 
-MVDLoss is a torch.autograd.Function around the library's hand-written
-adjoint passes: forward runs n iterations from psi0 with the given PSFs and
-returns L = sum_v |psi_n (x) P_v - phi_v|^2; its gradients with respect to
-the PSF values and psi0 come from the same library call.  psf_from_theta
-builds the anisotropic Gaussian PSF of a view from (sigma_xy, sigma_z) in
-torch, so gradients reach the PSF parameters through autograd.
+Two torch.autograd.Functions around the library's hand-written adjoint
+passes:
+  * MVDLoss: forward runs n iterations from psi0 with the given PSFs and
+    returns L = sum_v |psi_n (x) P_v - phi_v|^2; its gradients with respect
+    to the PSF values and psi0 come from the same library call;
+  * MVDDeconvolve: forward returns psi_n itself, so any loss written in torch
+    can follow it; backward is the library's vector-Jacobian product
+    (mvd_backward), which recomputes the run from psi0 with checkpoints.
+psf_from_theta builds the anisotropic Gaussian PSF of a view from
+(sigma_xy, sigma_z) in torch, so gradients reach the PSF parameters through
+autograd.
 """
 from __future__ import annotations
 
@@ -33,6 +38,33 @@ class MVDLoss(torch.autograd.Function):
         gpsi = None if ctx.gpsi is None else (ctx.gpsi * float(gout)).to(torch.float32)
         n_psf = len(ctx.needs_input_grad) - 3
         gps = (None,) * n_psf if ctx.gp is None else tuple(gout * g for g in ctx.gp)
+        return (None, None, gpsi) + gps
+
+
+class MVDDeconvolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, handle, n_iter, psi0, *psfs):
+        host = [p.detach().to("cpu", torch.float32).numpy() for p in psfs]
+        handle.set_psfs(host)
+        handle.set_estimate(psi0.detach())
+        handle.iterate(int(n_iter), "rl")
+        out = handle.estimate().clone()
+        ctx.handle, ctx.n_iter, ctx.host = handle, int(n_iter), host
+        ctx.psi0 = psi0.detach()
+        ctx.meta = [(p.dtype, p.device) for p in psfs]
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        want_p = any(ctx.needs_input_grad[3:])
+        want_psi = ctx.needs_input_grad[2]
+        h = ctx.handle
+        h.set_psfs(ctx.host)  # the handle may have run other PSFs since the forward pass
+        gp, gpsi = h.backward(ctx.n_iter, ctx.psi0, gout, grad_psf=want_p, grad_psi0=want_psi)
+        gps = (None,) * len(ctx.meta) if gp is None else \
+            tuple(torch.from_numpy(g).to(dtype=dt, device=dev) for g, (dt, dev) in zip(gp, ctx.meta))
+        if gpsi is not None:
+            gpsi = gpsi.to(ctx.psi0.dtype)
         return (None, None, gpsi) + gps
 
 

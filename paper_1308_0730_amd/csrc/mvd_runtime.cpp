@@ -1154,13 +1154,18 @@ void x_init_rt(mvd_handle* h) {
   HIPCHECK(mvd_launch_x(args(h, h->stream, h->rt_grid[0]), h->rt_cfg[0], 0, 0, nullptr, h->d_flags, 1));
 }
 
+// seed == nullptr: the loss sum_v |psi_n (x) P_v - phi_v|^2 and its
+// gradients; otherwise the vector-Jacobian product with seed = d/dpsi_n
+// (seed_kind host or device) and no loss.
 void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
-                    double* const* grad_psf, float* grad_psi0, int grad_kind) {
+                    double* const* grad_psf, float* grad_psi0, int grad_kind, const float* seed = nullptr,
+                    int seed_kind = MVD_MEM_HOST) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "the differentiated form runs with the circular boundary only");
   if (variant != MVD_RL) bad("gradients are available for MVD_RL");
   if (n < 0) bad("n must be >= 0");
-  if (!loss) bad("loss is NULL");
+  if (!seed && !loss) bad("loss is NULL");
+  if (seed && seed_kind != MVD_MEM_HOST && seed_kind != MVD_MEM_DEVICE) bad("grad_psi_n_kind must be host or device");
   if (grad_psi0 && grad_kind != MVD_MEM_HOST && grad_kind != MVD_MEM_DEVICE) bad("grad_kind must be host or device");
   Block& B = h->blocks[0];
   const int N = h->nviews;
@@ -1183,11 +1188,16 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
     for (int v = 0; v < N; ++v) grad_forward_view(h, v);
   }
   HIPCHECK(hipMemcpyAsync(h->g_psiT, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed
-  HIPCHECK(hipMemsetAsync(h->g_gbar, 0, V * sizeof(float), st));
+  // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed, or the
+  // caller's seed
   HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)N * S * sizeof(double2), st));
+  if (seed)
+    HIPCHECK(hipMemcpyAsync(h->g_gbar, seed, V * sizeof(float),
+                            seed_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHECK(hipMemsetAsync(h->g_gbar, 0, V * sizeof(float), st));
   const LaunchArgs ax = args(h, st, h->rt_grid[0]);
-  for (int v = 0; v < N; ++v) {
+  for (int v = 0; v < N && !seed; ++v) {
     Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
     AdjPtrs ap = adj_ptrs(h, v);
     ap.part = h->g_gbar;
@@ -1203,9 +1213,11 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
       HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
     }
   }
-  HIPCHECK(mvd_launch_reduce(h->g_parts, h->rt_grid[0], N, h->g_loss, h->g_lr, h->g_ln, st));
-  std::vector<double> lv(N);
-  HIPCHECK(hipMemcpyAsync(lv.data(), h->g_loss, N * sizeof(double), hipMemcpyDeviceToHost, st));
+  std::vector<double> lv(N, 0.0);
+  if (!seed) {
+    HIPCHECK(mvd_launch_reduce(h->g_parts, h->rt_grid[0], N, h->g_loss, h->g_lr, h->g_ln, st));
+    HIPCHECK(hipMemcpyAsync(lv.data(), h->g_loss, N * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   if (want_grad) {
     // reverse sweep: recompute each iteration from its checkpoint, then the
     // adjoints of its view-updates in reverse order
@@ -1273,7 +1285,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
   HIPCHECK(hipStreamSynchronize(st));
   double L = 0;
   for (double x : lv) L += x;
-  *loss = L;
+  if (loss) *loss = L;
   h->spec_valid = false;
   h->iterations = n;
   if (read_flag(h)) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
@@ -1671,6 +1683,19 @@ int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0
     return MVD_EINVAL;
   }
   return guard(h, [&] { loss_grad_impl(h, n, variant, psi0, psi0_kind, loss, grad_psf, grad_psi0, grad_kind); });
+}
+
+int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, const float* grad_psi_n,
+                 int grad_psi_n_kind, double* const* grad_psf, float* grad_psi0, int grad_kind) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (!grad_psi_n) bad("grad_psi_n is NULL");
+    loss_grad_impl(h, n, variant, psi0, psi0_kind, nullptr, grad_psf, grad_psi0, grad_kind, grad_psi_n,
+                   grad_psi_n_kind);
+  });
 }
 
 int mvd_set_psfs(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {

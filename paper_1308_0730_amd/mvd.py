@@ -75,6 +75,8 @@ def lib():
     L.mvd_view_update.argtypes = [H, C.c_int, C.c_int]
     L.mvd_loss_grad.argtypes = [H, C.c_int, C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                 C.POINTER(C.c_void_p), C.c_void_p, C.c_int]
+    L.mvd_backward.argtypes = [H, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                               C.POINTER(C.c_void_p), C.c_void_p, C.c_int]
     L.mvd_set_psfs.argtypes = [H, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int]
     L.mvd_set_tiles.argtypes = [H, C.c_int, C.c_int, C.c_int]
     L.mvd_get_tiles.argtypes = [H, C.POINTER(C.c_int)]
@@ -96,7 +98,7 @@ def lib():
                  "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
-                 "mvd_tile_shape", "mvd_loss_grad", "mvd_set_psfs"):
+                 "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -277,12 +279,37 @@ class Deconvolver:
         (None: flat start) and, optionally, its gradients: a list of float64
         arrays shaped like the PSFs, and a CUDA tensor shaped like the volume.
         Returns (loss, grad_psfs or None, grad_psi0 or None)."""
+        src, gps, gp_ptrs, gpsi = self._grad_buffers(psi0, grad_psf, grad_psi0, psf_shapes)
+        loss = C.c_double()
+        rc = lib().mvd_loss_grad(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
+                                 C.byref(loss), _ptr_array(gp_ptrs),
+                                 None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
+        _check(rc, self._h)
+        return loss.value, gps, gpsi
+
+    def backward(self, n, psi0, grad_psi_n, grad_psf=True, grad_psi0=True, psf_shapes=None):
+        """Vector-Jacobian product of n RL iterations from psi0 (None: flat
+        start): for grad_psi_n = dL/dpsi_n of any scalar L, returns
+        (dL/dpsf list of float64 arrays or None, dL/dpsi0 CUDA tensor or None).
+        Leaves the estimate at psi_n."""
+        nx, ny, nz = self.dims[0]
+        src, gps, gp_ptrs, gpsi = self._grad_buffers(psi0, grad_psf, grad_psi0, psf_shapes)
+        g = grad_psi_n.detach().to(self.device, torch.float32).contiguous() if isinstance(grad_psi_n, torch.Tensor) \
+            else torch.from_numpy(np.ascontiguousarray(np.asarray(grad_psi_n, np.float32))).to(self.device)
+        if tuple(g.shape) != (nz, ny, nx):
+            raise ValueError(f"grad_psi_n has shape {tuple(g.shape)}, expected {(nz, ny, nx)}")
+        rc = lib().mvd_backward(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
+                                C.c_void_p(g.data_ptr()), MEM_DEVICE, _ptr_array(gp_ptrs),
+                                None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
+        _check(rc, self._h)
+        return gps, gpsi
+
+    def _grad_buffers(self, psi0, grad_psf, grad_psi0, psf_shapes):
         nx, ny, nz = self.dims[0]
         src = None
         if psi0 is not None:
             src = psi0.detach().to(self.device, torch.float32).contiguous() if isinstance(psi0, torch.Tensor) \
                 else torch.from_numpy(np.ascontiguousarray(np.asarray(psi0, np.float32))).to(self.device)
-        loss = C.c_double()
         shapes = psf_shapes or getattr(self, "_psf_shapes", None)
         gps = None
         gp_ptrs = None
@@ -290,13 +317,9 @@ class Deconvolver:
             if shapes is None:
                 raise ValueError("PSF shapes unknown: pass psf_shapes or call set_psfs first")
             gps = [np.zeros(sh, np.float64) for sh in shapes]
-            gp_ptrs = (C.c_void_p * len(gps))(*[g.ctypes.data for g in gps])
+            gp_ptrs = (C.c_void_p * len(gps))(*[x.ctypes.data for x in gps])
         gpsi = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if grad_psi0 else None
-        rc = lib().mvd_loss_grad(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
-                                 C.byref(loss), None if gp_ptrs is None else C.cast(gp_ptrs, C.POINTER(C.c_void_p)),
-                                 None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
-        _check(rc, self._h)
-        return loss.value, gps, gpsi
+        return src, gps, gp_ptrs, gpsi
 
     def tiles(self):
         """Current launch-shape candidates (x, y, z)."""
@@ -378,6 +401,10 @@ def create_raw(blocks, options=None):
     rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, None if options is None else C.byref(options))
     msg = lib().mvd_last_error(None).decode()
     return rc, (h if h.value else None), msg
+
+
+def _ptr_array(arr):
+    return None if arr is None else C.cast(arr, C.POINTER(C.c_void_p))
 
 
 def tile_candidates(kind, max_len):

@@ -54,6 +54,66 @@ def test_gradient_matches_oracle(mvd, weighted, lam):
         assert rel(a, b) <= 2e-4
 
 
+def grad_case(weighted, seed=5):
+    dims = (40, 36, 30)
+    s = synth.make_problem(dims, 8, [0.0, 70.0, 130.0], (5, 5, 7), 1.0, 2.0, 31)
+    rng = np.random.default_rng(seed)
+    psfs = [asym_psf(rng, (9, 7, 7), off) for off in ((0.6, -0.4, 0.3), (-0.5, 0.5, 0.7), (0.3, 0.2, -0.6))]
+    w = [np.clip(rng.uniform(-0.2, 1.2, size=s.views[0].shape), 0, 1).astype(np.float32) for _ in range(3)] \
+        if weighted else None
+    psi0 = rng.uniform(5, 25, size=s.views[0].shape).astype(np.float32)
+    return s, psfs, w, psi0, rng
+
+
+@pytest.mark.parametrize("weighted,lam", [(False, 0.0), (True, 0.02)])
+def test_backward_matches_oracle_vjp(mvd, weighted, lam):
+    """mvd_backward with a random upstream gradient against the oracle's
+    vector-Jacobian product; the handle is left at psi_n."""
+    s, psfs, w, psi0, rng = grad_case(weighted)
+    gbar = rng.normal(size=psi0.shape).astype(np.float32)
+    n = 3
+    psi_n, gpsi, gP = O.vjp(s.views, psfs, n, psi0.astype(np.float64), gbar.astype(np.float64), w, lam)
+    with mvd.Deconvolver(s.views, psfs, w, lam=lam) as d:
+        gp2, gpsi2 = d.backward(n, psi0, gbar)
+        gpsi2 = gpsi2.cpu().numpy()
+        e = d.estimate().cpu().numpy()
+        # host seed, PSF gradients only
+        gp3, none = d.backward(n, torch.from_numpy(psi0).cuda(), gbar, grad_psi0=False)
+    print(f"psi0 grad rel {rel(gpsi2, gpsi):.2e}; psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gp2, gP)]}; "
+          f"psi_n rel {rel(e, psi_n):.2e}")
+    assert none is None
+    assert rel(e, psi_n) <= 1e-5
+    assert rel(gpsi2, gpsi) <= 2e-4
+    for a, b, c in zip(gp2, gP, gp3):
+        assert rel(a, b) <= 2e-4
+        assert np.array_equal(a, c)
+
+
+def test_deconvolve_layer_under_a_torch_loss(mvd):
+    """MVDDeconvolve (psi_n as a differentiable torch output) under a loss
+    written in torch, L = sum (psi_n - truth)^2 over a mask: the gradients
+    torch receives in psi0 and the PSFs against the oracle's vector-Jacobian
+    product seeded with that loss's dL/dpsi_n."""
+    from paper_1308_0730_amd.autograd import MVDDeconvolve
+    s, psfs, w, psi0, rng = grad_case(False, seed=6)
+    truth = torch.from_numpy(s.truth.astype(np.float32)).cuda()
+    mask = torch.from_numpy((rng.uniform(size=psi0.shape) < 0.5).astype(np.float32)).cuda()
+    n = 2
+    with mvd.Deconvolver(s.views, psfs) as d:
+        p0 = torch.from_numpy(psi0).cuda().requires_grad_(True)
+        ps = [torch.from_numpy(p.astype(np.float64)).requires_grad_(True) for p in psfs]
+        out = MVDDeconvolve.apply(d, n, p0, *ps)
+        L = (((out - truth) ** 2) * mask).sum()
+        L.backward()
+        gbar = (2.0 * (out.detach() - truth) * mask).cpu().numpy().astype(np.float64)
+    psi_n, gpsi, gP = O.vjp(s.views, psfs, n, psi0.astype(np.float64), gbar)
+    assert rel(out.detach().cpu().numpy(), psi_n) <= 1e-5
+    assert rel(p0.grad.cpu().numpy(), gpsi) <= 2e-4
+    for a, b in zip(ps, gP):
+        assert a.grad.dtype == torch.float64
+        assert rel(a.grad.numpy(), b) <= 2e-4
+
+
 def test_forward_only_loss(mvd):
     dims = (40, 36, 30)
     s = synth.make_problem(dims, 8, [0.0, 90.0], (5, 5, 7), 1.0, 2.0, 32)
