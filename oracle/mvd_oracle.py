@@ -27,10 +27,16 @@ Conventions (the paper is silent on them; each is a documented reading):
   * Weights blend the step: psi <- psi + w (t - psi)  (section on partially
     overlapping data: w is the fraction of one RL step that is applied).
 
-Parity status: every function here is pinned by tests in
-tests/test_oracle_pins.py (brute-force direct convolution, explicit-matrix
+Parity status: every function here is pinned by tests that do not retype
+it: tests/test_oracle_pins.py (brute-force direct convolution, explicit-matrix
 EM/OSEM, fixed point, flux, non-negativity, closed forms, delta-kernel special
-cases, finite differences).  No function is "parity unpinned".
+cases), tests/test_oracle_combined.py (combined updates: explicit EM, fixed
+point, single-view and identical-view reductions), tests/test_oracle_weights.py
+(normalisation modes and the contributing-view image on hand-counted cases),
+tests/test_oracle_linear.py (linear boundary: explicit restricted-matrix EM,
+fixed point, delta kernels) and tests/test_oracle_grad.py (adjoint identities,
+central finite differences of the loss and of <gbar, psi_n>).  No function is
+"parity unpinned".
 """
 from __future__ import annotations
 

@@ -9,6 +9,7 @@
 // ratio, update) can use operands prefetched into registers in that order.
 #pragma once
 #include "fft_engine.h"
+#include "fft_small_tw.h"
 
 namespace mvdk {
 
@@ -76,6 +77,67 @@ struct Dft<16, INV> {
     }
   }
 };
+
+// R-point DFT of a composite radix R = R1 R2 in registers (Cooley-Tukey,
+// decimation in time): X[k1 + R1 k2] = sum_n2 W_R^{n2 k1} W_R2^{n2 k2}
+// sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}.  The twiddles W_R^m are constants
+// (m = n2 k1 mod R after unrolling); quarter turns are exact swaps.
+template <int R1, int R2, bool INV>
+struct DftPQ {
+  static constexpr int R = R1 * R2;
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      float2 t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + n2];
+      Dft<R1, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const int m = (n2 * k1) % R;
+        float2 x = t[k1];
+        if (m == 0) {
+        } else if (4 * m == R) {
+          x = mul_mi<INV>(x);
+        } else if (2 * m == R) {
+          x = make_float2(-x.x, -x.y);
+        } else if (4 * m == 3 * R) {
+          x = mul_mi<!INV>(x);
+        } else {
+          const float c = SmallTw<R>::c[m];
+          const float s = INV ? SmallTw<R>::s[m] : -SmallTw<R>::s[m];
+          x = make_float2(c * x.x - s * x.y, c * x.y + s * x.x);
+        }
+        a[n2][k1] = x;
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 t[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[n2][k1];
+      Dft<R2, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+    }
+  }
+};
+
+template <bool INV>
+struct Dft<6, INV> : DftPQ<2, 3, INV> {};
+template <bool INV>
+struct Dft<9, INV> : DftPQ<3, 3, INV> {};
+template <bool INV>
+struct Dft<10, INV> : DftPQ<2, 5, INV> {};
+template <bool INV>
+struct Dft<12, INV> : DftPQ<4, 3, INV> {};
+template <bool INV>
+struct Dft<15, INV> : DftPQ<3, 5, INV> {};
+template <bool INV>
+struct Dft<20, INV> : DftPQ<4, 5, INV> {};
+template <bool INV>
+struct Dft<25, INV> : DftPQ<5, 5, INV> {};
 
 // Accessor adaptors: the five-argument store used by the compile-time stages.
 template <class A>

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(64 * WPB)
       const int r = RPW == 1 ? 0 : udiv(it, mP);
       const int k = it - r * npair;
       if (r < nrw && k < npair) {
-        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        const int64_t rbase = (int64_t)(wrow0 + r) * J.Mp;
         xa[i] = spec[rbase + k];
         xb[i] = (k == 0) ? nyq[wrow0 + r] : spec[rbase + M - k];
       }
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(64 * WPB)
       const int r = RPW == 1 ? 0 : udiv(it, mP);
       const int k = it - r * npair;
       if (r < nrw && k < npair) {
-        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        const int64_t rbase = (int64_t)(wrow0 + r) * J.Mp;
         const float2 zk = L.ld(r, k);
         if (k == 0) {
           spec[rbase] = make_float2(zk.x + zk.y, 0.f);
@@ -256,9 +256,9 @@ __global__ void __launch_bounds__(T)
   int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
-    off = (int64_t)y * M + xt * TX;
+    off = (int64_t)y * J.Mp + xt * TX;
     hoff = off;
-    ps = ny * M;
+    ps = ny * J.Mp;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
@@ -320,8 +320,8 @@ __global__ void __launch_bounds__(T)
 // T1[dz][ky][kx] = sum_kz A[kz][ky][kx] exp(+2 pi i kz (dz - cz) / nz) for kx
 // in [0, M] (the main part and the Nyquist plane), dz in the window.
 __global__ void __launch_bounds__(256)
-    k_idft_z(const double2* __restrict__ A, int M, int ny, int nz, int wz, const double2* __restrict__ twz,
-             double2* __restrict__ T1) {
+    k_idft_z(const double2* __restrict__ A, int M, int Mp, int ny, int nz, int wz,
+             const double2* __restrict__ twz, double2* __restrict__ T1) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)(M + 1) * ny * wz;
   if (idx >= total) return;
@@ -330,10 +330,10 @@ __global__ void __launch_bounds__(256)
   const int ky = (int)(rest % ny);
   const int dz = (int)(rest / ny);
   const int d = dz - (wz - 1) / 2;
-  const int64_t main_elems = (int64_t)M * ny * nz;
+  const int64_t main_elems = (int64_t)Mp * ny * nz;
   double sr = 0.0, si = 0.0;
   for (int k = 0; k < nz; ++k) {
-    const double2 a = kx < M ? A[((int64_t)k * ny + ky) * M + kx] : A[main_elems + (int64_t)k * ny + ky];
+    const double2 a = kx < M ? A[((int64_t)k * ny + ky) * Mp + kx] : A[main_elems + (int64_t)k * ny + ky];
     int64_t m = ((int64_t)k * d) % nz;
     if (m < 0) m += nz;
     const double2 w = twz[m];  // exp(-2 pi i m / nz); conjugated below
@@ -400,10 +400,10 @@ hipError_t mvd_launch_idft_yx(const double2* T1, int M, int nx, int ny, int wx, 
   return hipGetLastError();
 }
 
-hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
-                             hipStream_t s) {
+hipError_t mvd_launch_idft_z(const double2* A, int M, int Mp, int ny, int nz, int wz, const double2* twz,
+                             double2* T1, hipStream_t s) {
   const int64_t total = (int64_t)(M + 1) * ny * wz;
-  k_idft_z<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(A, M, ny, nz, wz, twz, T1);
+  k_idft_z<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(A, M, Mp, ny, nz, wz, twz, T1);
   return hipGetLastError();
 }
 

@@ -203,9 +203,9 @@ __global__ void __launch_bounds__(T)
   int xt, z, t2;
   ytile<INV>(local, mvd_tiles(J, PASS_Y, TX), nxt, nz, xt, z, t2);
   if (t2 < 0) {
-    g.base = spec + (int64_t)z * ny * M + xt * TX;
+    g.base = spec + (int64_t)z * ny * J.Mp + xt * TX;
     g.ls = 1;
-    g.ps = M;
+    g.ps = J.Mp;
     g.nl = min(TX, M - xt * TX);
   } else {
     g.base = spec + J.spec_main + (int64_t)t2 * TX * ny;
@@ -241,9 +241,9 @@ __global__ void __launch_bounds__(T)
   if (local < nxt * ny) {
     int xt, y;
     half_tile(local, nxt, ny, xt, y);
-    off = (int64_t)y * M + xt * TX;
+    off = (int64_t)y * J.Mp + xt * TX;
     hoff = off;
-    ps = ny * M;
+    ps = ny * J.Mp;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
@@ -315,9 +315,9 @@ __global__ void __launch_bounds__(T)
   int ps, nl;
   if (local < nxt * ny) {
     const int xt = local % nxt, y = local / nxt;
-    off = (int64_t)y * M + xt * TX;
+    off = (int64_t)y * J.Mp + xt * TX;
     hoff = off;
-    ps = ny * M;
+    ps = ny * J.Mp;
     nl = min(TX, M - xt * TX);
   } else {
     const int t2 = local - nxt * ny;
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(64 * WPB)
       const int it = lane + i * 64;
       const int r = it / NPAIR, k = it % NPAIR;
       if (r < nrw) {
-        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        const int64_t rbase = (int64_t)(wrow0 + r) * J.Mp;
         xa[i] = spec[rbase + k];
         xb[i] = (k == 0) ? nyq[wrow0 + r] : spec[rbase + M - k];
       }
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(64 * WPB)
       const int it = lane + i * 64;
       const int r = it / NPAIR, k = it % NPAIR;
       if (r < nrw) {
-        const int64_t rbase = (int64_t)(wrow0 + r) * M;
+        const int64_t rbase = (int64_t)(wrow0 + r) * J.Mp;
         const float2 zk = L.ld(r, k);
         if (k == 0) {
           spec[rbase] = make_float2(zk.x + zk.y, 0.f);

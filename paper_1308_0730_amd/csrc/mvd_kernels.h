@@ -60,8 +60,8 @@ hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partia
                            const AdjPtrs& ap);
 hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int conjH, float2* s_out,
                            const float2* s_in, double2* acc, int acc_mode);
-hipError_t mvd_launch_idft_z(const double2* A, int M, int ny, int nz, int wz, const double2* twz, double2* T1,
-                             hipStream_t s);
+hipError_t mvd_launch_idft_z(const double2* A, int M, int Mp, int ny, int nz, int wz, const double2* twz,
+                             double2* T1, hipStream_t s);
 // y and x stages after the z stage: out[dz][dy][dx] (FP64, no 1/V)
 hipError_t mvd_launch_idft_yx(const double2* T1, int M, int nx, int ny, int wx, int wy, int wz, const double2* twx,
                               const double2* twy, double2* T2, double* out, hipStream_t s);

@@ -41,6 +41,7 @@ struct Error : std::runtime_error {
 
 struct Block {
   int nx = 0, ny = 0, nz = 0, M = 0;
+  int Mp = 0;  // row pitch of the main half spectrum and of the kernel planes: M rounded up to 16
   int64_t V = 0, spec_main = 0, spec_elems = 0;
   // common z window of the stored kernel planes (odd, centred) and the
   // per-view size of a kernel-plane array; kz_cap is the allocated window
@@ -307,7 +308,7 @@ void set_kernel_window(Block& B) {
   for (const auto& K : B.P) kz = std::max(kz, K.kz);
   B.kz = kz;
   B.cz = (kz - 1) / 2;
-  B.h_main = (int64_t)B.M * B.ny * kz;
+  B.h_main = (int64_t)B.Mp * B.ny * kz;
   B.h_elems = B.h_main + (int64_t)B.ny * kz;
 }
 
@@ -326,7 +327,7 @@ void upload_kernel(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* ds
       for (int kx = 0; kx <= M; ++kx) {
         const mvdh::cd a = A2[((size_t)dz * ny + ky) * (M + 1) + kx] * inv;
         const size_t d = (size_t)(dz + d0);
-        const size_t o = kx < M ? (d * ny + ky) * M + kx : (size_t)B.h_main + d * ny + ky;
+        const size_t o = kx < M ? (d * ny + ky) * B.Mp + kx : (size_t)B.h_main + d * ny + ky;
         hk[2 * o] = (float)a.real();
         hk[2 * o + 1] = (float)a.imag();
       }
@@ -379,6 +380,7 @@ void build_jobs(mvd_handle* h) {
     j.ny = B.ny;
     j.nz = B.nz;
     j.M = B.M;
+    j.Mp = B.Mp;
     j.nviews = h->nviews;
     j.plan_x = h->plan_of_len.at(B.M);
     j.plan_y = h->plan_of_len.at(B.ny);
@@ -606,8 +608,9 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
         bad("block " + std::to_string(b) + ": the volume plus its PSF margin exceeds the largest transform length");
     }
     B.M = B.nx / 2;
+    B.Mp = (B.M + 15) & ~15;
     B.V = (int64_t)B.nx * B.ny * B.nz;
-    B.spec_main = (int64_t)B.M * B.ny * B.nz;
+    B.spec_main = (int64_t)B.Mp * B.ny * B.nz;
     B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
     B.psi = (float*)h->dalloc(B.V * sizeof(float));
     B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
@@ -1261,7 +1264,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
       for (int v = 0; v < N; ++v) {
         if (!grad_psf[v]) continue;
         const mvdh::Kern& P = B.P[v];
-        HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
+        HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.Mp, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
         HIPCHECK(mvd_launch_idft_yx(h->g_t1, B.M, B.nx, B.ny, P.kx, P.ky, P.kz, h->g_twx, h->g_twy, h->g_t2,
                                     h->g_gw, st));
         std::vector<double> g((size_t)P.kx * P.ky * P.kz);

@@ -41,11 +41,12 @@ struct JobDesc {
   int nviews;
   int plan_x, plan_y, plan_z;  // plans of lengths M, ny, nz
   int pp;                      // offset of exp(-2 pi i k / nx), k < M, in the twiddle pool
-  int pad0;
+  int Mp;                      // row pitch of the main half spectrum (complex): M rounded up
+                               // to 16, so every row starts on a 128-byte line
   int64_t V;
-  int64_t spec_main;           // M * ny * nz
+  int64_t spec_main;           // Mp * ny * nz
   int64_t spec_elems;          // spec_main + ny * nz
-  int64_t h_main;              // M * ny * kz: start of a kernel's kx = M taps
+  int64_t h_main;              // Mp * ny * kz: start of a kernel's kx = M taps
   int64_t h_elems;             // h_main + ny * kz: complex entries per view of H[role]
   float* psi;
   float* spec;                 // complex interleaved, spec_elems entries

@@ -33,7 +33,7 @@ def test_header_matches_generator(tmp_path):
         assert rad == g.radices(L) and t == g.col_threads(L) and tx == 16
     for e in rows:
         M, wpb, rpw, rad = e[0], e[1], e[2], e[3:]
-        assert rad == g.radices(M, big=8) and wpb == 4 and rpw == g.row_rows(M)
+        assert rad == g.row_radices(M) and wpb == 4 and rpw == g.row_rows(M)
         assert 16 not in rad
 
 
@@ -43,7 +43,7 @@ def test_radix_products_and_limits():
             L, rad = e[0], e[3:]
             prod = 1
             for r in rad:
-                assert r in (2, 3, 4, 5, 8, 16)
+                assert r in (2, 3, 4, 5, 8, 16) + _gen().COMPOSITE
                 prod *= r
             assert prod == L
     for e in _entries("MVD_EXACT_COL"):
@@ -52,5 +52,45 @@ def test_radix_products_and_limits():
         assert tx * L * 8 + L * 8 <= 160 * 1024  # tile and twiddles fit the LDS
     for e in _entries("MVD_EXACT_ROW"):
         M, wpb, rpw = e[:3]
-        assert wpb * rpw * M * 8 + 2 * M * 8 <= 64 * 1024  # rows and twiddle tables in LDS
-        assert rpw * (M // max(e[3:])) >= 64 or rpw == 16  # the largest-radix stage fills a wave
+        assert wpb * rpw * M * 8 <= _gen().ROW_LDS  # rows of a workgroup within the LDS budget
+        # the largest-radix stage fills a wave unless 16 rows or the LDS budget stop it
+        assert rpw * (M // max(e[3:])) >= 64 or rpw == 16 or wpb * (rpw + 1) * M * 8 > _gen().ROW_LDS
+
+
+def test_composite_twiddle_header():
+    """fft_small_tw.h holds cos and sin of 2 pi m / R for every composite
+    radix, as the generator computes them."""
+    import math
+    g = _gen()
+    txt = open(os.path.join(CSRC, "fft_small_tw.h")).read()
+    for R in g.COMPOSITE:
+        body = txt.split(f"struct SmallTw<{R}> {{")[1].split("\n};")[0]
+        c = [float(x.rstrip("f")) for x in re.search(r"c\[\d+\] = \{([^}]*)\}", body).group(1).split(",")]
+        s = [float(x.rstrip("f")) for x in re.search(r"s\[\d+\] = \{([^}]*)\}", body).group(1).split(",")]
+        assert len(c) == len(s) == R
+        for m in range(R):
+            assert abs(c[m] - math.cos(2 * math.pi * m / R)) < 1e-15
+            assert abs(s[m] - math.sin(2 * math.pi * m / R)) < 1e-15
+
+
+def test_composite_decomposition_algebra():
+    """The R1 x R2 register butterfly's index map and twiddles (inputs
+    x[R2 n1 + n2], inner DFTs over n1, twiddle exp(-2 pi i n2 k1 / R), outer
+    DFTs over n2, output X[k1 + R1 k2]) give the R-point DFT."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+    for R in _gen().COMPOSITE:
+        for R1 in range(2, R):
+            if R % R1:
+                continue
+            R2 = R // R1
+            x = rng.normal(size=R) + 1j * rng.normal(size=R)
+            a = np.empty((R2, R1), complex)
+            for n2 in range(R2):
+                t = np.fft.fft(x[n2::R2])  # x[R2 n1 + n2] over n1
+                a[n2] = t * np.exp(-2j * np.pi * n2 * np.arange(R1) / R)
+            X = np.empty(R, complex)
+            for k1 in range(R1):
+                X[k1 + R1 * np.arange(R2)] = np.fft.fft(a[:, k1])
+            assert np.allclose(X, np.fft.fft(x), atol=1e-12)
+
