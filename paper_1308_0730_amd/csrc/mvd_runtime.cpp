@@ -84,19 +84,24 @@ struct mvd_handle {
   int force_cfg = 0;
   // device tables
   JobDesc* d_jobs = nullptr;
-  // per pass kind: the job table sorted by that kind's length, and the
-  // groups of equal length launched one by one with the per-length
-  // compile-time plans
+  // per pass kind: the job table sorted by (lane, that kind's length), and
+  // the groups of equal lane and length launched one by one with the
+  // per-length compile-time plans
   struct Group {
     int len, first, njobs, grid, part_off;
     int lane;  // 0: the pass's stream, 1..kSide: side stream lane - 1
   };
-  // side streams (default priority) that run groups of one pass concurrently,
-  // forked from and joined back into the pass's stream with events
+  // side streams (default priority).  Every block has a lane (longest
+  // processing time first over the blocks' voxel counts), so all groups of a
+  // block run on one stream in pass order: a sequential iteration forks the
+  // side streams once and joins them at its end (defer_join); other
+  // sequences fork and join around every pass.
   static constexpr int kSide = 3;
   hipStream_t side[kSide] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kSide] = {};
+  bool defer_join = false;
+  std::vector<int> block_lane;
   JobDesc* d_jobs_k[3] = {nullptr, nullptr, nullptr};
   std::vector<int> order[3];
   std::vector<Group> groups[3];
@@ -407,12 +412,30 @@ void build_jobs(mvd_handle* h) {
   }
   HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                           h->stream));
+  // block lanes: largest block first onto the least loaded lane
+  const int nb = (int)h->blocks.size();
+  h->block_lane.assign(nb, 0);
+  {
+    std::vector<int> idx(nb);
+    for (int i = 0; i < nb; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h->blocks[a].V > h->blocks[b].V; });
+    int64_t load[1 + mvd_handle::kSide] = {};
+    for (int i : idx) {
+      int best = 0;
+      for (int l = 1; l <= mvd_handle::kSide; ++l)
+        if (load[l] < load[best]) best = l;
+      h->block_lane[i] = best;
+      load[best] += h->blocks[i].V;
+    }
+  }
   for (int k = 0; k < 3; ++k) {
     auto& ord = h->order[k];
     ord.resize(h->jobs.size());
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return job_len(h->blocks[a], k) < job_len(h->blocks[b], k); });
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      const int la = h->block_lane[a], lb = h->block_lane[b];
+      return la != lb ? la < lb : job_len(h->blocks[a], k) < job_len(h->blocks[b], k);
+    });
     std::vector<JobDesc> sorted;
     for (int i : ord) sorted.push_back(h->jobs[i]);
     HIPCHECK(hipMemcpyAsync(h->d_jobs_k[k], sorted.data(), sorted.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
@@ -448,15 +471,16 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
       g[k] = total_tiles(h, k, mvd_cfg_param(k, c[k]));
       continue;
     }
-    // groups of equal length in the sorted job order
+    // groups of equal lane and length in the sorted job order
     int64_t tiles = 0;
     const auto& ord = h->order[k];
     for (size_t i = 0; i < ord.size();) {
       const int len = job_len(h->blocks[ord[i]], k);
+      const int lane = h->block_lane[ord[i]];
       const int param = mvd_exact_param(k, len);
-      mvd_handle::Group gr{len, (int)i, 0, 0, (int)tiles};
+      mvd_handle::Group gr{len, (int)i, 0, 0, (int)tiles, lane};
       int64_t gt = 0;
-      for (; i < ord.size() && job_len(h->blocks[ord[i]], k) == len; ++i) {
+      for (; i < ord.size() && job_len(h->blocks[ord[i]], k) == len && h->block_lane[ord[i]] == lane; ++i) {
         gt += mvd_tiles(h->jobs[ord[i]], k, param);
         ++gr.njobs;
       }
@@ -467,18 +491,6 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
     }
     if (tiles > 0x7fffffff) bad("too many tiles");
     g[k] = (int)tiles;
-    // lanes: largest group first onto the least loaded lane
-    std::vector<int> idx(h->groups[k].size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h->groups[k][a].grid > h->groups[k][b].grid; });
-    int64_t load[1 + mvd_handle::kSide] = {};
-    for (int i : idx) {
-      int best = 0;
-      for (int l = 1; l <= mvd_handle::kSide; ++l)
-        if (load[l] < load[best]) best = l;
-      h->groups[k][i].lane = best;
-      load[best] += h->groups[k][i].grid;
-    }
   }
   const int gx = g[0], gy = g[1], gz = g[2];
   if ((size_t)h->nviews * gx > h->parts_cap) {
@@ -778,9 +790,14 @@ LaunchArgs group_args(mvd_handle* h, hipStream_t s, int kind, const mvd_handle::
 
 // The groups of one pass: each on its lane's stream; side lanes are forked
 // from s by an event and joined back before the pass is complete, so the
-// next pass on s sees every group's writes.
+// next pass on s sees every group's writes.  Under defer_join the side
+// streams were forked before the sequence and are joined after it.
 template <class F>
 void run_groups(mvd_handle* h, hipStream_t s, int kind, F&& launch) {
+  if (h->defer_join) {
+    for (const auto& g : h->groups[kind]) HIPCHECK(launch(g, g.lane ? h->side[g.lane - 1] : s));
+    return;
+  }
   unsigned used = 0;
   for (const auto& g : h->groups[kind]) used |= 1u << g.lane;
   const bool fork = (used & ~1u) != 0;
@@ -876,9 +893,34 @@ void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t
     timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
 }
 
-// One iteration: every view once, in index order (section 7).
+// One iteration: every view once, in index order (section 7).  When every
+// pass kind runs in groups and blocks sit on several lanes, each lane's
+// blocks go through all view-updates on their own stream, joined once at
+// the end (blocks are independent; stream order keeps each block's passes
+// in sequence).
 void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t = nullptr) {
-  for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, t);
+  bool lanes = false;
+  for (int l : h->block_lane) lanes |= l != 0;
+  const bool grouped = h->cfg_x == mvd_exact_cfg(PASS_X) && h->cfg_y == mvd_exact_cfg(PASS_Y) &&
+                       h->cfg_z == mvd_exact_cfg(PASS_Z);
+  if (!lanes || !grouped || t) {
+    for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, t);
+    return;
+  }
+  HIPCHECK(hipEventRecord(h->ev_fork, s));
+  for (int l = 0; l < mvd_handle::kSide; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
+  h->defer_join = true;
+  try {
+    for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, nullptr);
+  } catch (...) {
+    h->defer_join = false;
+    throw;
+  }
+  h->defer_join = false;
+  for (int l = 0; l < mvd_handle::kSide; ++l) {
+    HIPCHECK(hipEventRecord(h->ev_join[l], h->side[l]));
+    HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l], 0));
+  }
 }
 
 // One combined update (eq. 51): every view's back-projected ratio is taken
