@@ -99,3 +99,17 @@ def test_batched_every_launch_shape(mvd):
                 b.iterate(1, O.EFF)
                 for i in range(3):
                     np.testing.assert_array_equal(b.estimate(i).cpu().numpy(), ref2[i])
+
+
+def test_autotune_restores_estimates(mvd):
+    """The autotuner runs passes and whole iterations on the handle; every
+    block's estimate is as before afterwards, and the chosen shapes are set."""
+    from paper_1308_0730_amd import tune
+    blocks = [block(d, 400 + i) for i, d in enumerate(DIMS[:4])]
+    with mvd.Deconvolver.batch(blocks) as b:
+        b.iterate(1, O.EFF)
+        before = [b.estimate(i).cpu().numpy() for i in range(4)]
+        tiles, _ = tune.autotune(b, "eff", iters=1, cache_path=None)
+        assert tuple(b.tiles()) == tuple(tiles)
+        for i in range(4):
+            np.testing.assert_array_equal(b.estimate(i).cpu().numpy(), before[i])
