@@ -27,6 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 SOURCES = [
     ("mvd_kernels.hip", True),
     ("mvd_adjoint.hip", True),
+    ("mvd_exact_class.hip", True),
     ("mvd_exact_z.hip", True),
     ("mvd_exact_zext.hip", True),
     ("mvd_exact_x_comb.hip", True),

@@ -186,16 +186,8 @@ using namespace ctp;
 // ---------------------------------------------------------------------------
 // y pass (see k_ypass): complex transform along y of TX adjacent columns.
 template <bool INV, int T, int TX, int L, int... Rs>
-__global__ void __launch_bounds__(T)
-    k_ypass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
-               const float2* __restrict__ twp, int v) {
-  __shared__ float2 lds[L * TX];
-  __shared__ float2 s_tw[L];
-  int local;
-  const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
-  if (jid < 0) return;
-  const JobDesc& J = jobs[jid];
-  if (v >= J.nviews) return;
+__device__ __forceinline__ void ypass_tile(float2* lds, float2* s_tw, const JobDesc& J, int local,
+                                           const FftPlan* __restrict__ plans, const float2* __restrict__ twp) {
   const int M = J.M, ny = J.ny, nz = J.nz;
   float2* spec = reinterpret_cast<float2*>(J.spec);
   const int nxt = mvd_cdiv(M, TX);
@@ -219,21 +211,28 @@ __global__ void __launch_bounds__(T)
   CtRun<INV, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, g, LdsCol<TX>{lds}, out);
 }
 
-// ---------------------------------------------------------------------------
-// z pass with the spectral product (see k_zconv).
-template <int T, int TX, int L, int... Rs>
+template <bool INV, int T, int TX, int L, int... Rs>
 __global__ void __launch_bounds__(T)
-    k_zconv_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
-               const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
-  constexpr int RL = LastRadix<Rs...>::value;
-  using LM = LastMap<L, RL, T, TX, true>;
+    k_ypass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+               const float2* __restrict__ twp, int v) {
   __shared__ float2 lds[L * TX];
   __shared__ float2 s_tw[L];
   int local;
-  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
   if (jid < 0) return;
   const JobDesc& J = jobs[jid];
   if (v >= J.nviews) return;
+  ypass_tile<INV, T, TX, L, Rs...>(lds, s_tw, J, local, plans, twp);
+}
+
+// ---------------------------------------------------------------------------
+// z pass with the spectral product (see k_zconv).
+template <int T, int TX, int L, int... Rs>
+__device__ __forceinline__ void zconv_tile(float2* lds, float2* s_tw, const JobDesc& J, int local,
+                                           const FftPlan* __restrict__ plans, const float2* __restrict__ twp,
+                                           int v, int role, int conjH, int src_saved) {
+  constexpr int RL = LastRadix<Rs...>::value;
+  using LM = LastMap<L, RL, T, TX, true>;
   const int M = J.M, ny = J.ny;
   const int nxt = mvd_cdiv(M, TX);
   int64_t off, hoff;
@@ -290,6 +289,80 @@ __global__ void __launch_bounds__(T)
   CtRun<false, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, RegSrc<MB1, R1>{dp}, S, mul);
   Plain<GTile> out{g};
   CtRun<true, L, T, TX, true, SYNC_BLOCK, 1, true, Rs...>::run(threadIdx.x, s_tw, S, S, out);
+}
+
+template <int T, int TX, int L, int... Rs>
+__global__ void __launch_bounds__(T)
+    k_zconv_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+               const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
+  __shared__ float2 lds[L * TX];
+  __shared__ float2 s_tw[L];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  zconv_tile<T, TX, L, Rs...>(lds, s_tw, J, local, plans, twp, v, role, conjH, src_saved);
+}
+
+// ---------------------------------------------------------------------------
+// Column passes over blocks of several lengths in one launch: a class of
+// per-length plans ColPlan<L, radices...> sharing one thread count; every
+// workgroup runs the plan of its job's length (jobs sorted by length, so
+// the workgroups in flight mostly share one plan's code), in LDS sized for
+// the class's longest length.
+template <int L, int... Rs>
+struct ColPlan {};
+
+template <class P>
+struct ColRun;
+template <int L, int... Rs>
+struct ColRun<ColPlan<L, Rs...>> {
+  template <bool INV, int T, int TX>
+  static __device__ __forceinline__ bool y(int n, float2* lds, float2* s_tw, const JobDesc& J, int local,
+                                           const FftPlan* __restrict__ plans, const float2* __restrict__ twp) {
+    if (n != L) return false;
+    ypass_tile<INV, T, TX, L, Rs...>(lds, s_tw, J, local, plans, twp);
+    return true;
+  }
+  template <int T, int TX>
+  static __device__ __forceinline__ bool z(int n, float2* lds, float2* s_tw, const JobDesc& J, int local,
+                                           const FftPlan* __restrict__ plans, const float2* __restrict__ twp,
+                                           int v, int role, int conjH, int src_saved) {
+    if (n != L) return false;
+    zconv_tile<T, TX, L, Rs...>(lds, s_tw, J, local, plans, twp, v, role, conjH, src_saved);
+    return true;
+  }
+};
+
+template <bool INV, int T, int LMAX, class... Ps>
+__global__ void __launch_bounds__(T)
+    k_ypass_class(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+                  const float2* __restrict__ twp, int v) {
+  constexpr int TX = 16;
+  __shared__ float2 lds[LMAX * TX];
+  __shared__ float2 s_tw[LMAX];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Y, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  (void)(ColRun<Ps>::template y<INV, T, TX>(J.ny, lds, s_tw, J, local, plans, twp) || ...);
+}
+
+template <int T, int LMAX, class... Ps>
+__global__ void __launch_bounds__(T)
+    k_zconv_class(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
+                  const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
+  constexpr int TX = 16;
+  __shared__ float2 lds[LMAX * TX];
+  __shared__ float2 s_tw[LMAX];
+  int local;
+  const int jid = find_job(jobs, njobs, PASS_Z, TX, local);
+  if (jid < 0) return;
+  const JobDesc& J = jobs[jid];
+  if (v >= J.nviews) return;
+  (void)(ColRun<Ps>::template z<T, TX>(J.nz, lds, s_tw, J, local, plans, twp, v, role, conjH, src_saved) || ...);
 }
 
 // ---------------------------------------------------------------------------

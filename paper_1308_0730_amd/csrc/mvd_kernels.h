@@ -73,6 +73,11 @@ int mvd_exact_col_shape(int L, int* threads, int* lines);
 int mvd_exact_row_shape(int M, int* waves, int* rows);
 hipError_t mvd_launch_y_exact(const LaunchArgs& a, int L, int inv, int v);
 hipError_t mvd_launch_z_exact(const LaunchArgs& a, int L, int v, int role, int conjH, int src_saved);
+// Length classes of the column plans (0..4; -1 if L has no plan) and the
+// launches over blocks of several lengths of one class.
+int mvd_col_class(int L);
+hipError_t mvd_launch_y_class(const LaunchArgs& a, int cls, int inv, int v);
+hipError_t mvd_launch_z_class(const LaunchArgs& a, int cls, int v, int role, int conjH, int src_saved);
 hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt);
 hipError_t mvd_launch_x_exact_comb(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
                                    int opt);

@@ -89,7 +89,8 @@ struct mvd_handle {
   // per-length compile-time plans
   struct Group {
     int len, first, njobs, grid, part_off;
-    int lane;  // 0: the pass's stream, 1..kSide: side stream lane - 1
+    int lane;      // 0: the pass's stream, 1..kSide: side stream lane - 1
+    int cls = -1;  // column passes over several lengths: the length class of one launch
   };
   // side streams (default priority).  Every block has a lane (longest
   // processing time first over the blocks' voxel counts), so all groups of a
@@ -472,15 +473,23 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
       continue;
     }
     // groups of equal lane and length in the sorted job order
+    // column passes of blocks of several lengths: groups of one length
+    // class (one launch serves every length of the class)
     int64_t tiles = 0;
     const auto& ord = h->order[k];
+    bool several = false;
+    for (size_t i = 1; i < ord.size(); ++i)
+      several |= job_len(h->blocks[ord[i]], k) != job_len(h->blocks[ord[0]], k);
+    const bool by_class = k != PASS_X && several;
+    auto key = [&](int b) { return by_class ? mvd_col_class(job_len(h->blocks[b], k)) : job_len(h->blocks[b], k); };
     for (size_t i = 0; i < ord.size();) {
       const int len = job_len(h->blocks[ord[i]], k);
+      const int kv = key(ord[i]);
       const int lane = h->block_lane[ord[i]];
       const int param = mvd_exact_param(k, len);
-      mvd_handle::Group gr{len, (int)i, 0, 0, (int)tiles, lane};
+      mvd_handle::Group gr{len, (int)i, 0, 0, (int)tiles, lane, by_class ? kv : -1};
       int64_t gt = 0;
-      for (; i < ord.size() && job_len(h->blocks[ord[i]], k) == len && h->block_lane[ord[i]] == lane; ++i) {
+      for (; i < ord.size() && key(ord[i]) == kv && h->block_lane[ord[i]] == lane; ++i) {
         gt += mvd_tiles(h->jobs[ord[i]], k, param);
         ++gr.njobs;
       }
@@ -833,7 +842,8 @@ void run_y(mvd_handle* h, hipStream_t s, int inv, int v) {
     return;
   }
   run_groups(h, s, PASS_Y, [&](const mvd_handle::Group& g, hipStream_t st) {
-    return mvd_launch_y_exact(group_args(h, st, PASS_Y, g), g.len, inv, v);
+    return g.cls >= 0 ? mvd_launch_y_class(group_args(h, st, PASS_Y, g), g.cls, inv, v)
+                      : mvd_launch_y_exact(group_args(h, st, PASS_Y, g), g.len, inv, v);
   });
 }
 
@@ -843,7 +853,8 @@ void run_z(mvd_handle* h, hipStream_t s, int v, int role, int conjH, int src_sav
     return;
   }
   run_groups(h, s, PASS_Z, [&](const mvd_handle::Group& g, hipStream_t st) {
-    return mvd_launch_z_exact(group_args(h, st, PASS_Z, g), g.len, v, role, conjH, src_saved);
+    return g.cls >= 0 ? mvd_launch_z_class(group_args(h, st, PASS_Z, g), g.cls, v, role, conjH, src_saved)
+                      : mvd_launch_z_exact(group_args(h, st, PASS_Z, g), g.len, v, role, conjH, src_saved);
   });
 }
 

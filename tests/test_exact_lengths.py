@@ -94,3 +94,29 @@ def test_composite_decomposition_algebra():
                 X[k1 + R1 * np.arange(R2)] = np.fft.fft(a[:, k1])
             assert np.allclose(X, np.fft.fft(x), atol=1e-12)
 
+
+
+def test_column_length_classes():
+    """Every column length belongs to exactly one class; a class has one
+    thread count (that of each member's own plan) and the longest member as
+    its LDS size; the class lists carry each length's own radices."""
+    g = _gen()
+    txt = open(os.path.join(CSRC, "mvd_exact_lengths.h")).read()
+    of = dict(_entries("MVD_COL_CLASS_OF"))
+    assert sorted(of) == g.smooth5(8, 512)
+    body = txt.split("#define MVD_COL_CLASSES(X)")[1].split("\n\n")[0]
+    seen = []
+    for line in body.splitlines()[1:]:
+        m = re.match(r"\s*X\((\d+), (\d+), (\d+), (.*)\)( \\)?$", line)
+        assert m, line
+        c, t, lmax = int(m.group(1)), int(m.group(2)), int(m.group(3))
+        plans = [list(map(int, p.split(","))) for p in re.findall(r"ColPlan<([0-9, ]+)>", m.group(4))]
+        lens = [p[0] for p in plans]
+        assert lmax == max(lens)
+        for p in plans:
+            L = p[0]
+            assert of[L] == c == g.col_class(L)
+            assert t == g.col_threads(L)
+            assert p[1:] == g.radices(L)
+        seen += lens
+    assert sorted(seen) == g.smooth5(8, 512)
