@@ -113,3 +113,21 @@ def test_autotune_restores_estimates(mvd):
         assert tuple(b.tiles()) == tuple(tiles)
         for i in range(4):
             np.testing.assert_array_equal(b.estimate(i).cpu().numpy(), before[i])
+
+
+def test_batched_repeated_sizes_over_lanes(mvd):
+    """Blocks of repeated and different sizes (equal lengths on several
+    stream lanes, several lengths in one length class, and the column
+    passes' class launches beside per-length row launches) give every
+    block's plain result bitwise."""
+    dims = [(40, 36, 30), (40, 36, 30), (64, 64, 48), (40, 36, 30), (48, 40, 36), (64, 64, 48), (20, 18, 16)]
+    blocks = [block(d, 500 + i) for i, d in enumerate(dims)]
+    with mvd.Deconvolver.batch(blocks, lam=0.01) as b:
+        b.set_tiles(*tiles_of(mvd, b.max_lengths(), -1))
+        b.iterate(2, O.OPT1)
+        got = [b.estimate(i).cpu().numpy() for i in range(len(dims))]
+    for i, (v, p, w) in enumerate(blocks):
+        with mvd.Deconvolver(v, p, w, lam=0.01) as d:
+            d.set_tiles(*tiles_of(mvd, d.max_lengths(), -1))
+            d.iterate(2, O.OPT1)
+            np.testing.assert_array_equal(got[i], d.estimate().cpu().numpy())
