@@ -1,6 +1,7 @@
 // Passes of the differentiated form: the forward with the intermediates
 // stored, the loss, and the adjoint of every step of a view-update, in
-// reverse (runtime-plan transforms; any 5-smooth size).
+// reverse (runtime-plan transforms for any 5-smooth size; compile-time plans
+// for the x passes of power-of-two half-rows).
 //
 // Adjoint of one RL view-update (K_v = P_v*), given g = dL/dpsi':
 //   tbar = w g;  ubar = tbar / sqrt(1 + 4 lambda' u);  cbar = ubar psi [c > 0]
@@ -13,8 +14,10 @@
 // end gives dL/dP_v on its window.
 #include <hip/hip_runtime.h>
 
+#include "fft_ct.h"
 #include "fft_engine.h"
 #include "mvd_device.h"
+#include "mvd_exact_lengths.h"
 #include "mvd_kernels.h"
 
 using namespace mvdk;
@@ -25,7 +28,19 @@ using namespace mvdk;
 // transform of cbar); 6 adjoint of the ratio (inverse -> qbar, forward of
 // bbar); 7 finish (inverse -> s, out = part + s, no forward transform);
 // 8 loss residual (inverse -> b, r = b - phi, FP64 sum of r^2, forward of 2r).
-template <int MODE, int WPB, int RPW, int MAXM>
+// Row transforms of the adjoint x passes: the runtime plan, or with radices
+// Rs the compile-time plan of length MAXM (the block's M).
+template <bool INV, int MAXM, int RPW, int... Rs>
+__device__ __forceinline__ void xadj_lines(const FftPlan* pl, const float2* s_tw, int lane, const LdsRow<MAXM>& L) {
+  if constexpr (sizeof...(Rs) == 0) {
+    fft_lines<INV, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
+  } else {
+    Plain<LdsRow<MAXM>> out{L};
+    CtRun<INV, MAXM, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, out);
+  }
+}
+
+template <int MODE, int WPB, int RPW, int MAXM, int... Rs>
 __global__ void __launch_bounds__(64 * WPB)
     k_xadj(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
            const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
@@ -128,7 +143,7 @@ __global__ void __launch_bounds__(64 * WPB)
       }
     }
     gsync<SYNC_WAVE>();
-    fft_lines<true, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
+    xadj_lines<true, MAXM, RPW, Rs...>(pl, s_tw, lane, L);
   } else {
     __syncthreads();  // twiddle tables
   }
@@ -191,7 +206,7 @@ __global__ void __launch_bounds__(64 * WPB)
   gsync<SYNC_WAVE>();
 
   if (R2C) {
-    fft_lines<false, MAXM, 64, RPW, false, SYNC_WAVE>(pl, s_tw, lane, L, L, L);
+    xadj_lines<false, MAXM, RPW, Rs...>(pl, s_tw, lane, L);
 #pragma unroll
     for (int i = 0; i < NPIT; ++i) {
       const int it = lane + i * 64;
@@ -446,6 +461,53 @@ hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partia
   }
 #undef MODES
   return hipGetLastError();
+}
+
+// The adjoint x passes with the compile-time row plan of a power-of-two
+// half-row length (the shape of the per-length row table).
+template <int M, int WPB, int RPW, int... Rs>
+static hipError_t xadj_ct(const LaunchArgs& a, int mode, int v, Partial* parts, int* flags, const AdjPtrs& ap) {
+  if constexpr ((M & (M - 1)) == 0 && M >= 16) {
+    switch (mode) {
+#define XM(md)                                                                                           \
+  case md:                                                                                               \
+    k_xadj<md, WPB, RPW, M, Rs...><<<a.grid, 64 * WPB, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, \
+                                                                      parts, flags, ap);                 \
+    break;
+      XM(3) XM(4) XM(5) XM(6) XM(7) XM(8)
+#undef XM
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+int mvd_xadj_rows(int M) {
+  switch (M) {
+#define X(m, wpb, rpw, ...) \
+  case m:                   \
+    return ((m & (m - 1)) == 0 && m >= 16) ? wpb * rpw : 0;
+    MVD_EXACT_ROW(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
+hipError_t mvd_launch_xadj_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
+                                 const AdjPtrs& ap) {
+  switch (M) {
+#define X(m, wpb, rpw, ...) \
+  case m:                   \
+    return xadj_ct<m, wpb, rpw, __VA_ARGS__>(a, mode, v, parts, flags, ap);
+    MVD_EXACT_ROW(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int conjH, float2* s_out,

@@ -58,6 +58,11 @@ hipError_t mvd_launch_set_int(int* p, int val, hipStream_t s);
 // differentiated form (mvd_adjoint.hip); cfg indexes the runtime-plan shapes
 hipError_t mvd_launch_xadj(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags,
                            const AdjPtrs& ap);
+// The same with the compile-time row plan of a power-of-two half-row length M
+// (16 to 256); mvd_xadj_rows gives its rows per tile, 0 if M has none.
+int mvd_xadj_rows(int M);
+hipError_t mvd_launch_xadj_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
+                                 const AdjPtrs& ap);
 hipError_t mvd_launch_zext(const LaunchArgs& a, int cfg, int v, int role, int conjH, float2* s_out,
                            const float2* s_in, double2* acc, int acc_mode);
 hipError_t mvd_launch_idft_z(const double2* A, int M, int Mp, int ny, int nz, int wz, const double2* twz,

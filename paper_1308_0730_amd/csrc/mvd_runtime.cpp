@@ -134,6 +134,9 @@ struct mvd_handle {
   // differentiated form: runtime-plan shapes, grids and buffers (block 0)
   int rt_cfg[3] = {-1, -1, -1};
   int rt_grid[3] = {0, 0, 0};
+  // the differentiated form's x passes: rows per tile of the compile-time
+  // row plan (0: runtime plans) and their grid
+  int gx_rows = 0, gx_grid = 0;
   int grad_ckpt_cap = 0;
   float* g_ckpt = nullptr;                 // checkpoints, one volume per iteration
   float *g_b = nullptr, *g_q = nullptr, *g_c = nullptr, *g_psi = nullptr;  // [view][V]
@@ -1122,7 +1125,10 @@ void grad_setup(mvd_handle* h, int n) {
     h->g_gbar = (float*)h->dalloc(V * sizeof(float));
     h->g_part = (float*)h->dalloc(V * sizeof(float));
     h->g_psiT = (float*)h->dalloc(V * sizeof(float));
-    h->g_parts = (Partial*)h->dalloc(N * h->rt_grid[0] * sizeof(Partial));
+    // the x passes: the compile-time row plan for power-of-two half-rows
+    h->gx_rows = mvd_xadj_rows(B.M);
+    h->gx_grid = h->gx_rows > 0 ? mvd_tiles(h->jobs[0], PASS_X, h->gx_rows) : h->rt_grid[0];
+    h->g_parts = (Partial*)h->dalloc(N * h->gx_grid * sizeof(Partial));
     h->g_loss = (double*)h->dalloc(N * sizeof(double));
     h->g_lr = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
     h->g_ln = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
@@ -1144,6 +1150,15 @@ AdjPtrs adj_ptrs(mvd_handle* h, int v) {
   a.part = h->g_part;
   a.out = h->g_gbar;
   return a;
+}
+
+// An x pass of the differentiated form (mode 3..8 of the adjoint x kernels).
+void grad_x(mvd_handle* h, int mode, int v, Partial* parts, const AdjPtrs& ap) {
+  const LaunchArgs ax = args(h, h->stream, h->gx_grid);
+  if (h->gx_rows > 0)
+    HIPCHECK(mvd_launch_xadj_exact(ax, h->blocks[0].M, mode, v, parts, h->d_flags, ap));
+  else
+    HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], mode, v, parts, h->d_flags, ap));
 }
 
 // Forward view-update v with its intermediates stored (b, q, c, the input
@@ -1171,39 +1186,37 @@ void grad_zext(mvd_handle* h, int v, int conjH, float2* s_out, const float2* s_i
 void grad_forward_view(mvd_handle* h, int v) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
-  const LaunchArgs ax = args(h, s, h->rt_grid[0]);
   const AdjPtrs ap = adj_ptrs(h, v);
-  Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
+  Partial* parts = h->g_parts + (size_t)v * h->gx_grid;
   grad_y(h, 0, v);
   grad_zext(h, v, 0, h->g_spsi + (size_t)v * B.spec_elems, nullptr, nullptr, 0);
   grad_y(h, 1, v);
-  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 3, v, parts, h->d_flags, ap));
+  grad_x(h, 3, v, parts, ap);
   grad_y(h, 0, v);
   grad_zext(h, v, 1, h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0);
   grad_y(h, 1, v);
-  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 4, v, parts, h->d_flags, ap));
+  grad_x(h, 4, v, parts, ap);
 }
 
 // Adjoint of view-update v: g_gbar holds dL/dpsi' on entry and dL/dpsi on exit.
 void grad_adjoint_view(mvd_handle* h, int v) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
-  const LaunchArgs ax = args(h, s, h->rt_grid[0]);
   const AdjPtrs ap = adj_ptrs(h, v);
   double2* acc = h->g_acc + (size_t)v * B.spec_elems;
   // cbar and the direct part of psibar
-  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 5, v, nullptr, h->d_flags, ap));
+  grad_x(h, 5, v, nullptr, ap);
   // qbar = cbar (x) P_v, with A_v += conj(Cbar) Q
   grad_y(h, 0, v);
   grad_zext(h, v, 0, nullptr, h->g_sq + (size_t)v * B.spec_elems, acc, 1);
   grad_y(h, 1, v);
   // bbar
-  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 6, v, nullptr, h->d_flags, ap));
+  grad_x(h, 6, v, nullptr, ap);
   // bbar (x) P_v*, with A_v += Bbar conj(Psi)
   grad_y(h, 0, v);
   grad_zext(h, v, 1, nullptr, h->g_spsi + (size_t)v * B.spec_elems, acc, 0);
   grad_y(h, 1, v);
-  HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
+  grad_x(h, 7, v, nullptr, ap);
 }
 
 void x_init_rt(mvd_handle* h) {
@@ -1252,26 +1265,25 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
                             seed_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
   else
     HIPCHECK(hipMemsetAsync(h->g_gbar, 0, V * sizeof(float), st));
-  const LaunchArgs ax = args(h, st, h->rt_grid[0]);
   for (int v = 0; v < N && !seed; ++v) {
-    Partial* parts = h->g_parts + (size_t)v * h->rt_grid[0];
+    Partial* parts = h->g_parts + (size_t)v * h->gx_grid;
     AdjPtrs ap = adj_ptrs(h, v);
     ap.part = h->g_gbar;
     x_init_rt(h);
     grad_y(h, 0, v);
     grad_zext(h, v, 0, h->g_sT, nullptr, nullptr, 0);
     grad_y(h, 1, v);
-    HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 8, v, parts, h->d_flags, ap));
+    grad_x(h, 8, v, parts, ap);
     if (want_grad) {
       grad_y(h, 0, v);
       grad_zext(h, v, 1, nullptr, h->g_sT, h->g_acc + (size_t)v * S, 0);
       grad_y(h, 1, v);
-      HIPCHECK(mvd_launch_xadj(ax, h->rt_cfg[0], 7, v, nullptr, h->d_flags, ap));
+      grad_x(h, 7, v, nullptr, ap);
     }
   }
   std::vector<double> lv(N, 0.0);
   if (!seed) {
-    HIPCHECK(mvd_launch_reduce(h->g_parts, h->rt_grid[0], N, h->g_loss, h->g_lr, h->g_ln, st));
+    HIPCHECK(mvd_launch_reduce(h->g_parts, h->gx_grid, N, h->g_loss, h->g_lr, h->g_ln, st));
     HIPCHECK(hipMemcpyAsync(lv.data(), h->g_loss, N * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   if (want_grad) {

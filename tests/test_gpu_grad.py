@@ -32,9 +32,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("weighted,lam", [(False, 0.0), (True, 0.02)])
-def test_gradient_matches_oracle(mvd, weighted, lam):
-    dims = (40, 36, 30)
+@pytest.mark.parametrize("weighted,lam,dims", [(False, 0.0, (40, 36, 30)), (True, 0.02, (40, 36, 30)),
+                                               (True, 0.02, (64, 20, 24))])
+def test_gradient_matches_oracle(mvd, weighted, lam, dims):
     s = synth.make_problem(dims, 8, [0.0, 70.0, 130.0], (5, 5, 7), 1.0, 2.0, 31)
     rng = np.random.default_rng(5)
     psfs = [asym_psf(rng, (9, 7, 7), off) for off in ((0.6, -0.4, 0.3), (-0.5, 0.5, 0.7), (0.3, 0.2, -0.6))]
@@ -54,8 +54,7 @@ def test_gradient_matches_oracle(mvd, weighted, lam):
         assert rel(a, b) <= 2e-4
 
 
-def grad_case(weighted, seed=5):
-    dims = (40, 36, 30)
+def grad_case(weighted, seed=5, dims=(40, 36, 30)):
     s = synth.make_problem(dims, 8, [0.0, 70.0, 130.0], (5, 5, 7), 1.0, 2.0, 31)
     rng = np.random.default_rng(seed)
     psfs = [asym_psf(rng, (9, 7, 7), off) for off in ((0.6, -0.4, 0.3), (-0.5, 0.5, 0.7), (0.3, 0.2, -0.6))]
@@ -65,11 +64,13 @@ def grad_case(weighted, seed=5):
     return s, psfs, w, psi0, rng
 
 
-@pytest.mark.parametrize("weighted,lam", [(False, 0.0), (True, 0.02)])
-def test_backward_matches_oracle_vjp(mvd, weighted, lam):
+@pytest.mark.parametrize("weighted,lam,dims", [(False, 0.0, (40, 36, 30)), (True, 0.02, (40, 36, 30)),
+                                               (True, 0.02, (32, 36, 30)), (False, 0.0, (64, 20, 24))])
+def test_backward_matches_oracle_vjp(mvd, weighted, lam, dims):
     """mvd_backward with a random upstream gradient against the oracle's
-    vector-Jacobian product; the handle is left at psi_n."""
-    s, psfs, w, psi0, rng = grad_case(weighted)
+    vector-Jacobian product; the handle is left at psi_n.  Half-rows of 20
+    use the runtime-plan adjoint x passes, 16 and 32 the compile-time ones."""
+    s, psfs, w, psi0, rng = grad_case(weighted, dims=dims)
     gbar = rng.normal(size=psi0.shape).astype(np.float32)
     n = 3
     psi_n, gpsi, gP = O.vjp(s.views, psfs, n, psi0.astype(np.float64), gbar.astype(np.float64), w, lam)
