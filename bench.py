@@ -247,6 +247,40 @@ def convergence_form():
     return r
 
 
+def linear_form(steps, warmup):
+    """The linear (padded) boundary at embryo scale: a 480x480x216 volume,
+    six views, 31x31x41 PSFs, overlap weights, lambda 0.0006, OPT1, 10
+    iterations, deconvolved on the volume plus the PSF radius on every side
+    (a 512x512x256 grid, the plain workload's); value counts the volume's
+    voxels, grid_value the grid's."""
+    import torch
+    from paper_1308_0730_amd import mvd, synth, tune
+    t0 = time.time()
+    s = synth.config3(dims=(480, 480, 216))
+    print(f"[bench] linear workload generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    its, var, n = 10, "opt1", len(s.views)
+    with mvd.Deconvolver(s.views, s.psfs, s.weights, lam=0.0006, boundary="linear") as d:
+        d.iterate(1, var)  # sensitivities, compound kernels, graph
+        tune.autotune(d, var, iters=1, cache_path=None)
+        for _ in range(warmup):
+            d.iterate(its, var)
+        st = d.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            d.iterate(its, var)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        grid = d.grid_dims()
+    vox = int(np.prod(s.dims)) * n * its
+    gvox = int(np.prod(grid)) * n * its
+    return {"workload": "linear boundary: 480x480x216, 6 views at 60 deg, 31x31x41 PSFs, overlap weights, "
+                        "lambda 0.0006, Optimization I, 10 iterations",
+            "grid": list(grid), "ms_per_step": round(ms, 3), "value": round(vox / (ms / 1e3) / 1e9, 3),
+            "unit": "Gvox/s", "grid_value": round(gvox / (ms / 1e3) / 1e9, 3)}
+
+
 def synth_config5():
     from paper_1308_0730_amd import synth
     return synth.config5()
@@ -265,8 +299,9 @@ def main():
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (48 blocks, against the plain form looped over them), the "
-                         "differentiated (forward against forward + backward) and the convergence "
-                         "(every scheme x variant to one distance from the ground truth) measurements")
+                         "differentiated (forward against forward + backward), the convergence "
+                         "(every scheme x variant to one distance from the ground truth) and the "
+                         "linear-boundary measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -360,8 +395,16 @@ def main():
 
     forms = None
     if not args.no_forms:
-        forms = {"batched": batched_form(max(1, args.steps // 2), 1), "grad": grad_form(3, 1),
-                 "convergence": convergence_form()}
+        forms = {}
+        for name, fn in (("batched", lambda: batched_form(max(1, args.steps // 2), 1)),
+                         ("grad", lambda: grad_form(3, 1)), ("convergence", convergence_form),
+                         ("linear", lambda: linear_form(max(1, args.steps // 2), 1))):
+            try:
+                forms[name] = fn()
+            except Exception as e:  # a failing side measurement must not cost the main line
+                print(f"[bench] form {name} failed: {e!r}", file=sys.stderr, flush=True)
+                forms[name] = {"error": repr(e)}
+            torch.cuda.empty_cache()
 
     dims = [list(b.dims) for b in blocks]
     out = {
