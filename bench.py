@@ -281,6 +281,43 @@ def linear_form(steps, warmup):
             "unit": "Gvox/s", "grid_value": round(gvox / (ms / 1e3) / 1e9, 3)}
 
 
+def spim_form():
+    """The simulated SPIM acquisition (sphere object, 15-degree offset,
+    light-sheet attenuation, axial x3 sampling, Poisson counts,
+    re-registration) of a 96^3 volume with four views, deconvolved with
+    Optimization I (20 sequential iterations) using PSFs rotated 0, 10 and 20
+    degrees off: the best correlation to the ground truth and where it is
+    reached, next to the views' own correlation."""
+    from paper_1308_0730_amd import spim_sim
+    t0 = time.time()
+    acq = spim_sim.simulate()
+    t_sim = time.time() - t0
+    t0 = time.time()
+    r = spim_sim.psf_robustness(acq, errors=(0.0, 10.0, 20.0), variant="opt1", n_iter=20)
+    r.update({"workload": "SPIM simulation 96^3, 4 views at 90 deg, 13x13x25 PSFs (1.0, 3.0), OPT1, 20 iterations",
+              "simulate_s": round(t_sim, 2), "deconvolve_s": round(time.time() - t0, 2)})
+    return r
+
+
+def psf_refine_form():
+    """PSF refinement through the differentiated form: the per-view Gaussian
+    widths of a 64^3 four-view problem (17^3 PSFs, true widths (1.2, 4.0))
+    fitted from a start perturbed by U[0.75, 1.25], 4 RL iterations per loss,
+    up to 25 descent steps."""
+    from paper_1308_0730_amd import psf_refine, synth
+    angles = [0.0, 45.0, 90.0, 135.0]
+    s = synth.make_problem((64, 64, 64), 40, angles, (17, 17, 17), 1.2, 4.0, 77, noise="none")
+    true = np.array([[1.2, 4.0]] * 4)
+    th0 = true * np.random.default_rng(5).uniform(0.75, 1.25, size=true.shape)
+    t0 = time.time()
+    th, hist = psf_refine.refine(s.views, angles, (17, 17, 17), th0, n_iter=4, steps=25)
+    return {"workload": "64^3, 4 views, 17^3 PSFs, widths (1.2, 4.0) per view from a start x U[0.75, 1.25]",
+            "steps": len(hist) - 1, "loss_start": hist[0][0], "loss_end": hist[-1][0],
+            "max_rel_width_error_start": round(float(np.abs(th0 / true - 1).max()), 4),
+            "max_rel_width_error_end": round(float(np.abs(th / true - 1).max()), 4),
+            "wall_s": round(time.time() - t0, 2)}
+
+
 def synth_config5():
     from paper_1308_0730_amd import synth
     return synth.config5()
@@ -300,8 +337,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (48 blocks, against the plain form looped over them), the "
                          "differentiated (forward against forward + backward), the convergence "
-                         "(every scheme x variant to one distance from the ground truth) and the "
-                         "linear-boundary measurements")
+                         "(every scheme x variant to one distance from the ground truth), the "
+                         "linear-boundary, the simulated-SPIM and the PSF-refinement measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -398,7 +435,8 @@ def main():
         forms = {}
         for name, fn in (("batched", lambda: batched_form(max(1, args.steps // 2), 1)),
                          ("grad", lambda: grad_form(3, 1)), ("convergence", convergence_form),
-                         ("linear", lambda: linear_form(max(1, args.steps // 2), 1))):
+                         ("linear", lambda: linear_form(max(1, args.steps // 2), 1)),
+                         ("spim", spim_form), ("psf_refine", psf_refine_form)):
             try:
                 forms[name] = fn()
             except Exception as e:  # a failing side measurement must not cost the main line
