@@ -72,10 +72,11 @@ def test_one_iteration_from_oracle_estimate(mvd, variant, weighted, lam):
     assert rel(got, ref) <= ONE_STEP, rel(got, ref)
 
 
-@pytest.mark.parametrize("dims", [(150, 54, 50), (64, 100, 48), (4, 2, 2), (250, 24, 18)])
+@pytest.mark.parametrize("dims", [(150, 54, 50), (64, 100, 48), (4, 2, 2), (250, 24, 18), (1024, 6, 4)])
 def test_one_iteration_odd_and_mixed_radix_sizes(mvd, dims):
-    """Odd half-row length (nx/2 = 75 = 3*5*5), radix-5 lengths and the
-    smallest valid volume."""
+    """Odd half-row length (nx/2 = 75 = 3*5*5), radix-5 lengths, the
+    smallest valid volume and the largest x extent (nx = 1024: 512-point
+    rows, runtime plans only)."""
     k = tuple(min(5, n if n % 2 else n - 1) for n in (dims[2], dims[1], dims[0]))
     views, psfs, _ = problem(dims, 2, 12, psf_shape=k)
     pb = O.Problem(views, psfs)
@@ -219,3 +220,28 @@ def test_every_launch_shape(mvd, dims):
                 assert e <= ONE_STEP, (kind, c, e)
                 tried += 1
     assert tried >= 3
+
+
+def test_zero_iterations_change_nothing(mvd):
+    """mvd_iterate with n = 0 is a no-op: the estimate and the statistics
+    stay as they were."""
+    views, psfs, w = problem((40, 36, 30), 3, 41, weights=True)
+    with mvd.Deconvolver(views, psfs, w) as d:
+        d.iterate(2, O.OPT1)
+        before = d.estimate().cpu().numpy()
+        st = d.stats()
+        d.iterate(0, O.OPT1)
+        np.testing.assert_array_equal(d.estimate().cpu().numpy(), before)
+        assert d.stats()["iterations"] == st["iterations"]
+
+
+def test_all_zero_views_are_rejected(mvd):
+    """Views without any signal have no mean intensity to start from (the
+    flat start and the ratio guard are both scaled by it): create fails
+    with MVD_EINVAL and names the block."""
+    views, psfs, _ = problem((16, 12, 10), 2, 43)
+    zero = [np.zeros_like(v) for v in views]
+    with pytest.raises(mvd.MVDError) as e:
+        mvd.Deconvolver(zero, psfs)
+    assert e.value.code == mvd.MVD_EINVAL and "all zero" in str(e.value)
+
