@@ -81,8 +81,9 @@ typedef struct mvd_handle mvd_handle;
  *   n_views   1..MVD_MAX_VIEWS
  *   dims      {nx, ny, nz}: nx even, every extent 5-smooth (2^a 3^b 5^c),
  *             4 <= nx <= 2*MVD_MAX_LEN, 2 <= ny, nz <= MVD_MAX_LEN
- *   views     n_views pointers to nx*ny*nz floats, finite and >= 0, registered
- *             onto the common grid (section 6: identity transformation)
+ *   views     n_views pointers to nx*ny*nz floats, finite and >= 0, not all
+ *             zero (s scales the start and the ratio guard), registered onto
+ *             the common grid (section 6: identity transformation)
  *   psfs      n_views pointers; psf_dims[3*v + {0,1,2}] = {kx, ky, kz};
  *             finite, >= 0, positive sum, each extent (after odd padding)
  *             no larger than the volume's
@@ -116,7 +117,8 @@ typedef void (*mvd_free_fn)(void* ptr, void* ctx);
  *              MVD_BOUNDARY_LINEAR (1): the views are known on the volume only
  *              and psi also lives on a margin of one PSF radius around it.
  *              The handle computes on the volume extended by the largest
- *              PSF radius per axis, rounded up to transform lengths; each
+ *              PSF radius per axis, rounded up to transform lengths (that
+ *              grid must stay within the limits above: MVD_EINVAL); each
  *              view's blur is evaluated on the volume and the
  *              back-projection is divided by the view's sensitivity
  *              1_volume (x) K_v (EM with the restricted system matrix;
@@ -160,8 +162,11 @@ typedef struct mvd_stats_t {
 int mvd_create(mvd_handle** out, const mvd_problem* p, const mvd_options* o);
 
 /* Batched form: n_blocks independent volumes of any valid dims with the same
- * n_views, deconvolved together; every pass of an iteration is one launch
- * that covers all blocks. */
+ * n_views, deconvolved together; every pass of an iteration covers all
+ * blocks, in one launch (runtime or single-length plans) or, with the
+ * per-length plans, one launch per stream lane and length (length class for
+ * the column passes of blocks of several lengths); an iteration is replayed
+ * from one HIP graph. */
 int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
                      const mvd_options* o);
 
@@ -234,8 +239,9 @@ int mvd_set_psfs(mvd_handle* h, const float* const* psfs, const int* psf_dims, i
  * usable only when every block has that length; 0 = runtime plan, any
  * 5-smooth length up to max_len; -1 = the per-length compile-time plans,
  * one shape for each 5-smooth length up to max_len, launched per group of
- * blocks of equal length: threads and per_tile are reported as 0 since they
- * depend on the length).  mvd_tile_candidates lists, into
+ * blocks of equal length, or of one length class for the column passes of
+ * blocks of several lengths: threads and per_tile are reported as 0 since
+ * they depend on the length).  mvd_tile_candidates lists, into
  * out[0..cap), the candidates for transforms of length max_len and returns
  * how many exist.  mvd_set_tiles selects one candidate per kind for a handle
  * (MVD_EINVAL if one does not fit its volumes); later iterations use them.
