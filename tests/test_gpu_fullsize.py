@@ -83,3 +83,31 @@ def test_embryo_flux_identity(mvd, embryo):
         tot = float(np.sum(s.views[v], dtype=np.float64))
         assert abs(st["flux"][v] - tot) <= 2e-6 * tot, (v, st["flux"][v], tot)
     assert st["ratio_clamps"] == 0 and not st["nonfinite"]
+
+
+def test_batched_blocks_view_update_sampled(mvd):
+    """Six blocks of the batched workload at their full, uneven sizes in the
+    launch shapes the benchmark times (autotuned: per-length plans, length
+    classes, stream lanes): one view-update of every block checked at
+    sampled voxels against the oracle's windowed evaluation."""
+    blocks = synth.config4(n_blocks=6)
+    v = 2
+    with mvd.Deconvolver.batch([(b.views, b.psfs, b.weights) for b in blocks]) as d:
+        print("launch shapes", tuned(d, O.EFF))
+        d.iterate(1, O.EFF)
+        psi = [d.estimate(i).cpu().numpy().astype(np.float64) for i in range(len(blocks))]
+        d.view_update(v, O.EFF)
+        out = [d.estimate(i).cpu().numpy() for i in range(len(blocks))]
+    rng = np.random.default_rng(11)
+    for i, b in enumerate(blocks):
+        scale = float(np.mean([np.mean(x, dtype=np.float64) for x in b.views]))
+        P = O.prepare_psf(b.psfs[v])
+        K = O.compound_kernel(b.psfs, v, O.EFF)
+        nz, ny, nx = psi[i].shape
+        pts = [tuple(int(a) for a in p) for p in rng.integers(0, [nz, ny, nx], size=(24, 3))]
+        pts += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz // 2, ny // 2, nx // 2)]
+        ref = O.view_update_at(psi[i], b.views[v], P, K, pts, None, 0.0, O.EPS_SCALE * scale)
+        got = np.array([out[i][p] for p in pts], np.float64)
+        e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"block {i} {b.dims}: sampled view-update rel_l2={e:.3e}")
+        assert e <= 1e-5
