@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(T)
 // per-length plans ColPlan<L, radices...> sharing one thread count; every
 // workgroup runs the plan of its job's length (jobs sorted by length, so
 // the workgroups in flight mostly share one plan's code), in LDS sized for
-// the class's longest length.
+// the class's longest length; TX lines per tile.
 template <int L, int... Rs>
 struct ColPlan {};
 
@@ -335,11 +335,10 @@ struct ColRun<ColPlan<L, Rs...>> {
   }
 };
 
-template <bool INV, int T, int LMAX, class... Ps>
+template <bool INV, int T, int TX, int LMAX, class... Ps>
 __global__ void __launch_bounds__(T)
     k_ypass_class(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
                   const float2* __restrict__ twp, int v) {
-  constexpr int TX = 16;
   __shared__ float2 lds[LMAX * TX];
   __shared__ float2 s_tw[LMAX];
   int local;
@@ -350,11 +349,10 @@ __global__ void __launch_bounds__(T)
   (void)(ColRun<Ps>::template y<INV, T, TX>(J.ny, lds, s_tw, J, local, plans, twp) || ...);
 }
 
-template <int T, int LMAX, class... Ps>
+template <int T, int TX, int LMAX, class... Ps>
 __global__ void __launch_bounds__(T)
     k_zconv_class(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
                   const float2* __restrict__ twp, int v, int role, int conjH, int src_saved) {
-  constexpr int TX = 16;
   __shared__ float2 lds[LMAX * TX];
   __shared__ float2 s_tw[LMAX];
   int local;

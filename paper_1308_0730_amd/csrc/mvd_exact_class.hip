@@ -20,14 +20,14 @@ int mvd_col_class(int L) {
 
 hipError_t mvd_launch_y_class(const LaunchArgs& a, int cls, int inv, int v) {
   switch (cls) {
-#define X(c, t, lmax, ...)                                                                                 \
-  case c:                                                                                                  \
-    if (inv)                                                                                               \
-      k_ypass_class<true, t, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, \
-                                                                           v);                             \
-    else                                                                                                   \
-      k_ypass_class<false, t, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans,      \
-                                                                            a.tw, v);                      \
+#define X(c, t, tx, lmax, ...)                                                                     \
+  case c:                                                                                          \
+    if (inv)                                                                                       \
+      k_ypass_class<true, t, tx, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs,    \
+                                                                               a.plans, a.tw, v);  \
+    else                                                                                           \
+      k_ypass_class<false, t, tx, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs,   \
+                                                                                a.plans, a.tw, v); \
     break;
     MVD_COL_CLASSES(X)
 #undef X
@@ -39,10 +39,11 @@ hipError_t mvd_launch_y_class(const LaunchArgs& a, int cls, int inv, int v) {
 
 hipError_t mvd_launch_z_class(const LaunchArgs& a, int cls, int v, int role, int conjH, int src_saved) {
   switch (cls) {
-#define X(c, t, lmax, ...)                                                                                  \
-  case c:                                                                                                   \
-    k_zconv_class<t, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, a.tw, v, role, \
-                                                                    conjH, src_saved);                     \
+#define X(c, t, tx, lmax, ...)                                                                  \
+  case c:                                                                                       \
+    k_zconv_class<t, tx, lmax, __VA_ARGS__><<<a.grid, t, 0, a.stream>>>(a.jobs, a.njobs, a.plans, \
+                                                                        a.tw, v, role, conjH,     \
+                                                                        src_saved);               \
     break;
     MVD_COL_CLASSES(X)
 #undef X

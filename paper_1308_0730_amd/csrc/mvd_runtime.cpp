@@ -217,7 +217,7 @@ void validate_shape(const mvd_problem* p, int idx) {
   if (p->n_views < 1 || p->n_views > MVD_MAX_VIEWS) bad(b + "n_views must be in [1, 64]");
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
   if (nx < 4 || nx % 2 || nx / 2 > MVD_MAX_LEN) bad(b + "nx must be even, >= 4 and <= 1024");
-  if (ny < 2 || ny > MVD_MAX_LEN || nz < 2 || nz > MVD_MAX_LEN) bad(b + "ny and nz must be in [2, 512]");
+  if (ny < 2 || ny > MVD_MAX_LEN_YZ || nz < 2 || nz > MVD_MAX_LEN_YZ) bad(b + "ny and nz must be in [2, 1024]");
   if (!mvdh::is_smooth5(nx / 2) || !mvdh::is_smooth5(ny) || !mvdh::is_smooth5(nz))
     bad(b + "every extent must be 5-smooth (2^a 3^b 5^c)");
   if (!p->views || !p->psfs || !p->psf_dims) bad(b + "views, psfs and psf_dims are required");
@@ -628,7 +628,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
       B.nx = next_smooth5(B.ux + 2 * r[0], true);
       B.ny = next_smooth5(B.uy + 2 * r[1], false);
       B.nz = next_smooth5(B.uz + 2 * r[2], false);
-      if (B.nx / 2 > MVD_MAX_LEN || B.ny > MVD_MAX_LEN || B.nz > MVD_MAX_LEN)
+      if (B.nx / 2 > MVD_MAX_LEN || B.ny > MVD_MAX_LEN_YZ || B.nz > MVD_MAX_LEN_YZ)
         bad("block " + std::to_string(b) + ": the volume plus its PSF margin exceeds the largest transform length");
     }
     B.M = B.nx / 2;

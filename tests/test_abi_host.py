@@ -50,6 +50,8 @@ def test_rejects_bad_shapes():
     expect_einval([(v, p, w)], "nx must be even")
     v, p, w = small_problem(rng, (14, 6, 4))
     expect_einval([(v, p, w)], "5-smooth")
+    v, p, w = small_problem(rng, (8, 1080, 4))
+    expect_einval([(v, p, w)], "ny and nz must be in [2, 1024]")
     v, p, w = small_problem(rng, (8, 6, 4))
     p = [np.ones((9, 3, 3), np.float32)] * 2
     expect_einval([(v, p, w)], "larger than the volume")

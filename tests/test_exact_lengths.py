@@ -26,11 +26,11 @@ def test_header_matches_generator(tmp_path):
     g = _gen()
     cols = _entries("MVD_EXACT_COL")
     rows = _entries("MVD_EXACT_ROW")
-    assert [e[0] for e in cols] == g.smooth5(8, 512)
+    assert [e[0] for e in cols] == g.smooth5(8, g.MAX_COL)
     assert [e[0] for e in rows] == g.smooth5(4, 256)
     for e in cols:
         L, t, tx, rad = e[0], e[1], e[2], e[3:]
-        assert rad == g.radices(L) and t == g.col_threads(L) and tx == 16
+        assert rad == g.radices(L) and t == g.col_threads(L) and tx == g.col_lines(L) == (16 if L <= 512 else 8)
     for e in rows:
         M, wpb, rpw, rad = e[0], e[1], e[2], e[3:]
         assert rad == g.row_radices(M) and wpb == 4 and rpw == g.row_rows(M)
@@ -103,20 +103,20 @@ def test_column_length_classes():
     g = _gen()
     txt = open(os.path.join(CSRC, "mvd_exact_lengths.h")).read()
     of = dict(_entries("MVD_COL_CLASS_OF"))
-    assert sorted(of) == g.smooth5(8, 512)
+    assert sorted(of) == g.smooth5(8, g.MAX_COL)
     body = txt.split("#define MVD_COL_CLASSES(X)")[1].split("\n\n")[0]
     seen = []
     for line in body.splitlines()[1:]:
-        m = re.match(r"\s*X\((\d+), (\d+), (\d+), (.*)\)( \\)?$", line)
+        m = re.match(r"\s*X\((\d+), (\d+), (\d+), (\d+), (.*)\)( \\)?$", line)
         assert m, line
-        c, t, lmax = int(m.group(1)), int(m.group(2)), int(m.group(3))
-        plans = [list(map(int, p.split(","))) for p in re.findall(r"ColPlan<([0-9, ]+)>", m.group(4))]
+        c, t, tx, lmax = int(m.group(1)), int(m.group(2)), int(m.group(3)), int(m.group(4))
+        plans = [list(map(int, p.split(","))) for p in re.findall(r"ColPlan<([0-9, ]+)>", m.group(5))]
         lens = [p[0] for p in plans]
         assert lmax == max(lens)
         for p in plans:
             L = p[0]
             assert of[L] == c == g.col_class(L)
-            assert t == g.col_threads(L)
+            assert t == g.col_threads(L) and tx == g.col_lines(L)
             assert p[1:] == g.radices(L)
         seen += lens
-    assert sorted(seen) == g.smooth5(8, 512)
+    assert sorted(seen) == g.smooth5(8, g.MAX_COL)

@@ -131,3 +131,20 @@ def test_batched_repeated_sizes_over_lanes(mvd):
             d.set_tiles(*tiles_of(mvd, d.max_lengths(), -1))
             d.iterate(2, O.OPT1)
             np.testing.assert_array_equal(got[i], d.estimate().cpu().numpy())
+
+
+def test_batched_columns_above_512(mvd):
+    """Blocks with y lengths above 512 (their own length class, 8-line
+    tiles) beside ordinary ones give every block's plain result bitwise."""
+    dims = [(16, 720, 10), (16, 1000, 12), (20, 36, 30), (16, 720, 10)]
+    blocks = [block(d, 600 + i) for i, d in enumerate(dims)]
+    with mvd.Deconvolver.batch(blocks) as b:
+        b.set_tiles(*tiles_of(mvd, b.max_lengths(), -1))
+        b.iterate(2, O.EFF)
+        got = [b.estimate(i).cpu().numpy() for i in range(len(dims))]
+    for i, (v, p, w) in enumerate(blocks):
+        with mvd.Deconvolver(v, p, w) as d:
+            d.set_tiles(*tiles_of(mvd, d.max_lengths(), -1))
+            d.iterate(2, O.EFF)
+            np.testing.assert_array_equal(got[i], d.estimate().cpu().numpy())
+
