@@ -73,7 +73,7 @@ extern "C" {
 #define MVD_MEM_DEVICE 1
 
 #define MVD_MAX_VIEWS 64
-#define MVD_MAX_LEN 512     /* largest nx/2 */
+#define MVD_MAX_LEN 1024    /* largest nx/2 */
 #define MVD_MAX_LEN_YZ 1024 /* largest ny and nz */
 
 typedef struct mvd_handle mvd_handle;
@@ -82,9 +82,9 @@ typedef struct mvd_handle mvd_handle;
  *   n_views   1..MVD_MAX_VIEWS
  *   dims      {nx, ny, nz}: nx even, every extent 5-smooth (2^a 3^b 5^c),
  *             4 <= nx <= 2*MVD_MAX_LEN, 2 <= ny, nz <= MVD_MAX_LEN_YZ (lengths
- *             above 512 along y or z have compile-time plans only: the
- *             differentiated form, which also needs runtime plans, takes up
- *             to 512)
+ *             above 512 along y or z and half-rows above 512 have
+ *             compile-time plans only: the differentiated form, which also
+ *             needs runtime plans, takes nx <= 1024 and ny, nz <= 512)
  *   views     n_views pointers to nx*ny*nz floats, finite and >= 0, not all
  *             zero (s scales the start and the ratio guard), registered onto
  *             the common grid (section 6: identity transformation)

@@ -496,7 +496,7 @@ int mvd_exact_cfg(int kind) { return rt_num(kind) + mvd_ct_num_cfgs(kind); }
 int mvd_num_cfgs(int kind) { return mvd_exact_cfg(kind) + 1; }
 static int cfg_field(int kind, int cfg, int f) {
   const int n = rt_num(kind);
-  if (cfg == mvd_exact_cfg(kind)) return f == 2 ? (kind == PASS_X ? 256 : MVD_MAX_LEN_YZ) : 0;
+  if (cfg == mvd_exact_cfg(kind)) return f == 2 ? (kind == PASS_X ? MVD_MAX_LEN : MVD_MAX_LEN_YZ) : 0;
   if (cfg >= n) return mvd_ct_cfg(kind, cfg - n, f);
   return kind == PASS_X ? kRowCfg[cfg][f] : kColCfg[cfg][f];
 }

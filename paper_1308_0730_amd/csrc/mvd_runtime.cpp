@@ -216,7 +216,7 @@ void validate_shape(const mvd_problem* p, int idx) {
   if (!p) bad(b + "problem is NULL");
   if (p->n_views < 1 || p->n_views > MVD_MAX_VIEWS) bad(b + "n_views must be in [1, 64]");
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  if (nx < 4 || nx % 2 || nx / 2 > MVD_MAX_LEN) bad(b + "nx must be even, >= 4 and <= 1024");
+  if (nx < 4 || nx % 2 || nx / 2 > MVD_MAX_LEN) bad(b + "nx must be even, >= 4 and <= 2048");
   if (ny < 2 || ny > MVD_MAX_LEN_YZ || nz < 2 || nz > MVD_MAX_LEN_YZ) bad(b + "ny and nz must be in [2, 1024]");
   if (!mvdh::is_smooth5(nx / 2) || !mvdh::is_smooth5(ny) || !mvdh::is_smooth5(nz))
     bad(b + "every extent must be 5-smooth (2^a 3^b 5^c)");

@@ -27,7 +27,7 @@ def test_header_matches_generator(tmp_path):
     cols = _entries("MVD_EXACT_COL")
     rows = _entries("MVD_EXACT_ROW")
     assert [e[0] for e in cols] == g.smooth5(8, g.MAX_COL)
-    assert [e[0] for e in rows] == g.smooth5(4, 256)
+    assert [e[0] for e in rows] == g.smooth5(4, g.MAX_ROW)
     for e in cols:
         L, t, tx, rad = e[0], e[1], e[2], e[3:]
         assert rad == g.radices(L) and t == g.col_threads(L) and tx == g.col_lines(L) == (16 if L <= 512 else 8)

@@ -73,12 +73,12 @@ def test_one_iteration_from_oracle_estimate(mvd, variant, weighted, lam):
 
 
 @pytest.mark.parametrize("dims", [(150, 54, 50), (64, 100, 48), (4, 2, 2), (250, 24, 18), (1024, 6, 4),
-                                  (16, 1024, 6), (8, 6, 1000)])
+                                  (2048, 6, 4), (1000, 6, 4), (16, 1024, 6), (8, 6, 1000)])
 def test_one_iteration_odd_and_mixed_radix_sizes(mvd, dims):
     """Odd half-row length (nx/2 = 75 = 3*5*5), radix-5 lengths, the
-    smallest valid volume, the largest x extent (nx = 1024: 512-point
-    rows, runtime plans only) and column lengths above 512 (1024 along y,
-    1000 along z: compile-time plans on 8-line tiles)."""
+    smallest valid volume, long rows (nx = 1000, 1024 and the largest,
+    2048: half-rows of 500, 512 and 1024) and column lengths above 512
+    (1024 along y, 1000 along z: compile-time plans on 8-line tiles)."""
     k = tuple(min(5, n if n % 2 else n - 1) for n in (dims[2], dims[1], dims[0]))
     views, psfs, _ = problem(dims, 2, 12, psf_shape=k)
     pb = O.Problem(views, psfs)
