@@ -81,10 +81,9 @@ typedef struct mvd_handle mvd_handle;
 /* One volume to deconvolve (a block of the batched form).
  *   n_views   1..MVD_MAX_VIEWS
  *   dims      {nx, ny, nz}: nx even, every extent 5-smooth (2^a 3^b 5^c),
- *             4 <= nx <= 2*MVD_MAX_LEN, 2 <= ny, nz <= MVD_MAX_LEN_YZ (lengths
- *             above 512 along y or z and half-rows above 512 have
- *             compile-time plans only: the differentiated form, which also
- *             needs runtime plans, takes nx <= 1024 and ny, nz <= 512)
+ *             4 <= nx <= 2*MVD_MAX_LEN, 2 <= ny, nz <= MVD_MAX_LEN_YZ (the
+ *             differentiated form takes half-rows nx/2 up to 512, or powers
+ *             of two up to 1024: its other adjoint x passes use runtime plans)
  *   views     n_views pointers to nx*ny*nz floats, finite and >= 0, not all
  *             zero (s scales the start and the ratio guard), registered onto
  *             the common grid (section 6: identity transformation)

@@ -137,6 +137,7 @@ struct mvd_handle {
   // the differentiated form's x passes: rows per tile of the compile-time
   // row plan (0: runtime plans) and their grid
   int gx_rows = 0, gx_grid = 0;
+  bool grad_ready = false;
   int grad_ckpt_cap = 0;
   float* g_ckpt = nullptr;                 // checkpoints, one volume per iteration
   float *g_b = nullptr, *g_q = nullptr, *g_c = nullptr, *g_psi = nullptr;  // [view][V]
@@ -1101,16 +1102,24 @@ void iterate_combined_impl(mvd_handle* h, int n, int variant, int mean) {
 
 void grad_setup(mvd_handle* h, int n) {
   const Block& B = h->blocks[0];
-  if (h->rt_cfg[0] < 0) {
+  if (!h->grad_ready) {
+    // runtime-plan shapes only for the passes no compile-time plan serves:
+    // the adjoint x passes of half-rows that are not a power of two in
+    // [16, 1024] (the y and z passes and the x transform of psi have
+    // per-length plans for every supported length)
     const int lens[3] = {B.M, B.ny, B.nz};
     const int nrt[3] = {5, 4, 4};
+    const bool need[3] = {mvd_xadj_rows(B.M) == 0, mvd_exact_param(PASS_Y, B.ny) <= 0,
+                          mvd_exact_param(PASS_Z, B.nz) <= 0};
     for (int k = 0; k < 3; ++k) {
+      if (!need[k]) continue;
       for (int c = 0; c < nrt[k]; ++c)
         if (mvd_cfg_maxlen(k, c) >= lens[k]) {
           h->rt_cfg[k] = c;
           break;
         }
-      if (h->rt_cfg[k] < 0) bad("no runtime launch shape for the differentiated form");
+      if (h->rt_cfg[k] < 0)
+        bad("the differentiated form takes half-rows up to 512, or power-of-two half-rows up to 1024");
       h->rt_grid[k] = total_tiles(h, k, mvd_cfg_param(k, h->rt_cfg[k]));
     }
     const size_t N = h->nviews, V = B.V, S = B.spec_elems;
@@ -1132,6 +1141,7 @@ void grad_setup(mvd_handle* h, int n) {
     h->g_loss = (double*)h->dalloc(N * sizeof(double));
     h->g_lr = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
     h->g_ln = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+    h->grad_ready = true;
   }
   if (n > h->grad_ckpt_cap) {
     h->g_ckpt = (float*)h->dalloc((size_t)n * B.V * sizeof(float));
@@ -1219,8 +1229,14 @@ void grad_adjoint_view(mvd_handle* h, int v) {
   grad_x(h, 7, v, nullptr, ap);
 }
 
+// The x transform of psi that starts a run of the differentiated form.
 void x_init_rt(mvd_handle* h) {
-  HIPCHECK(mvd_launch_x(args(h, h->stream, h->rt_grid[0]), h->rt_cfg[0], 0, 0, nullptr, h->d_flags, 1));
+  const int M = h->blocks[0].M, p = mvd_exact_param(PASS_X, M);
+  if (p > 0)
+    HIPCHECK(mvd_launch_x_exact(args(h, h->stream, mvd_tiles(h->jobs[0], PASS_X, p)), M, 0, 0, nullptr, h->d_flags,
+                                XOPT_SPEC));
+  else
+    HIPCHECK(mvd_launch_x(args(h, h->stream, h->rt_grid[0]), h->rt_cfg[0], 0, 0, nullptr, h->d_flags, XOPT_SPEC));
 }
 
 // seed == nullptr: the loss sum_v |psi_n (x) P_v - phi_v|^2 and its

@@ -65,11 +65,13 @@ def grad_case(weighted, seed=5, dims=(40, 36, 30)):
 
 
 @pytest.mark.parametrize("weighted,lam,dims", [(False, 0.0, (40, 36, 30)), (True, 0.02, (40, 36, 30)),
-                                               (True, 0.02, (32, 36, 30)), (False, 0.0, (64, 20, 24))])
+                                               (True, 0.02, (32, 36, 30)), (False, 0.0, (64, 20, 24)),
+                                               (False, 0.0, (16, 720, 10)), (True, 0.02, (2048, 8, 10))])
 def test_backward_matches_oracle_vjp(mvd, weighted, lam, dims):
     """mvd_backward with a random upstream gradient against the oracle's
     vector-Jacobian product; the handle is left at psi_n.  Half-rows of 20
-    use the runtime-plan adjoint x passes, 16 and 32 the compile-time ones."""
+    and 8 use the runtime-plan adjoint x passes, 16, 32 and 1024 the
+    compile-time ones; 720 along y exceeds the runtime plans' lengths."""
     s, psfs, w, psi0, rng = grad_case(weighted, dims=dims)
     gbar = rng.normal(size=psi0.shape).astype(np.float32)
     n = 3
