@@ -33,8 +33,12 @@ EM/OSEM, fixed point, flux, non-negativity, closed forms, delta-kernel special
 cases), tests/test_oracle_combined.py (combined updates: explicit EM, fixed
 point, single-view and identical-view reductions), tests/test_oracle_weights.py
 (normalisation modes and the contributing-view image on hand-counted cases),
-tests/test_oracle_linear.py (linear boundary: explicit restricted-matrix EM,
-fixed point, delta kernels) and tests/test_oracle_grad.py (adjoint identities,
+tests/test_oracle_linear.py (linear boundary: the restricted-matrix EM step
+weighted by the sensitivity with explicit matrices, fixed point, flux
+identity, delta kernels), tests/test_oracle_blocked.py (block-wise form:
+equal to the whole-volume update and to direct summation with a halo of
+twice the kernel radius, different with a thinner one) and
+tests/test_oracle_grad.py (adjoint identities,
 central finite differences of the loss and of <gbar, psi_n>).  No function is
 "parity unpinned".
 """
@@ -337,14 +341,17 @@ class Problem:
 # The views are known on the volume only; light from sources up to one PSF
 # radius p outside it reaches it.  psi lives on the extended domain
 # (n + 2p per axis, the volume at offset p); b = psi * P is evaluated on the
-# volume (linear convolution), and the update divides the back-projection by
-# the view's sensitivity N = 1_volume * K (EM with the restricted system
-# matrix: psi' = psi A^T(phi / A psi) / A^T 1).  Margin voxels with
-# N < SENS_MIN (they send less than 1 % of their light into the volume) are
-# not updated: the division would magnify the transforms' round-off there.  Weights apply on the volume and are 1 in
-# the margin.
-
-SENS_MIN = 1e-2
+# volume (linear convolution).  Where a view has no data (outside the volume)
+# its ratio is neutral, q = 1, and the back-projection c = q * K is taken over
+# that extended ratio, so the update is the same as the circular one on the
+# extended domain.  Written with the view's sensitivity N = 1_volume * K (the
+# part of K's light a voxel sends into the volume) this step is
+#     psi (c) = psi (1 - N + K^T q)  =  psi + N (psi K^T q / N - psi):
+# the restricted-matrix EM step psi K^T q / N taken as the fraction N of a
+# full step, the same device the paper uses for partially overlapping views
+# (a weight is the fraction of one RL step applied at a voxel).  It has no
+# constant of its own and never divides by N.  Weights apply on the volume
+# and are 1 in the margin.
 
 
 def margins(psfs):
@@ -367,21 +374,31 @@ def lin_blur(psi_e, P, p):
 
 
 def lin_back(q, K, p):
-    """Back-projection onto the extended domain: sum_x K[c + (xi - x)] q(x)."""
+    """Back-projection of a ratio given on the volume (zero elsewhere) onto
+    the extended domain: sum_x K[c + (xi - x)] q(x)."""
     return signal.fftconvolve(q, pad_kernel(K, p), mode="full")
 
 
-def view_update_linear(psi_e, phi, P, K, p, w_e=None, lam_p=0.0, eps=0.0):
-    """One view-update with the linear boundary (see the block comment)."""
+def sensitivity(n, K, p):
+    """N = 1_volume * K on the extended domain: the part of K's light that a
+    voxel sends into the volume."""
+    return lin_back(np.ones(n), K, p)
+
+
+def view_update_linear(psi_e, phi, P, K, p, w_e=None, lam_p=0.0, eps=0.0, stats=None):
+    """One view-update with the linear boundary (see the block comment):
+    b on the volume, q = phi / max(b, eps) there and 1 on a band of 2p around
+    it (every ratio the extended domain's back-projection reaches), c = q * K
+    on the extended domain, then the steps of the circular update."""
     b = lin_blur(psi_e, P, p)
     q = phi / np.maximum(b, eps)
-    c = np.maximum(lin_back(q, K, p), 0.0)
-    N = lin_back(np.ones_like(phi), K, p)
-    live = N >= SENS_MIN
-    u = psi_e.copy()
-    u[live] = psi_e[live] * c[live] / N[live]
+    q_ext = np.pad(q, [(2 * a, 2 * a) for a in p], constant_values=1.0)
+    c = signal.fftconvolve(q_ext, pad_kernel(K, p), mode="valid")
+    if stats is not None:
+        stats["ratio_clamps"] = stats.get("ratio_clamps", 0) + int(np.count_nonzero(b < eps))
+        stats["neg_clamps"] = stats.get("neg_clamps", 0) + int(np.count_nonzero(c < 0))
+    u = psi_e * np.maximum(c, 0.0)
     t = tikhonov(u, lam_p)
-    t[~live] = psi_e[~live]
     if w_e is None:
         return t
     return psi_e + w_e * (t - psi_e)
@@ -413,10 +430,71 @@ class ProblemLinear(Problem):
         for _ in range(n_iter):
             for v in range(self.n):
                 w = None if self.weights_e is None else self.weights_e[v]
-                psi = view_update_linear(psi, self.views[v], self.P[v], K[v], self.p, w, self.lam_p, self.eps)
+                psi = view_update_linear(psi, self.views[v], self.P[v], K[v], self.p, w, self.lam_p, self.eps,
+                                         stats=stats)
                 if flux is not None:
                     flux.append(float(psi.sum()))
         return psi
+
+
+# ------------------------------------------------------- block-wise form --
+#
+# The paper processes a volume "in blocks to reduce the memory requirements"
+# (main text; implementation section: copying and pasting blocks).  Here the
+# volume (any extents, circular boundary: one period of a periodic grid) is
+# cut into near-equal blocks; for each view-update every block takes psi,
+# phi_v and w_v on its own computation grid, the block plus a halo wrapped
+# periodically from the volume, runs the circular update on that grid and
+# pastes its own voxels back.  Every block of one view-update reads the same
+# psi.  A halo of at least twice the kernel radius on each side leaves the
+# pasted voxels equal to the whole-volume update (the blur needs psi within
+# one radius of a ratio voxel, the back-projection the ratio within one
+# radius of an updated voxel); a thinner halo lets the grid's wrap-around
+# reach them.
+
+def block_layout(n, tiles):
+    """(origin, extent) of `tiles` near-equal blocks along an axis of n voxels."""
+    o = [(k * n) // tiles for k in range(tiles + 1)]
+    return [(o[k], o[k + 1] - o[k]) for k in range(tiles)]
+
+
+def wrap_window(f, start, shape):
+    """f on the box start + [0, shape) per axis, read periodically."""
+    idx = [np.arange(a, a + m) % n for a, m, n in zip(start, shape, f.shape)]
+    return f[np.ix_(*idx)]
+
+
+def view_update_blocked(psi, phi, P, K, tiles, halo, grid, w=None, lam_p=0.0, eps=0.0, conv=circ_conv):
+    """One view-update computed block by block (see the block comment).
+    tiles: blocks per axis (z, y, x); halo: voxels of the grid before a
+    block's first voxel, per axis; grid: extents of every block's
+    computation grid, at least the largest block plus twice the halo."""
+    psi = np.asarray(psi, dtype=np.float64)
+    out = np.empty_like(psi)
+    lay = [block_layout(psi.shape[a], tiles[a]) for a in range(3)]
+    for oz, ez in lay[0]:
+        for oy, ey in lay[1]:
+            for ox, ex in lay[2]:
+                if ez + 2 * halo[0] > grid[0] or ey + 2 * halo[1] > grid[1] or ex + 2 * halo[2] > grid[2]:
+                    raise ValueError("the grid must hold a block and its halo on both sides")
+                start = (oz - halo[0], oy - halo[1], ox - halo[2])
+                g_w = None if w is None else wrap_window(w, start, grid)
+                g_new = view_update(wrap_window(psi, start, grid), wrap_window(phi, start, grid), P, K, g_w,
+                                    lam_p, eps, conv=conv)
+                out[oz:oz + ez, oy:oy + ey, ox:ox + ex] = g_new[halo[0]:halo[0] + ez, halo[1]:halo[1] + ey,
+                                                                halo[2]:halo[2] + ex]
+    return out
+
+
+def iterate_blocked(pb, psi, n_iter, variant, tiles, halo, grid):
+    """n_iter sequential iterations of Problem pb computed block by block."""
+    K = pb.kernels(variant)
+    psi = np.array(psi, dtype=np.float64)
+    for _ in range(n_iter):
+        for v in range(pb.n):
+            w = None if pb.weights is None else pb.weights[v]
+            psi = view_update_blocked(psi, pb.views[v], pb.P[v], K[v], tiles, halo, grid, w, pb.lam_p, pb.eps)
+    return psi
 
 
 def run(views, psfs, n_iter, variant, weights=None, lam=0.0, psi0=None, trajectory=False):
