@@ -298,3 +298,59 @@ def test_sampled_view_update_equals_whole_volume_update():
     pts = [(0, 0, 0), (9, 11, 13), (5, 6, 7), (1, 10, 2), (8, 0, 12)]
     got = O.view_update_at(psi, phi, P, K, pts, w, 0.03, 1e-3)
     np.testing.assert_allclose(got, [full[p] for p in pts], rtol=1e-12)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.4])
+def test_fractional_weight_blends_the_step_linearly(lam):
+    """Delta PSFs make both convolutions the identity, so one RL step from psi
+    gives u = phi (every voxel, no clamp): the step's target is t with
+    lambda' t^2 + t = phi, and a weight 0 < w < 1 moves psi the fraction w of
+    the way to it, psi' = psi + w (t - psi) (the section on partially
+    overlapping data: a weight is the fraction of the RL step applied).  A
+    geometric blend psi (t / psi)^w, or Tikhonov applied after the blend,
+    lands elsewhere."""
+    rng = np.random.default_rng(15)
+    shape = (5, 6, 7)
+    phi = rand_volume(rng, shape, 2.0, 40.0)
+    psi = rand_volume(rng, shape, 1.0, 60.0)
+    w = rng.uniform(0.1, 0.9, size=shape)
+    pb = O.Problem([phi], [np.ones((1, 1, 1))], [w], lam=lam)
+    out = pb.iterate(psi, 1, O.RL)
+    t = psi + (out - psi) / w  # the step's target implied by a linear blend
+    lp = lam / pb.s
+    np.testing.assert_allclose(lp * t * t + t, phi, rtol=1e-12)
+    if lam == 0.0:
+        np.testing.assert_allclose(out, psi + w * (phi - psi), rtol=1e-13)
+    geometric = psi * (t / psi) ** w
+    assert np.max(np.abs(geometric - out) / out) > 1e-2
+    if lam > 0:
+        late = psi + w * (phi - psi)
+        late = 2 * late / (1 + np.sqrt(1 + 4 * lp * late))
+        assert np.max(np.abs(late - out) / out) > 1e-3
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_even_psf_extent_centre(axis):
+    """An even extent gets one trailing zero plane, so the centre of a
+    2-voxel kernel is its second voxel: a delta there blurs nothing, a delta
+    on the first voxel shifts by one voxel toward the origin, b(x) =
+    psi(x + 1).  A leading plane would swap the two results."""
+    rng = np.random.default_rng(16 + axis)
+    psi = rand_volume(rng, (6, 7, 8))
+    shape = [1, 1, 1]
+    shape[axis] = 2
+    first, second = np.zeros(shape), np.zeros(shape)
+    first.flat[0] = 1.0
+    second.flat[1] = 1.0
+    np.testing.assert_allclose(O.circ_conv_direct(psi, O.prepare_psf(second)), psi, rtol=1e-15)
+    np.testing.assert_allclose(O.circ_conv_direct(psi, O.prepare_psf(first)), np.roll(psi, -1, axis=axis),
+                               rtol=1e-15)
+    np.testing.assert_allclose(O.circ_conv(psi, O.prepare_psf(first)), np.roll(psi, -1, axis=axis), rtol=1e-12)
+    # the whole update: one RL step with the first-voxel delta from any psi
+    # gives psi'(x) = phi(x - 1), whose blur is phi again
+    phi = rand_volume(rng, (6, 7, 8), 1.0, 9.0)
+    pb = O.Problem([phi], [first])
+    np.testing.assert_allclose(pb.iterate(pb.psi0(), 1, O.RL), np.roll(phi, 1, axis=axis), rtol=1e-12)
+    out = pb.iterate(psi, 1, O.RL)
+    np.testing.assert_allclose(out, np.roll(phi, 1, axis=axis), rtol=1e-12)
+    np.testing.assert_allclose(O.circ_conv(out, O.prepare_psf(first)), phi, rtol=1e-12)
