@@ -122,11 +122,15 @@ typedef void (*mvd_free_fn)(void* ptr, void* ctx);
  *              The handle computes on the volume extended by the largest
  *              PSF radius per axis, rounded up to transform lengths (that
  *              grid must stay within the limits above: MVD_EINVAL); each
- *              view's blur is evaluated on the volume and the
- *              back-projection is divided by the view's sensitivity
- *              1_volume (x) K_v (EM with the restricted system matrix;
- *              margin voxels that send less than 1 % of their light
- *              into the volume (sensitivity < 0.01) are not updated).
+ *              view's blur is evaluated on the volume, and outside the
+ *              volume, where the view has no data, its ratio is 1, so the
+ *              back-projection over the grid leaves a margin voxel's step
+ *              to the part of its light that reaches the volume (per voxel
+ *              the restricted-matrix EM step applied as the fraction
+ *              1_volume (x) K_v of a full step, as weights apply a fraction
+ *              of a step: section on partially overlapping data; the volume
+ *              padded by the PSF size, Supp. Table 1).  No threshold and no
+ *              division by that fraction.
  *              Weights apply on the volume and are 1 in the margin.  Only
  *              the sequential scheme (mvd_iterate, mvd_view_update) runs with
  *              it; estimates are read and set on the volume (setting one

@@ -118,7 +118,6 @@ struct RowOp {
   float2* buf;
   const float2 (&pa)[MAXB][R];
   const float2 (&pb)[MAXB][R];
-  const float2 (&pn)[MAXB][R];  // the view's sensitivity (MODE 5)
   float* psi_rows;  // psi at row wrow0 (MODES 2, 4)
   float* acc_rows;  // the combined factor at row wrow0 (MODES 3, 4)
   int nx, nrw;
@@ -132,21 +131,12 @@ struct RowOp {
     if (line >= nrw) return;
     float2 o;
     if (MODE == 1) {
-      ncr += (z.x < eps) + (z.y < eps);
-      o = make_float2(pa[i][r].x / fmaxf(z.x, eps), pa[i][r].y / fmaxf(z.y, eps));
-    } else if (MODE == 2 || MODE == 5) {
+      o = ratio2(pa[i][r], z, eps, ncr);
+    } else if (MODE == 2) {
       ncn += (z.x < 0.f) + (z.y < 0.f);
       const float2 p = pa[i][r];
       const float ux = p.x * (z.x > 0.f ? z.x : 0.f), uy = p.y * (z.y > 0.f ? z.y : 0.f);
-      float tx, ty;
-      if (MODE == 5) {
-        const float2 n = pn[i][r];
-        tx = n.x >= MVD_SENS_MIN ? tikhonov(ux / n.x, lamp) : p.x;
-        ty = n.y >= MVD_SENS_MIN ? tikhonov(uy / n.y, lamp) : p.y;
-      } else {
-        tx = tikhonov(ux, lamp);
-        ty = tikhonov(uy, lamp);
-      }
+      const float tx = tikhonov(ux, lamp), ty = tikhonov(uy, lamp);
       if (weighted) {
         o = make_float2(p.x + pb[i][r].x * (tx - p.x), p.y + pb[i][r].y * (ty - p.y));
       } else {
@@ -439,7 +429,7 @@ __global__ void __launch_bounds__(64 * WPB)
                const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
                int opt) {
   constexpr int T = 64 * WPB;
-  constexpr bool UPD = MODE == 2 || MODE == 4 || MODE == 5;  // modes that write psi
+  constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
   constexpr int RW = WPB * RPW;
   constexpr int NPAIR = M / 2 + 1;
   constexpr int NPIT = (RPW * NPAIR + 63) / 64;
@@ -489,14 +479,13 @@ __global__ void __launch_bounds__(64 * WPB)
   } else {
     // operands of the pointwise step, in the order the last inverse stage
     // produces its outputs
-    float2 pa[LM::MAXB][RL], pb[LM::MAXB][RL], pn[LM::MAXB][RL];
-    const float* opa = MODE == 1                 ? J.phi + vo + rowoff
-                       : (MODE == 2 || MODE == 5) ? J.psi + rowoff
-                                                  : (first ? nullptr : J.acc + rowoff);
-    const float* opb = (MODE == 2 || MODE == 5) ? (J.w ? J.w + vo + rowoff : nullptr)
-                       : MODE == 4               ? J.psi + rowoff
-                                                 : nullptr;
-    const float* opn = MODE == 5 ? J.sens[opt >> XOPT_VARIANT_SHIFT] + vo + rowoff : nullptr;
+    float2 pa[LM::MAXB][RL], pb[LM::MAXB][RL];
+    const float* opa = MODE == 1   ? J.phi + vo + rowoff
+                       : MODE == 2 ? J.psi + rowoff
+                                   : (first ? nullptr : J.acc + rowoff);
+    const float* opb = MODE == 2   ? (J.w ? J.w + vo + rowoff : nullptr)
+                       : MODE == 4 ? J.psi + rowoff
+                                   : nullptr;
 #pragma unroll
     for (int i = 0; i < LM::MAXB; ++i) {
       int line, j;
@@ -505,8 +494,7 @@ __global__ void __launch_bounds__(64 * WPB)
       for (int r = 0; r < RL; ++r) {
         const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
         pa[i][r] = (ok && opa) ? ld2(opa + g) : make_float2(0.f, 0.f);
-        pb[i][r] = ((MODE == 2 || MODE == 4 || MODE == 5) && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
-        if (MODE == 5) pn[i][r] = ok ? ld2(opn + g) : make_float2(0.f, 0.f);
+        pb[i][r] = ((MODE == 2 || MODE == 4) && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
       }
     }
     // rebuild the M-point spectrum Z of these rows from their half spectrum X
@@ -543,7 +531,7 @@ __global__ void __launch_bounds__(64 * WPB)
       }
     }
     gsync<SYNC_WAVE>();
-    RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  pn, J.psi + rowoff,
+    RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff,
                                     (MODE == 3 || MODE == 4) ? J.acc + rowoff : nullptr,
                                     nx,    nrw,   opb != nullptr,  first, geo,
                                     J.eps, J.lamp, 1.f / (float)J.nviews, 0.0, 0u, 0u, false};

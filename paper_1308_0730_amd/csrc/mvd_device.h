@@ -112,4 +112,13 @@ __device__ __forceinline__ float tikhonov(float u, float lamp) {
   return lamp > 0.f ? 2.f * u / (1.f + sqrtf(1.f + 4.f * lamp * u)) : u;
 }
 
+// Ratio of observed to expected for the two real values of a packed pair:
+// phi / max(b, eps), counting b < eps; 1 where the view has no data
+// (MVD_NO_DATA, grid voxels outside the volume with the linear boundary).
+__device__ __forceinline__ float2 ratio2(float2 phi, float2 b, float eps, unsigned& nclamp) {
+  const bool dx = phi.x >= 0.f, dy = phi.y >= 0.f;
+  nclamp += (dx && b.x < eps) + (dy && b.y < eps);
+  return make_float2(dx ? phi.x / fmaxf(b.x, eps) : 1.f, dy ? phi.y / fmaxf(b.y, eps) : 1.f);
+}
+
 }  // namespace mvdk

@@ -39,6 +39,19 @@ __global__ void __launch_bounds__(256) k_extract(float* __restrict__ vol, const 
     stg(vol + i, ldg(grid + grid_index(b, i)));
 }
 
+// every grid voxel outside the box gets val
+__global__ void __launch_bounds__(256) k_fill_outside(float* __restrict__ grid, Box b, float val) {
+  const int64_t n = (int64_t)b.nx * b.ny * b.nz;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int x = (int)(i % b.nx);
+    const int64_t r = i / b.nx;
+    const int y = (int)(r % b.ny);
+    const int z = (int)(r / b.ny);
+    const bool in = x >= b.ox && x < b.ox + b.ux && y >= b.oy && y < b.oy + b.uy && z >= b.oz && z < b.oz + b.uz;
+    if (!in) stg(grid + i, val);
+  }
+}
+
 int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
 Box box(const int* grid, const int* user, const int* off) {
@@ -58,5 +71,12 @@ hipError_t mvd_launch_extract(float* vol, const int* udims, const float* grid, c
                               hipStream_t s) {
   const Box b = box(gdims, udims, off);
   k_extract<<<blocks_for((int64_t)b.ux * b.uy * b.uz), 256, 0, s>>>(vol, grid, b);
+  return hipGetLastError();
+}
+
+hipError_t mvd_launch_fill_outside(float* grid, const int* gdims, const int* udims, const int* off, float val,
+                                   hipStream_t s) {
+  const Box b = box(gdims, udims, off);
+  k_fill_outside<<<blocks_for((int64_t)b.nx * b.ny * b.nz), 256, 0, s>>>(grid, b, val);
   return hipGetLastError();
 }

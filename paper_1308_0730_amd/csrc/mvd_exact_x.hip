@@ -1,5 +1,4 @@
-// x passes of the sequential scheme (modes 0-2, and 5 with the linear
-// boundary) with compile-time plans for
+// x passes of the sequential scheme (modes 0-2) with compile-time plans for
 // every 5-smooth half-row length (lists in mvd_exact_lengths.h); the modes
 // of the combined updates are in mvd_exact_x_comb.hip.  A launch covers jobs
 // whose nx / 2 is the plan's length.
@@ -37,7 +36,6 @@ hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Parti
       XM(0, m, wpb, rpw, __VA_ARGS__)     \
       XM(1, m, wpb, rpw, __VA_ARGS__)     \
       XM(2, m, wpb, rpw, __VA_ARGS__)     \
-      XM(5, m, wpb, rpw, __VA_ARGS__)     \
       default:                            \
         return hipErrorInvalidValue;      \
     }                                     \

@@ -101,3 +101,6 @@ hipError_t mvd_launch_embed(float* grid, const int* gdims, const float* vol, con
                             hipStream_t s);
 hipError_t mvd_launch_extract(float* vol, const int* udims, const float* grid, const int* gdims, const int* off,
                               hipStream_t s);
+// every voxel of the grid outside the (ux, uy, uz) box at offset off gets val
+hipError_t mvd_launch_fill_outside(float* grid, const int* gdims, const int* udims, const int* off, float val,
+                                   hipStream_t s);

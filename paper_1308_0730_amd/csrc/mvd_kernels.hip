@@ -32,9 +32,8 @@ using namespace mvdk;
 // folds max(c, 0) of one view into the factor acc (product, or sum); MODE 4
 // does the same for the last view, then psi <- T(psi . mean) with the
 // |V|-th root of the product or the sum over |V|, and the forward x of the
-// new psi (when opt has XOPT_SPEC).  MODE 5: MODE 2 with the linear
-// boundary: the back-projection is divided by the view's sensitivity (of the
-// variant in the option bits), and voxels below MVD_SENS_MIN keep psi.
+// new psi (when opt has XOPT_SPEC).  Where the view holds MVD_NO_DATA (grid
+// voxels outside the volume with the linear boundary) the ratio is 1.
 //
 // A row of nx reals is handled as M = nx/2 complex values z[n] = x[2n] +
 // i x[2n+1]; the half spectrum follows from the M-point transform Z by
@@ -50,7 +49,7 @@ __global__ void __launch_bounds__(64 * WPB)
   constexpr int T = 64 * WPB;
   constexpr int RW = WPB * RPW;
   constexpr int EPT = (RPW * MAXM + 63) / 64;
-  constexpr bool UPD = MODE == 2 || MODE == 4 || MODE == 5;  // modes that write psi
+  constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
   constexpr int NPIT = (RPW * (MAXM / 2 + 1) + 63) / 64;
   __shared__ float2 lds[RW * MAXM];
   __shared__ float2 s_tw[MAXM];
@@ -89,22 +88,20 @@ __global__ void __launch_bounds__(64 * WPB)
   const int64_t vo = (int64_t)v * J.V;
   const float eps = J.eps, lamp = J.lamp;
   const float* wv = J.w ? J.w + vo : nullptr;
-  const float* sv = MODE == 5 ? J.sens[opt >> XOPT_VARIANT_SHIFT] + vo : nullptr;
 
   // prefetch the pointwise operands of this lane's elements
-  float2 pa[EPT], pb[EPT], pn[EPT];
+  float2 pa[EPT], pb[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int it = lane + i * 64;
     const int r = RPW == 1 ? 0 : udiv(it, mM);
     const int p = it - r * M;
-    pa[i] = pb[i] = pn[i] = make_float2(0.f, 0.f);
+    pa[i] = pb[i] = make_float2(0.f, 0.f);
     if (r < nrw && p < M) {
       const int64_t g = (int64_t)(wrow0 + r) * nx + 2 * p;
       if (MODE == 1) pa[i] = ld2(J.phi + vo + g);
-      if (MODE == 0 || MODE == 2 || MODE == 5) pa[i] = ld2(J.psi + g);
-      if ((MODE == 2 || MODE == 5) && wv) pb[i] = ld2(wv + g);
-      if (MODE == 5) pn[i] = ld2(sv + g);
+      if (MODE == 0 || MODE == 2) pa[i] = ld2(J.psi + g);
+      if (MODE == 2 && wv) pb[i] = ld2(wv + g);
       if ((MODE == 3 || MODE == 4) && !first) pa[i] = ld2(J.acc + g);
       if (MODE == 4) pb[i] = ld2(J.psi + g);
     }
@@ -171,8 +168,7 @@ __global__ void __launch_bounds__(64 * WPB)
         const float2 z = L.ld(r, p);
         float2 o;
         if (MODE == 1) {
-          ncr += (z.x < eps) + (z.y < eps);
-          o = make_float2(pa[i].x / fmaxf(z.x, eps), pa[i].y / fmaxf(z.y, eps));
+          o = ratio2(pa[i], z, eps, ncr);
         } else if (MODE == 3 || MODE == 4) {
           ncn += (z.x < 0.f) + (z.y < 0.f);
           const float cx = z.x > 0.f ? z.x : 0.f, cy = z.y > 0.f ? z.y : 0.f;
@@ -197,14 +193,7 @@ __global__ void __launch_bounds__(64 * WPB)
           ncn += (z.x < 0.f) + (z.y < 0.f);
           const float ux = pa[i].x * (z.x > 0.f ? z.x : 0.f);
           const float uy = pa[i].y * (z.y > 0.f ? z.y : 0.f);
-          float tx, ty;
-          if (MODE == 5) {
-            tx = pn[i].x >= MVD_SENS_MIN ? tikhonov(ux / pn[i].x, lamp) : pa[i].x;
-            ty = pn[i].y >= MVD_SENS_MIN ? tikhonov(uy / pn[i].y, lamp) : pa[i].y;
-          } else {
-            tx = tikhonov(ux, lamp);
-            ty = tikhonov(uy, lamp);
-          }
+          const float tx = tikhonov(ux, lamp), ty = tikhonov(uy, lamp);
           if (wv) {
             o = make_float2(pa[i].x + pb[i].x * (tx - pa[i].x), pa[i].y + pb[i].y * (ty - pa[i].y));
           } else {
@@ -514,7 +503,7 @@ int mvd_exact_param(int kind, int len) {
 }
 
 hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* parts, int* flags, int opt) {
-  if (mode < 0 || mode > 5) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 4) return hipErrorInvalidValue;
   if (cfg >= rt_num(PASS_X)) return mvd_launch_x_ct(a, cfg - rt_num(PASS_X), mode, v, parts, flags, opt);
   switch (cfg) {
 #define XM(md, wpb, rpw, m)                                                                              \
@@ -530,7 +519,6 @@ hipError_t mvd_launch_x(const LaunchArgs& a, int cfg, int mode, int v, Partial* 
       XM(2, wpb, rpw, m)     \
       XM(3, wpb, rpw, m)     \
       XM(4, wpb, rpw, m)     \
-      XM(5, wpb, rpw, m)     \
     }                        \
     break;
     MVD_ROW_CFGS(X)

@@ -63,7 +63,6 @@ hipError_t mvd_launch_x_ct(const LaunchArgs& a, int cfg, int mode, int v, Partia
       XM(2, wpb, rpw, m, __VA_ARGS__)   \
       XM(3, wpb, rpw, m, __VA_ARGS__)   \
       XM(4, wpb, rpw, m, __VA_ARGS__)   \
-      XM(5, wpb, rpw, m, __VA_ARGS__)   \
       default:                          \
         return hipErrorInvalidValue;    \
     }                                   \

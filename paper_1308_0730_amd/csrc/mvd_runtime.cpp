@@ -58,8 +58,6 @@ struct Block {
   // in the computation grid (nx, ny, nz); circular: the same box, offset 0
   int ux = 0, uy = 0, uz = 0, ox = 0, oy = 0, oz = 0;
   int64_t UV = 0;
-  float* sens[4] = {nullptr, nullptr, nullptr, nullptr};  // [nviews][V] per variant
-  float* lin_save = nullptr;                               // psi while a sensitivity is built
   std::vector<mvdh::Kern> P;  // prepared PSFs
   std::vector<double> psf_sum;     // sums of the raw PSF inputs
   std::vector<std::array<int, 3>> psf_dims;  // raw extents {kx, ky, kz}
@@ -125,7 +123,6 @@ struct mvd_handle {
   size_t parts_cap = 0;
   bool spec_valid = false;
   bool linear = false;            // MVD_BOUNDARY_LINEAR
-  bool sens_built[4] = {false, false, false, false};
   bool built[N_ROLES] = {true, false, false, false};
   int64_t iterations = 0;
   // one graph per (scheme, variant): scheme 0 sequential, 1 combined with
@@ -410,7 +407,6 @@ void build_jobs(mvd_handle* h) {
     for (int r = 0; r < N_ROLES; ++r) j.H[r] = B.H[r];
     j.acc = B.acc;
     j.saved = B.saved;
-    for (int r = 0; r < 4; ++r) j.sens[r] = B.sens[r];
     j.eps = B.eps;
     j.lamp = B.lamp;
     h->jobs.push_back(j);
@@ -649,8 +645,9 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
           HIPCHECK(hipMemcpyAsync(B.w + (size_t)v * B.V, p.weights[v], B.V * sizeof(float), kind, h->stream));
       }
     } else {
-      // views are zero and weights one outside the volume; host inputs pass
-      // through the (not yet used) estimate buffer
+      // views are zero (until the value checks below) and weights one
+      // outside the volume; host inputs pass through the (not yet used)
+      // estimate buffer
       HIPCHECK(mvd_launch_fill(B.phi, (int64_t)N * B.V, 0.f, h->stream));
       if (p.weights) HIPCHECK(mvd_launch_fill(B.w, (int64_t)N * B.V, 1.f, h->stream));
       auto put = [&](float* grid, const float* src) {
@@ -681,6 +678,12 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     }
     B.s = total / ((double)N * (double)B.UV);
     if (!(B.s > 0)) bad("block " + std::to_string(b) + ": the views are all zero");
+    // linear boundary: outside the volume a view has no data (the ratio pass
+    // takes q = 1 there)
+    if (h->linear)
+      for (int v = 0; v < N; ++v)
+        HIPCHECK(mvd_launch_fill_outside(B.phi + (size_t)v * B.V, grid_dims(B), user_dims(B), offsets(B), MVD_NO_DATA,
+                                         h->stream));
     B.eps = (float)(h->eps_scale * B.s);
     B.lamp = (float)(h->lambda / B.s);
     if (p.mem_kind == MVD_MEM_DEVICE) {
@@ -902,10 +905,7 @@ void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t
   timed(0, [&] { run_y(h, s, 0, v); });
   timed(2, [&] { run_z(h, s, v, role, conj_back, 0); });
   timed(1, [&] { run_y(h, s, 1, v); });
-  if (h->linear)
-    timed(4, [&] { run_x(h, s, 5, v, parts, XOPT_SPEC | (variant << XOPT_VARIANT_SHIFT)); });
-  else
-    timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
+  timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
 }
 
 // One iteration: every view once, in index order (section 7).  When every
@@ -968,49 +968,6 @@ void enqueue_combined_iteration(mvd_handle* h, hipStream_t s, int variant, bool 
   }
 }
 
-void ensure_combined(mvd_handle* h);
-
-// Linear boundary: each view's sensitivity 1_volume (x) K_v for `variant`
-// (K_v = P_v* for RL), computed with the handle's own passes: the
-// indicator of the volume goes through the forward x and y transforms once,
-// then per view through the z pass of K_v (reading the saved spectrum), the
-// inverse y and the inverse x, whose output is max(., 0).  psi is kept aside.
-void ensure_sens(mvd_handle* h, int variant) {
-  if (h->sens_built[variant]) return;
-  const int role = variant == MVD_RL ? ROLE_P : variant;
-  const int conj_back = variant == MVD_RL ? 1 : 0;
-  ensure_combined(h);
-  hipStream_t s = h->stream;
-  for (auto& B : h->blocks) {
-    if (!B.sens[variant]) B.sens[variant] = (float*)h->dalloc((size_t)h->nviews * B.V * sizeof(float));
-    if (!B.lin_save) B.lin_save = (float*)h->dalloc(B.V * sizeof(float));
-    HIPCHECK(hipMemcpyAsync(B.lin_save, B.psi, B.V * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // psi <- indicator: zero grid, ones embedded from the factor buffer
-    HIPCHECK(mvd_launch_fill(B.psi, B.V, 0.f, s));
-    HIPCHECK(mvd_launch_fill(B.acc, B.UV, 1.f, s));
-    HIPCHECK(mvd_launch_embed(B.psi, grid_dims(B), B.acc, user_dims(B), offsets(B), s));
-  }
-  build_jobs(h);
-  run_x(h, s, 0, 0, nullptr, XOPT_SPEC);
-  run_y(h, s, 0, 0);
-  for (const auto& B : h->blocks)
-    HIPCHECK(hipMemcpyAsync(B.saved, B.spec, B.spec_elems * 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  for (int v = 0; v < h->nviews; ++v) {
-    Partial* parts = h->d_parts + (size_t)v * h->grid_x;
-    run_z(h, s, v, role, conj_back, 1);
-    run_y(h, s, 1, v);
-    run_x(h, s, 3, v, parts, XOPT_FIRST);
-    for (const auto& B : h->blocks)
-      HIPCHECK(hipMemcpyAsync(B.sens[variant] + (size_t)v * B.V, B.acc, B.V * sizeof(float), hipMemcpyDeviceToDevice,
-                              s));
-  }
-  for (const auto& B : h->blocks)
-    HIPCHECK(hipMemcpyAsync(B.psi, B.lin_save, B.V * sizeof(float), hipMemcpyDeviceToDevice, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  h->spec_valid = false;
-  h->sens_built[variant] = true;
-}
-
 void ensure_combined(mvd_handle* h) {
   bool grown = false;
   for (auto& B : h->blocks) {
@@ -1030,7 +987,6 @@ void prepare_run(mvd_handle* h, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   const int role = variant == MVD_RL ? ROLE_P : variant;
   ensure_role(h, role);
-  if (h->linear) ensure_sens(h, variant);
   if (!h->spec_valid) {
     run_x(h, h->stream, 0, 0, nullptr, XOPT_SPEC);
     h->spec_valid = true;

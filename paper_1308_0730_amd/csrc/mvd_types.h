@@ -58,21 +58,18 @@ struct JobDesc {
   float* acc;                  // [V] combined-update factor (product or sum over views), or nullptr
   float* saved;                // spec_elems complex: x/y-stage spectrum of psi kept over a combined
                                // iteration, or nullptr
-  const float* sens[4];        // linear boundary: [nviews][V] sensitivity 1_volume (x) K_v per
-                               // variant (RL, EFF, OPT1, OPT2), nullptr if not built
 };
 
-// Linear boundary: a voxel whose sensitivity is below this is not updated.
-#define MVD_SENS_MIN 1e-2f
+// Linear boundary: a view holds this value on the grid voxels outside the
+// volume (where it has no data); the ratio pass takes q = 1 there.  Views
+// are >= 0 on the volume, so the marker is never a measured value.
+#define MVD_NO_DATA (-1.0f)
 
 // Options of the x passes (bit set).  SPEC: write the forward x transform
 // of the new psi (update modes).  FIRST: the first view of a combined
 // iteration (the factor starts from this view's value).  GEO: combine by
 // product and |V|-th root, else by sum and division by |V|.
 enum { XOPT_SPEC = 1, XOPT_FIRST = 2, XOPT_GEO = 4 };
-// The variant of an update with the linear boundary (x mode 5) rides in the
-// option bits from XOPT_VARIANT_SHIFT up.
-enum { XOPT_VARIANT_SHIFT = 8 };
 
 // Per-workgroup partial results of the x passes (one entry per x tile).
 struct Partial {
