@@ -321,6 +321,34 @@ int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_di
 int mvd_kernel_spectrum(const double* kernel, const int* kdims, const int* dims, float* main_out,
                         float* nyq_out);
 
+/* ---- no-allocation run ---------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * work as mvd_create, mvd_set_estimate (when psi0 is not NULL), mvd_iterate
+ * and mvd_get_estimate into psi_out, on one volume, with every device buffer
+ * (estimate, spectrum, views, weights, kernel planes, FFT plans and tables,
+ * partial sums, flags) placed in a static array of the library of
+ * MVD_NOALLOC_SCRATCH_BYTES per GPU instead of being allocated.  No
+ * hipMalloc, hipFree, stream, event or graph is created; the kernels are
+ * those of mvd_iterate, launched directly on o->stream (NULL: the default
+ * stream), and the call returns when they are done.
+ *   p        one volume as for mvd_create (host or device inputs)
+ *   o        options as for mvd_create (NULL = defaults), except that alloc
+ *            and free must be NULL (MVD_EINVAL) and use_graphs is ignored
+ *   psi0     NULL (flat start s) or nx*ny*nz device floats, finite, >= 0
+ *   n, variant  as for mvd_iterate
+ *   psi_out  nx*ny*nz device floats: the estimate after the run (may be psi0)
+ * Returns MVD_EINVAL with a message naming the sizes when the problem needs
+ * more than the array holds (roughly 4 (2 + n_views (1 + weights)) bytes per
+ * voxel plus the kernel planes, e.g. 128^3 with 4 views and no weights),
+ * MVD_ENONFINITE if the estimate became non-finite.  Every call on a GPU
+ * reuses that GPU's array and starts from nothing in it; calls that overlap
+ * on one GPU (from several threads, or on streams the caller does not
+ * order) race on the array and give wrong results. */
+#define MVD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mvd_iterate_noalloc(const mvd_problem* p, const mvd_options* o, const float* psi0, int n, int variant,
+                        float* psi_out);
+
 /* Library version string. */
 const char* mvd_version(void);
 

@@ -23,6 +23,13 @@ namespace {
 
 thread_local std::string g_err;
 
+// The no-allocation run (mvd_iterate_noalloc): every buffer it needs lives
+// in this array, one copy per GPU, held from the library's load on that GPU
+// until the process ends.  In host code the name only stands in for the
+// symbol; its device address on the current GPU comes from
+// hipGetSymbolAddress, looked up once per device (scratch_on_current_device).
+static __device__ __align__(256) unsigned char scratch[MVD_NOALLOC_SCRATCH_BYTES];
+
 struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
@@ -80,6 +87,10 @@ struct mvd_handle {
   double lambda = 0, eps_scale = 1e-6;
   bool use_graphs = true;
   int force_cfg = 0;
+  // buffers come from a caller-owned region and no stream, event or graph
+  // is created (the no-allocation entry point: one block, direct launches
+  // on the caller's stream)
+  bool no_alloc = false;
   // device tables
   JobDesc* d_jobs = nullptr;
   // per pass kind: the job table sorted by (lane, that kind's length), and
@@ -595,12 +606,17 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
   }
 
   HIPCHECK(hipGetDevice(&h->device));
-  HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-  for (int i = 0; i < mvd_handle::kSide; ++i) {
-    HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
-    HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
+  if (h->no_alloc) {
+    if (nb != 1) bad("the no-allocation run takes one volume");
+    h->use_graphs = false;
+  } else {
+    HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    for (int i = 0; i < mvd_handle::kSide; ++i) {
+      HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
+    }
+    HIPCHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
   }
-  HIPCHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
 
   std::vector<FftPlan> plans;
   std::vector<float2> tw;
@@ -1453,6 +1469,66 @@ const Block& block_of(mvd_handle* h, int b) {
   return h->blocks[b];
 }
 
+// Copy the estimate of a block out (the volume of the grid with the linear
+// boundary); returns the non-finite flag.  Synchronises.
+int get_estimate_impl(mvd_handle* h, float* dst, int dst_kind, int block) {
+  const Block& B = block_of(h, block);
+  if (!dst) bad("dst is NULL");
+  if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
+  if (!h->linear) {
+    HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
+                            dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    // the volume out of the grid; host copies pass through the factor buffer
+    float* to = dst;
+    if (dst_kind == MVD_MEM_HOST) {
+      ensure_combined(h);
+      to = B.acc;
+    }
+    HIPCHECK(mvd_launch_extract(to, user_dims(B), B.psi, grid_dims(B), offsets(B), h->stream));
+    if (dst_kind == MVD_MEM_HOST)
+      HIPCHECK(hipMemcpyAsync(dst, to, B.UV * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  }
+  return read_flag(h);
+}
+
+// Replace the estimate of a block (checked finite and >= 0); resets the
+// iteration count and the non-finite flag.  Synchronises.
+void set_estimate_impl(mvd_handle* h, const float* src, int src_kind, int block) {
+  Block& B = const_cast<Block&>(block_of(h, block));
+  if (!src) bad("src is NULL");
+  if (src_kind != MVD_MEM_HOST && src_kind != MVD_MEM_DEVICE) bad("src_kind must be host or device");
+  // with the linear boundary the volume goes into the grid (host data via
+  // the factor buffer) and the margin restarts at s
+  float* to = B.psi;
+  if (h->linear) {
+    ensure_combined(h);
+    to = B.acc;
+  }
+  if (src_kind == MVD_MEM_HOST) {
+    for (int64_t i = 0; i < B.UV; ++i)
+      if (!(src[i] >= 0.f) || !std::isfinite(src[i])) bad("estimate has a negative or non-finite value");
+    HIPCHECK(hipMemcpyAsync(to, src, B.UV * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  } else {
+    double s;
+    unsigned long long nb;
+    device_check(h, src, B.UV, 0.f, INFINITY, &s, &nb);
+    if (nb) bad("estimate has a negative or non-finite value");
+    if (h->linear)
+      to = const_cast<float*>(src);
+    else
+      HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+  }
+  if (h->linear) {
+    HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, h->stream));
+    HIPCHECK(mvd_launch_embed(B.psi, grid_dims(B), to, user_dims(B), offsets(B), h->stream));
+  }
+  HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->spec_valid = false;
+  h->iterations = 0;
+}
+
 template <class F>
 int guard(mvd_handle* h, F&& f) {
   try {
@@ -1471,6 +1547,82 @@ int guard(mvd_handle* h, F&& f) {
   } catch (...) {
     (h ? h->err : g_err) = "unknown failure";
     return MVD_EDEVICE;
+  }
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[256] = {};
+
+void* scratch_on_current_device() {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) bad("device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      throw Error(MVD_EDEVICE, std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+    }
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+// Bump allocation over the scratch array (the handle's allocator callbacks;
+// dalloc rounds every request up to 256 bytes, so every buffer stays
+// 256-byte aligned).  Nothing is freed: the region is reused by the next run.
+struct ScratchArena {
+  unsigned char* base;
+  size_t cap, used, refused;
+};
+
+void* arena_alloc(size_t bytes, void* ctx) {
+  auto* a = static_cast<ScratchArena*>(ctx);
+  if (bytes > a->cap - a->used) {
+    a->refused = bytes;
+    return nullptr;
+  }
+  void* p = a->base + a->used;
+  a->used += bytes;
+  return p;
+}
+
+void arena_free(void*, void*) {}
+
+void iterate_noalloc_impl(const mvd_problem* p, const mvd_options* o, const float* psi0, int n, int variant,
+                          float* psi_out) {
+  if (!p) bad("problem is NULL");
+  if (!psi_out) bad("psi_out is NULL");
+  if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
+  if (n < 0) bad("n must be >= 0");
+  if (o && (o->alloc || o->free)) bad("the no-allocation run takes no allocator callbacks");
+  mvd_options opt{};
+  if (o) opt = *o;
+  ScratchArena arena{static_cast<unsigned char*>(scratch_on_current_device()), MVD_NOALLOC_SCRATCH_BYTES, 0, 0};
+  opt.alloc = arena_alloc;
+  opt.free = arena_free;
+  opt.alloc_ctx = &arena;
+  opt.use_graphs = 0;
+  mvd_handle h;
+  h.no_alloc = true;
+  try {
+    create_impl(&h, 1, p, &opt);
+    if (psi0) set_estimate_impl(&h, psi0, MVD_MEM_DEVICE, 0);
+    iterate_impl(&h, n, variant);
+    const int nonfinite = get_estimate_impl(&h, psi_out, MVD_MEM_DEVICE, 0);
+    h.release();
+    if (nonfinite) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
+  } catch (...) {
+    // nothing queued may outlive the call: the next run reuses the region
+    (void)hipStreamSynchronize(h.stream);
+    h.release();
+    if (arena.refused)
+      bad("the problem needs more device memory than the no-allocation run's scratch array holds (" +
+          std::to_string(MVD_NOALLOC_SCRATCH_BYTES) + " bytes; a request of " + std::to_string(arena.refused) +
+          " bytes with " + std::to_string(arena.used) + " in use)");
+    throw;
   }
 }
 
@@ -1557,26 +1709,7 @@ int mvd_get_estimate(mvd_handle* h, float* dst, int dst_kind, int block) {
     return MVD_EINVAL;
   }
   int nonfinite = 0;
-  int rc = guard(h, [&] {
-    const Block& B = block_of(h, block);
-    if (!dst) bad("dst is NULL");
-    if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
-    if (!h->linear) {
-      HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
-                              dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
-    } else {
-      // the volume out of the grid; host copies pass through the factor buffer
-      float* to = dst;
-      if (dst_kind == MVD_MEM_HOST) {
-        ensure_combined(h);
-        to = B.acc;
-      }
-      HIPCHECK(mvd_launch_extract(to, user_dims(B), B.psi, grid_dims(B), offsets(B), h->stream));
-      if (dst_kind == MVD_MEM_HOST)
-        HIPCHECK(hipMemcpyAsync(dst, to, B.UV * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    }
-    nonfinite = read_flag(h);
-  });
+  int rc = guard(h, [&] { nonfinite = get_estimate_impl(h, dst, dst_kind, block); });
   if (rc == MVD_OK && nonfinite) {
     h->err = "the estimate became non-finite";
     return MVD_ENONFINITE;
@@ -1589,40 +1722,7 @@ int mvd_set_estimate(mvd_handle* h, const float* src, int src_kind, int block) {
     g_err = "handle is NULL";
     return MVD_EINVAL;
   }
-  return guard(h, [&] {
-    Block& B = const_cast<Block&>(block_of(h, block));
-    if (!src) bad("src is NULL");
-    if (src_kind != MVD_MEM_HOST && src_kind != MVD_MEM_DEVICE) bad("src_kind must be host or device");
-    // with the linear boundary the volume goes into the grid (host data via
-    // the factor buffer) and the margin restarts at s
-    float* to = B.psi;
-    if (h->linear) {
-      ensure_combined(h);
-      to = B.acc;
-    }
-    if (src_kind == MVD_MEM_HOST) {
-      for (int64_t i = 0; i < B.UV; ++i)
-        if (!(src[i] >= 0.f) || !std::isfinite(src[i])) bad("estimate has a negative or non-finite value");
-      HIPCHECK(hipMemcpyAsync(to, src, B.UV * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    } else {
-      double s;
-      unsigned long long nb;
-      device_check(h, src, B.UV, 0.f, INFINITY, &s, &nb);
-      if (nb) bad("estimate has a negative or non-finite value");
-      if (h->linear)
-        to = const_cast<float*>(src);
-      else
-        HIPCHECK(hipMemcpyAsync(B.psi, src, B.V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
-    }
-    if (h->linear) {
-      HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, h->stream));
-      HIPCHECK(mvd_launch_embed(B.psi, grid_dims(B), to, user_dims(B), offsets(B), h->stream));
-    }
-    HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
-    HIPCHECK(hipStreamSynchronize(h->stream));
-    h->spec_valid = false;
-    h->iterations = 0;
-  });
+  return guard(h, [&] { set_estimate_impl(h, src, src_kind, block); });
 }
 
 int mvd_stats(mvd_handle* h, mvd_stats_t* s) {
@@ -1835,6 +1935,11 @@ int mvd_kernel_spectrum(const double* kernel, const int* kdims, const int* dims,
     K.a.assign(kernel, kernel + (size_t)K.kx * K.ky * K.kz);
     mvdh::spectrum_host(K, dims[0], dims[1], dims[2], main_out, nyq_out);
   });
+}
+
+int mvd_iterate_noalloc(const mvd_problem* p, const mvd_options* o, const float* psi0, int n, int variant,
+                        float* psi_out) {
+  return guard(nullptr, [&] { iterate_noalloc_impl(p, o, psi0, n, variant, psi_out); });
 }
 
 const char* mvd_version(void) { return "mvd 0.1 (gfx950)"; }

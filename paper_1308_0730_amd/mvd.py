@@ -91,6 +91,8 @@ def lib():
     L.mvd_compound_kernel.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int, C.c_int,
                                       C.c_void_p, C.POINTER(C.c_int)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
+    L.mvd_iterate_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Options), C.c_void_p, C.c_int, C.c_int,
+                                      C.c_void_p]
     L.mvd_version.restype = C.c_char_p
     for name in ("mvd_create", "mvd_create_batch", "mvd_iterate", "mvd_iterate_combined", "mvd_grid_dims",
                  "mvd_normalize_weights",
@@ -98,7 +100,7 @@ def lib():
                  "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
-                 "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs"):
+                 "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -166,6 +168,38 @@ class _Marshalled:
                                C.cast(self._p, C.POINTER(C.c_void_p)), C.cast(self._k, C.POINTER(C.c_int)),
                                None if self._w is None else C.cast(self._w, C.POINTER(C.c_void_p)),
                                MEM_DEVICE if on_device else MEM_HOST)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def iterate_noalloc(views, psfs, n, variant="eff", weights=None, lam=0.0, eps_scale=0.0, psi0=None, out=None,
+                    boundary="circular", tile_config=0, device=None):
+    """n iterations on one volume through mvd_iterate_noalloc: the library
+    allocates nothing (its buffers live in a static array of
+    NOALLOC_SCRATCH_BYTES per GPU).  Inputs as for Deconvolver; psi0 (None:
+    flat start) and out are CUDA tensors of the volume's shape (out is created
+    when None: that allocation is the caller's).  Returns out."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    on_device = any(isinstance(v, torch.Tensor) and v.is_cuda for v in views)
+    stream = torch.cuda.current_stream(dev)
+    opts = Options(float(lam), float(eps_scale), C.c_void_p(stream.cuda_stream), ALLOC_FN(), FREE_FN(), None, 0,
+                   int(tile_config), {"circular": 0, "linear": 1}[boundary] if isinstance(boundary, str)
+                   else int(boundary))
+    with torch.cuda.device(dev):
+        m = _Marshalled(views, psfs, weights, dev, on_device)
+        nx, ny, nz = m.dims
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+        for name, t in (("out", out), ("psi0", psi0)):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+                                  or tuple(t.shape) != (nz, ny, nx) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {(nz, ny, nx)}")
+        rc = lib().mvd_iterate_noalloc(C.byref(m.problem), C.byref(opts),
+                                       None if psi0 is None else C.c_void_p(psi0.data_ptr()), int(n),
+                                       _variant(variant), C.c_void_p(out.data_ptr()))
+    _check(rc)
+    return out
 
 
 class Deconvolver:
