@@ -177,6 +177,42 @@ int mvd_create(mvd_handle** out, const mvd_problem* p, const mvd_options* o);
 int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
                      const mvd_options* o);
 
+/* Block-wise form (main text: the volume is processed in blocks to reduce
+ * the memory requirements; implementation section: blocks are copied out,
+ * deconvolved and pasted back).  One volume of any extents >= 1 (not
+ * limited by the transform lengths, not 5-smooth), taken as one period of a
+ * periodic grid, is cut into near-equal blocks per axis (block k of t along
+ * an axis of n voxels starts at floor(k n / t)).  Every view-update reads,
+ * for each block, the window of the estimate made of the block and `halo`
+ * voxels on each side (wrapping periodically), runs the view-update of
+ * mvd_iterate on that window's grid (the largest block plus twice the halo,
+ * rounded up to a transform length; every block uses the same grid), and
+ * pastes the block's own voxels back; every block of a view-update reads the
+ * estimate from before that view-update.  With halo >= twice the largest
+ * PSF radius per axis the result equals the whole-volume update.
+ *   p      the volume (dims any extents >= 1; views, PSFs and weights as for
+ *          mvd_create; host or device memory)
+ *   tiles  NULL or blocks per axis {tx, ty, tz}, each in [1, extent], or 0
+ *          for the fewest blocks whose grid fits the transform lengths
+ *          (nx <= 2 MVD_MAX_LEN, ny, nz <= MVD_MAX_LEN_YZ)
+ *   halo   NULL (twice the largest odd-padded PSF radius per axis, the
+ *          exact choice) or {hx, hy, hz} >= 0
+ * MVD_EINVAL if a block's grid exceeds the transform lengths.  The handle
+ * runs the sequential scheme (mvd_iterate, mvd_view_update, mvd_profile,
+ * mvd_get_estimate and mvd_set_estimate of the whole volume as block 0,
+ * mvd_stats with the flux of the volume; ratio and negativity clamps are
+ * counted over the block grids); the combined updates, the differentiated
+ * form, mvd_set_psfs and the weight normalisation return MVD_ESTATE.
+ * mvd_grid_dims reports a block's grid; blocks share one set of kernel
+ * planes. */
+int mvd_create_blocked(mvd_handle** out, const mvd_problem* p, const mvd_options* o, const int* tiles,
+                       const int* halo);
+
+/* Blocks per axis, halo and volume extents {x, y, z} of a handle (each may be
+ * NULL): {1, 1, 1}, {0, 0, 0} and the volume for handles that are not
+ * block-wise (block 0's volume for batched handles). */
+int mvd_blocking(const mvd_handle* h, int* tiles, int* halo, int* dims);
+
 /* Run n >= 0 iterations of `variant` (MVD_RL..MVD_OPT2).  Asynchronous.  The
  * compound-kernel spectra of a variant are built on its first use. */
 int mvd_iterate(mvd_handle* h, int n, int variant);

@@ -650,15 +650,16 @@ def view_update_at(psi, phi, P, K, points, w=None, lam_p=0.0, eps=0.0):
     around x, which needs b = psi (x) P on that window, which needs psi on a
     box of both windows.  Same arithmetic as view_update, evaluated locally
     (for volumes too large for the whole-volume oracle)."""
-    psi = np.asarray(psi, dtype=np.float64)
     hk = [(n - 1) // 2 for n in K.shape]
     hp = [(n - 1) // 2 for n in P.shape]
     out = []
     for pt in points:
-        box = _periodic_box(psi, pt, [a + b for a, b in zip(hk, hp)])
+        # windows are taken first and converted to FP64 (the inputs may be
+        # large float32 volumes)
+        box = _periodic_box(psi, pt, [a + b for a, b in zip(hk, hp)]).astype(np.float64)
         # b on K's window around pt: valid convolution of the box with P
         b = signal.fftconvolve(box, P, mode="valid")
-        q = _periodic_box(np.asarray(phi, dtype=np.float64), pt, hk) / np.maximum(b, eps)
+        q = _periodic_box(phi, pt, hk).astype(np.float64) / np.maximum(b, eps)
         # c(pt) = sum_d K[c + d] q(pt - d): q's window is indexed pt + e, so K flips
         c = float(np.sum(K[::-1, ::-1, ::-1] * q))
         p0 = float(psi[tuple(pt)])

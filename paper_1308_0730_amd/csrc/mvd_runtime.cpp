@@ -91,6 +91,25 @@ struct mvd_handle {
   // is created (the no-allocation entry point: one block, direct launches
   // on the caller's stream)
   bool no_alloc = false;
+  // block-wise form: the volume (any extents, one period of a periodic
+  // grid) is cut into near-equal blocks; each block computes on its own grid
+  // (the block plus a halo on both sides, read periodically from the volume
+  // before every view-update) and pastes its own voxels back after it
+  bool blocked = false;
+  struct Tiling {
+    int dims[3] = {0, 0, 0};   // the volume (x, y, z)
+    int tiles[3] = {1, 1, 1};  // blocks per axis
+    int halo[3] = {0, 0, 0};   // grid voxels before a block's first voxel, per axis
+    int64_t V = 0;
+    float* psi = nullptr;      // [V] the estimate
+    Partial* sparts = nullptr; // [nviews][blocks][kScatterWG] FP64 sums of the pasted voxels
+    double* sink_flux = nullptr;  // reduction outputs the block-wise form does not report
+    unsigned long long* sink_cnt = nullptr;
+    std::vector<std::array<int, 3>> origin, extent, start;  // per block; start = (origin - halo) mod dims
+  } tl;
+  static constexpr int kScatterWG = 256;
+  // blocks of one geometry share the kernel planes of one block
+  bool shared_kernels = false;
   // device tables
   JobDesc* d_jobs = nullptr;
   // per pass kind: the job table sorted by (lane, that kind's length), and
@@ -434,7 +453,7 @@ void build_jobs(mvd_handle* h) {
     int64_t load[1 + mvd_handle::kSide] = {};
     for (int i : idx) {
       int best = 0;
-      for (int l = 1; l <= mvd_handle::kSide; ++l)
+      for (int l = 1; l <= mvd_handle::kSide && !h->blocked && !h->no_alloc; ++l)
         if (load[l] < load[best]) best = l;
       h->block_lane[i] = best;
       load[best] += h->blocks[i].V;
@@ -565,12 +584,7 @@ const int* offsets(const Block& B) {
   return d;
 }
 
-void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options* o) {
-  if (nb < 1) bad("n_blocks must be >= 1");
-  if (!ps) bad("problem is NULL");
-  for (int b = 0; b < nb; ++b) validate_shape(&ps[b], b);
-  for (int b = 1; b < nb; ++b)
-    if (ps[b].n_views != ps[0].n_views) bad("every block needs the same number of views");
+void parse_options(mvd_handle* h, const mvd_options* o) {
   if (o) {
     if (!(o->lambda >= 0) || !std::isfinite(o->lambda)) bad("lambda must be finite and >= 0");
     if (!(o->eps_scale >= 0) || !std::isfinite(o->eps_scale)) bad("eps_scale must be finite and >= 0");
@@ -588,6 +602,99 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
       bad("boundary must be MVD_BOUNDARY_CIRCULAR or MVD_BOUNDARY_LINEAR");
     h->linear = o->boundary == MVD_BOUNDARY_LINEAR;
   }
+}
+
+void make_streams(mvd_handle* h, int nb) {
+  HIPCHECK(hipGetDevice(&h->device));
+  if (h->no_alloc) {
+    if (nb != 1) bad("the no-allocation run takes one volume");
+    h->use_graphs = false;
+  } else {
+    HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    for (int i = 0; i < mvd_handle::kSide; ++i) {
+      HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
+    }
+    HIPCHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+  }
+}
+
+// Geometry of a block's grid and its buffers (psi, spectrum, views, weights).
+void alloc_block(mvd_handle* h, Block& B, bool weights) {
+  const int N = h->nviews;
+  B.M = B.nx / 2;
+  B.Mp = (B.M + 15) & ~15;
+  B.V = (int64_t)B.nx * B.ny * B.nz;
+  B.spec_main = (int64_t)B.Mp * B.ny * B.nz;
+  B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
+  B.psi = (float*)h->dalloc(B.V * sizeof(float));
+  B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
+  B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
+  if (weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
+}
+
+// FFT plans and twiddle tables of a block's lengths.
+void add_plans(mvd_handle* h, const Block& B, std::vector<FftPlan>& plans, std::vector<float2>& tw) {
+  plan_for(h, B.M, plans, tw);
+  plan_for(h, B.ny, plans, tw);
+  plan_for(h, B.nz, plans, tw);
+  if (!h->pp_of_nx.count(B.nx)) {
+    h->pp_of_nx[B.nx] = (int)tw.size();
+    const auto t = mvdh::twiddles(B.nx);
+    for (int k = 0; k < B.M; ++k) tw.push_back(make_float2((float)t[k].real(), (float)t[k].imag()));
+  }
+}
+
+// The rest of a create once every block holds its inputs and kernel planes:
+// plans and tables on the device, the job tables, launch shapes and the
+// statistics buffers.
+void finish_create(mvd_handle* h, std::vector<FftPlan>& plans, std::vector<float2>& tw) {
+  const int nb = (int)h->blocks.size(), N = h->nviews;
+  h->d_plans = (FftPlan*)h->dalloc(plans.size() * sizeof(FftPlan));
+  h->d_tw = (float2*)h->dalloc(tw.size() * sizeof(float2));
+  HIPCHECK(hipMemcpyAsync(h->d_plans, plans.data(), plans.size() * sizeof(FftPlan), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, h->stream));
+  h->d_jobs = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
+  for (int k = 0; k < 3; ++k) h->d_jobs_k[k] = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
+
+  int maxM = 0, maxY = 0, maxZ = 0;
+  for (auto& B : h->blocks) {
+    maxM = std::max(maxM, B.M);
+    maxY = std::max(maxY, B.ny);
+    maxZ = std::max(maxZ, B.nz);
+  }
+  build_jobs(h);
+  h->max_len[PASS_X] = maxM;
+  h->max_len[PASS_Y] = maxY;
+  h->max_len[PASS_Z] = maxZ;
+  h->uniform_len[PASS_X] = maxM;
+  h->uniform_len[PASS_Y] = maxY;
+  h->uniform_len[PASS_Z] = maxZ;
+  for (auto& B : h->blocks) {
+    if (B.M != maxM) h->uniform_len[PASS_X] = 0;
+    if (B.ny != maxY) h->uniform_len[PASS_Y] = 0;
+    if (B.nz != maxZ) h->uniform_len[PASS_Z] = 0;
+  }
+  set_tiles(h, pick_cfg(h, PASS_X), pick_cfg(h, PASS_Y), pick_cfg(h, PASS_Z));
+  h->d_flags = (int*)h->dalloc(sizeof(int));
+  h->d_flux = (double*)h->dalloc(N * sizeof(double));
+  h->d_ratio = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+  h->d_neg = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
+  HIPCHECK(hipMemsetAsync(h->d_flux, 0, N * sizeof(double), h->stream));
+  HIPCHECK(hipMemsetAsync(h->d_ratio, 0, N * sizeof(unsigned long long), h->stream));
+  HIPCHECK(hipMemsetAsync(h->d_neg, 0, N * sizeof(unsigned long long), h->stream));
+  HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->spec_valid = false;
+}
+
+void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options* o) {
+  if (nb < 1) bad("n_blocks must be >= 1");
+  if (!ps) bad("problem is NULL");
+  for (int b = 0; b < nb; ++b) validate_shape(&ps[b], b);
+  for (int b = 1; b < nb; ++b)
+    if (ps[b].n_views != ps[0].n_views) bad("every block needs the same number of views");
+  parse_options(h, o);
   h->nviews = ps[0].n_views;
   // host-memory values are checked before any device call
   std::vector<std::vector<mvdh::Kern>> prepared(nb);
@@ -605,18 +712,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     }
   }
 
-  HIPCHECK(hipGetDevice(&h->device));
-  if (h->no_alloc) {
-    if (nb != 1) bad("the no-allocation run takes one volume");
-    h->use_graphs = false;
-  } else {
-    HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    for (int i = 0; i < mvd_handle::kSide; ++i) {
-      HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
-      HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
-    }
-    HIPCHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-  }
+  make_streams(h, nb);
 
   std::vector<FftPlan> plans;
   std::vector<float2> tw;
@@ -644,15 +740,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
       if (B.nx / 2 > MVD_MAX_LEN || B.ny > MVD_MAX_LEN_YZ || B.nz > MVD_MAX_LEN_YZ)
         bad("block " + std::to_string(b) + ": the volume plus its PSF margin exceeds the largest transform length");
     }
-    B.M = B.nx / 2;
-    B.Mp = (B.M + 15) & ~15;
-    B.V = (int64_t)B.nx * B.ny * B.nz;
-    B.spec_main = (int64_t)B.Mp * B.ny * B.nz;
-    B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
-    B.psi = (float*)h->dalloc(B.V * sizeof(float));
-    B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
-    B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
-    if (p.weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
+    alloc_block(h, B, p.weights != nullptr);
     const hipMemcpyKind kind = p.mem_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (!h->linear) {
       for (int v = 0; v < N; ++v) {
@@ -737,58 +825,180 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
     B.kz_cap = B.kz;
     B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.h_elems * 2 * sizeof(float));
     for (int v = 0; v < N; ++v) upload_kernel(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.h_elems * 2);
-    plan_for(h, B.M, plans, tw);
-    plan_for(h, B.ny, plans, tw);
-    plan_for(h, B.nz, plans, tw);
-    if (!h->pp_of_nx.count(B.nx)) {
-      h->pp_of_nx[B.nx] = (int)tw.size();
-      const auto t = mvdh::twiddles(B.nx);
-      for (int k = 0; k < B.M; ++k) tw.push_back(make_float2((float)t[k].real(), (float)t[k].imag()));
-    }
+    add_plans(h, B, plans, tw);
     HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, h->stream));
   }
-  h->d_plans = (FftPlan*)h->dalloc(plans.size() * sizeof(FftPlan));
-  h->d_tw = (float2*)h->dalloc(tw.size() * sizeof(float2));
-  HIPCHECK(hipMemcpyAsync(h->d_plans, plans.data(), plans.size() * sizeof(FftPlan), hipMemcpyHostToDevice, h->stream));
-  HIPCHECK(hipMemcpyAsync(h->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, h->stream));
-  h->d_jobs = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
-  for (int k = 0; k < 3; ++k) h->d_jobs_k[k] = (JobDesc*)h->dalloc(nb * sizeof(JobDesc));
+  finish_create(h, plans, tw);
+}
 
-  int maxM = 0, maxY = 0, maxZ = 0;
-  for (auto& B : h->blocks) {
-    maxM = std::max(maxM, B.M);
-    maxY = std::max(maxY, B.ny);
-    maxZ = std::max(maxZ, B.nz);
+// Block-wise form (main text: processing in blocks to reduce memory; the
+// implementation section's copying and pasting of blocks).  The volume may
+// have any extents: only the blocks' grids are transformed.  Blocks per axis
+// are near-equal (origins k n / t); every block computes on one grid of the
+// largest block plus the halo on both sides, rounded up to a transform
+// length.  A halo of twice the largest PSF radius (the default) leaves the
+// pasted voxels equal to the whole-volume update.
+void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options* o, const int* tiles,
+                         const int* halo) {
+  if (!p) bad("problem is NULL");
+  parse_options(h, o);
+  if (h->linear) bad("the block-wise form runs with the circular boundary");
+  const int N = p->n_views;
+  if (N < 1 || N > MVD_MAX_VIEWS) bad("n_views must be in [1, 64]");
+  if (!p->views || !p->psfs || !p->psf_dims) bad("views, psfs and psf_dims are required");
+  if (p->mem_kind != MVD_MEM_HOST && p->mem_kind != MVD_MEM_DEVICE) bad("mem_kind must be host or device");
+  auto& T = h->tl;
+  for (int a = 0; a < 3; ++a) {
+    T.dims[a] = p->dims[a];
+    if (T.dims[a] < 1) bad("extents must be >= 1");
   }
-  build_jobs(h);
-  h->max_len[PASS_X] = maxM;
-  h->max_len[PASS_Y] = maxY;
-  h->max_len[PASS_Z] = maxZ;
-  h->uniform_len[PASS_X] = maxM;
-  h->uniform_len[PASS_Y] = maxY;
-  h->uniform_len[PASS_Z] = maxZ;
-  for (auto& B : h->blocks) {
-    if (B.M != maxM) h->uniform_len[PASS_X] = 0;
-    if (B.ny != maxY) h->uniform_len[PASS_Y] = 0;
-    if (B.nz != maxZ) h->uniform_len[PASS_Z] = 0;
+  T.V = vox(T.dims);
+  int R[3] = {0, 0, 0}, kmax[3] = {1, 1, 1};
+  for (int v = 0; v < N; ++v) {
+    if (!p->views[v] || !p->psfs[v]) bad("view or PSF pointer " + std::to_string(v) + " is NULL");
+    if (p->weights && !p->weights[v]) bad("weight pointer " + std::to_string(v) + " is NULL");
+    const int* k = p->psf_dims + 3 * v;
+    for (int a = 0; a < 3; ++a) {
+      if (k[a] < 1) bad("PSF extents must be >= 1");
+      R[a] = std::max(R[a], (k[a] | 1) / 2);
+      kmax[a] = std::max(kmax[a], k[a] | 1);
+    }
   }
-  set_tiles(h, pick_cfg(h, PASS_X), pick_cfg(h, PASS_Y), pick_cfg(h, PASS_Z));
-  h->d_flags = (int*)h->dalloc(sizeof(int));
-  h->d_flux = (double*)h->dalloc(N * sizeof(double));
-  h->d_ratio = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
-  h->d_neg = (unsigned long long*)h->dalloc(N * sizeof(unsigned long long));
-  HIPCHECK(hipMemsetAsync(h->d_flux, 0, N * sizeof(double), h->stream));
-  HIPCHECK(hipMemsetAsync(h->d_ratio, 0, N * sizeof(unsigned long long), h->stream));
-  HIPCHECK(hipMemsetAsync(h->d_neg, 0, N * sizeof(unsigned long long), h->stream));
-  HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
-  HIPCHECK(hipStreamSynchronize(h->stream));
-  h->spec_valid = false;
+  const int lim[3] = {2 * MVD_MAX_LEN, MVD_MAX_LEN_YZ, MVD_MAX_LEN_YZ};
+  int G[3];
+  for (int a = 0; a < 3; ++a) {
+    T.halo[a] = halo ? halo[a] : 2 * R[a];
+    if (T.halo[a] < 0) bad("halo must be >= 0");
+    const int n = T.dims[a];
+    auto grid_for = [&](int t) {
+      const int ext = (n + t - 1) / t;
+      const int g = std::max({ext + 2 * T.halo[a], kmax[a], a == 0 ? 4 : 2});
+      return next_smooth5(g, a == 0);
+    };
+    int t = tiles ? tiles[a] : 0;
+    if (t < 0 || t > n) bad("blocks per axis must be in [0, the extent] (0: as few as the transform lengths allow)");
+    if (t == 0) {
+      t = 1;
+      while (t < n && grid_for(t) > lim[a]) ++t;
+    }
+    G[a] = grid_for(t);
+    if (G[a] > lim[a])
+      bad("a block's grid (the block plus the halo on both sides) exceeds the largest transform length along axis " +
+          std::to_string(a) + ": more blocks or a thinner halo");
+    T.tiles[a] = t;
+  }
+  const int nb = T.tiles[0] * T.tiles[1] * T.tiles[2];
+  for (int bz = 0; bz < T.tiles[2]; ++bz)
+    for (int by = 0; by < T.tiles[1]; ++by)
+      for (int bx = 0; bx < T.tiles[0]; ++bx) {
+        const int k[3] = {bx, by, bz};
+        std::array<int, 3> org, ext, st;
+        for (int a = 0; a < 3; ++a) {
+          const int64_t n = T.dims[a], t = T.tiles[a];
+          org[a] = (int)(k[a] * n / t);
+          ext[a] = (int)((k[a] + 1) * n / t) - org[a];
+          st[a] = (int)((((int64_t)org[a] - T.halo[a]) % n + n) % n);
+        }
+        T.origin.push_back(org);
+        T.extent.push_back(ext);
+        T.start.push_back(st);
+      }
+  h->blocked = true;
+  h->shared_kernels = true;
+  h->nviews = N;
+
+  // host values and PSFs before any device call
+  std::vector<mvdh::Kern> prepared;
+  std::vector<double> psf_sum;
+  if (p->mem_kind == MVD_MEM_HOST) validate_host_values(p, 0);
+  make_streams(h, nb);
+  for (int v = 0; v < N; ++v) {
+    const int* k = p->psf_dims + 3 * v;
+    const auto hp = fetch_psf(p, v);
+    try {
+      prepared.push_back(mvdh::prepare_psf(hp.data(), k[0], k[1], k[2]));
+    } catch (const std::invalid_argument& e) {
+      bad("PSF " + std::to_string(v) + ": " + e.what());
+    }
+    double sum = 0;
+    for (float x : hp) sum += x;
+    psf_sum.push_back(sum);
+  }
+
+  T.psi = (float*)h->dalloc(T.V * sizeof(float));
+  h->blocks.resize(nb);
+  for (auto& B : h->blocks) {
+    B.nx = B.ux = G[0];
+    B.ny = B.uy = G[1];
+    B.nz = B.uz = G[2];
+    B.UV = (int64_t)G[0] * G[1] * G[2];
+    alloc_block(h, B, p->weights != nullptr);
+  }
+  // every view and weight volume through the staging estimate buffer (host
+  // inputs) into the windows of every block; s over the volume
+  double total = 0;
+  for (int v = 0; v < N; ++v) {
+    for (int wgt = 0; wgt < (p->weights ? 2 : 1); ++wgt) {
+      const float* src = wgt ? p->weights[v] : p->views[v];
+      if (p->mem_kind == MVD_MEM_HOST) {
+        HIPCHECK(hipMemcpyAsync(T.psi, src, T.V * sizeof(float), hipMemcpyHostToDevice, h->stream));
+        src = T.psi;
+      }
+      double sum;
+      unsigned long long nbad;
+      device_check(h, src, T.V, 0.f, wgt ? 1.f : INFINITY, &sum, &nbad);
+      if (nbad)
+        bad(wgt ? "weights " + std::to_string(v) + " outside [0, 1]"
+                : "view " + std::to_string(v) + " has a negative or non-finite value");
+      if (!wgt) total += sum;
+      for (int b = 0; b < nb; ++b) {
+        Block& B = h->blocks[b];
+        float* dst = (wgt ? B.w : B.phi) + (size_t)v * B.V;
+        HIPCHECK(mvd_launch_gather(dst, grid_dims(B), src, T.dims, T.start[b].data(), h->stream));
+      }
+    }
+  }
+  const double s = total / ((double)N * (double)T.V);
+  if (!(s > 0)) bad("the views are all zero");
+  std::vector<FftPlan> plans;
+  std::vector<float2> tw;
+  for (int b = 0; b < nb; ++b) {
+    Block& B = h->blocks[b];
+    B.s = s;
+    B.eps = (float)(h->eps_scale * s);
+    B.lamp = (float)(h->lambda / s);
+    B.P = prepared;
+    B.psf_sum = psf_sum;
+    for (int v = 0; v < N; ++v) {
+      const int* k = p->psf_dims + 3 * v;
+      B.psf_dims.push_back({k[0], k[1], k[2]});
+    }
+    set_kernel_window(B);
+    B.kz_cap = B.kz;
+    if (b == 0) {
+      B.H[ROLE_P] = (float*)h->dalloc((size_t)N * B.h_elems * 2 * sizeof(float));
+      for (int v = 0; v < N; ++v) upload_kernel(h, B, B.P[v], B.H[ROLE_P] + (size_t)v * B.h_elems * 2);
+    } else {
+      B.H[ROLE_P] = h->blocks[0].H[ROLE_P];
+    }
+    add_plans(h, B, plans, tw);
+  }
+  HIPCHECK(mvd_launch_fill(T.psi, T.V, (float)s, h->stream));
+  T.sparts = (Partial*)h->dalloc((size_t)N * nb * mvd_handle::kScatterWG * sizeof(Partial));
+  HIPCHECK(hipMemsetAsync(T.sparts, 0, (size_t)N * nb * mvd_handle::kScatterWG * sizeof(Partial), h->stream));
+  T.sink_flux = (double*)h->dalloc(N * sizeof(double));
+  T.sink_cnt = (unsigned long long*)h->dalloc(2 * N * sizeof(unsigned long long));
+  finish_create(h, plans, tw);
 }
 
 void ensure_role(mvd_handle* h, int role) {
   if (h->built[role]) return;
   const int variant = role;  // ROLE_EFF == MVD_EFF etc.
   for (auto& B : h->blocks) {
+    if (h->shared_kernels && &B != &h->blocks[0]) {
+      B.H[role] = h->blocks[0].H[role];
+      continue;
+    }
     if (!B.H[role]) B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.h_elems * 2 * sizeof(float));
     for (int v = 0; v < h->nviews; ++v) {
       const mvdh::Kern K = mvdh::compound_kernel(B.P, v, variant);
@@ -902,8 +1112,10 @@ struct PassTimer {
   }
 };
 
-// One view-update of view v: two convolutions and the pointwise steps.
-void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t = nullptr) {
+// One view-update of view v: two convolutions and the pointwise steps;
+// spec_out: the update pass also writes the x-stage spectrum of the new psi
+// (the input of the next view's blur).
+void enqueue_view_passes(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t, bool spec_out) {
   const int role = variant == MVD_RL ? ROLE_P : variant;
   const int conj_back = variant == MVD_RL ? 1 : 0;
   Partial* parts = h->d_parts + (size_t)v * h->grid_x;
@@ -921,7 +1133,28 @@ void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t
   timed(0, [&] { run_y(h, s, 0, v); });
   timed(2, [&] { run_z(h, s, v, role, conj_back, 0); });
   timed(1, [&] { run_y(h, s, 1, v); });
-  timed(4, [&] { run_x(h, s, 2, v, parts, XOPT_SPEC); });
+  timed(4, [&] { run_x(h, s, 2, v, parts, spec_out ? XOPT_SPEC : 0); });
+}
+
+// One view-update; with the block-wise form every block first reads its
+// window of the volume's estimate and transforms it along x, and pastes its
+// own voxels back afterwards (every block reads the estimate before any
+// block writes it: the windows are gathered in one step, in stream order).
+void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t = nullptr) {
+  if (!h->blocked) {
+    enqueue_view_passes(h, s, variant, v, t, true);
+    return;
+  }
+  auto& T = h->tl;
+  const int nb = (int)h->blocks.size();
+  for (int b = 0; b < nb; ++b)
+    HIPCHECK(mvd_launch_gather(h->blocks[b].psi, grid_dims(h->blocks[b]), T.psi, T.dims, T.start[b].data(), s));
+  run_x(h, s, 0, 0, nullptr, XOPT_SPEC);
+  enqueue_view_passes(h, s, variant, v, t, false);
+  for (int b = 0; b < nb; ++b)
+    HIPCHECK(mvd_launch_scatter(T.psi, T.dims, h->blocks[b].psi, grid_dims(h->blocks[b]), T.origin[b].data(),
+                                T.extent[b].data(), T.halo,
+                                T.sparts + ((size_t)v * nb + b) * mvd_handle::kScatterWG, mvd_handle::kScatterWG, s));
 }
 
 // One iteration: every view once, in index order (section 7).  When every
@@ -1003,7 +1236,7 @@ void prepare_run(mvd_handle* h, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   const int role = variant == MVD_RL ? ROLE_P : variant;
   ensure_role(h, role);
-  if (!h->spec_valid) {
+  if (!h->spec_valid && !h->blocked) {
     run_x(h, h->stream, 0, 0, nullptr, XOPT_SPEC);
     h->spec_valid = true;
   }
@@ -1034,6 +1267,19 @@ hipGraphExec_t graph_for(mvd_handle* h, int variant, int scheme = 0) {
   return ex;
 }
 
+// Statistics of the last iteration from the partial results (the flux of the
+// block-wise form from the pasted voxels).
+void reduce_stats(mvd_handle* h, hipStream_t s) {
+  if (!h->blocked) {
+    HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, s));
+    return;
+  }
+  auto& T = h->tl;
+  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, T.sink_flux, h->d_ratio, h->d_neg, s));
+  HIPCHECK(mvd_launch_reduce(T.sparts, (int)h->blocks.size() * mvd_handle::kScatterWG, h->nviews, h->d_flux,
+                             T.sink_cnt, T.sink_cnt + h->nviews, s));
+}
+
 void iterate_impl(mvd_handle* h, int n, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (n < 0) bad("n must be >= 0");
@@ -1045,7 +1291,7 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
   } else {
     for (int i = 0; i < n; ++i) enqueue_iteration(h, h->stream, variant);
   }
-  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, h->stream));
+  reduce_stats(h, h->stream);
   h->iterations += n;
 }
 
@@ -1053,9 +1299,10 @@ void iterate_combined_impl(mvd_handle* h, int n, int variant, int mean) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (mean != MVD_MEAN_GEOMETRIC && mean != MVD_MEAN_ARITHMETIC) bad("mean must be MVD_MEAN_GEOMETRIC or MVD_MEAN_ARITHMETIC");
   if (n < 0) bad("n must be >= 0");
+  if (h->linear) throw Error(MVD_ESTATE, "combined updates run with the circular boundary only");
+  if (h->blocked) throw Error(MVD_ESTATE, "combined updates run on whole volumes only");
   for (const auto& B : h->blocks)
     if (B.w) bad("combined updates take no weights (weights apply to sequential view-updates)");
-  if (h->linear) throw Error(MVD_ESTATE, "combined updates run with the circular boundary only");
   if (n == 0) return;
   prepare_run(h, variant);
   ensure_combined(h);
@@ -1219,6 +1466,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
                     int seed_kind = MVD_MEM_HOST) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "the differentiated form runs with the circular boundary only");
+  if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
   if (variant != MVD_RL) bad("gradients are available for MVD_RL");
   if (n < 0) bad("n must be >= 0");
   if (!seed && !loss) bad("loss is NULL");
@@ -1350,6 +1598,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
 void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "mvd_set_psfs takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "mvd_set_psfs runs with the circular boundary only");
+  if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
   if (!psfs || !psf_dims) bad("psfs and psf_dims are required");
   if (mem_kind != MVD_MEM_HOST && mem_kind != MVD_MEM_DEVICE) bad("mem_kind must be host or device");
   Block& B = h->blocks[0];
@@ -1406,6 +1655,7 @@ void normalize_weights_impl(mvd_handle* h, int mode, double value, double* m_out
   for (const auto& B : h->blocks)
     if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
   if (h->linear) throw Error(MVD_ESTATE, "weight normalisation runs with the circular boundary only");
+  if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
   if (!h->w_cmin) {
     h->w_cmin = (unsigned*)h->dalloc(sizeof(unsigned));
     h->w_cnt = (unsigned long long*)h->dalloc(2 * sizeof(unsigned long long));
@@ -1441,6 +1691,7 @@ void contributing_views_impl(mvd_handle* h, float* dst, int dst_kind, int block)
   const Block& B = h->blocks[block];
   if (!B.w) throw Error(MVD_ESTATE, "the handle was created without weights");
   if (h->linear) throw Error(MVD_ESTATE, "the contributing-view image needs the circular boundary");
+  if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
   if (dst_kind == MVD_MEM_DEVICE) {
     HIPCHECK(mvd_launch_overlap_count(B.w, h->nviews, B.V, dst, h->stream));
   } else {
@@ -1475,7 +1726,11 @@ int get_estimate_impl(mvd_handle* h, float* dst, int dst_kind, int block) {
   const Block& B = block_of(h, block);
   if (!dst) bad("dst is NULL");
   if (dst_kind != MVD_MEM_HOST && dst_kind != MVD_MEM_DEVICE) bad("dst_kind must be host or device");
-  if (!h->linear) {
+  if (h->blocked) {
+    if (block != 0) bad("the block-wise form has one estimate: block 0");
+    HIPCHECK(hipMemcpyAsync(dst, h->tl.psi, h->tl.V * sizeof(float),
+                            dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+  } else if (!h->linear) {
     HIPCHECK(hipMemcpyAsync(dst, B.psi, B.V * sizeof(float),
                             dst_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
   } else {
@@ -1498,6 +1753,25 @@ void set_estimate_impl(mvd_handle* h, const float* src, int src_kind, int block)
   Block& B = const_cast<Block&>(block_of(h, block));
   if (!src) bad("src is NULL");
   if (src_kind != MVD_MEM_HOST && src_kind != MVD_MEM_DEVICE) bad("src_kind must be host or device");
+  if (h->blocked) {
+    if (block != 0) bad("the block-wise form has one estimate: block 0");
+    const int64_t V = h->tl.V;
+    if (src_kind == MVD_MEM_HOST) {
+      for (int64_t i = 0; i < V; ++i)
+        if (!(src[i] >= 0.f) || !std::isfinite(src[i])) bad("estimate has a negative or non-finite value");
+      HIPCHECK(hipMemcpyAsync(h->tl.psi, src, V * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    } else {
+      double s;
+      unsigned long long nb;
+      device_check(h, src, V, 0.f, INFINITY, &s, &nb);
+      if (nb) bad("estimate has a negative or non-finite value");
+      HIPCHECK(hipMemcpyAsync(h->tl.psi, src, V * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    }
+    HIPCHECK(mvd_launch_set_int(h->d_flags, 0, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    h->iterations = 0;
+    return;
+  }
   // with the linear boundary the volume goes into the grid (host data via
   // the factor buffer) and the margin restarts at s
   float* to = B.psi;
@@ -1653,6 +1927,42 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks, 
 
 int mvd_create(mvd_handle** out, const mvd_problem* p, const mvd_options* o) {
   return mvd_create_batch(out, 1, p, o);
+}
+
+int mvd_create_blocked(mvd_handle** out, const mvd_problem* p, const mvd_options* o, const int* tiles,
+                       const int* halo) {
+  if (!out) {
+    g_err = "out is NULL";
+    return MVD_EINVAL;
+  }
+  *out = nullptr;
+  mvd_handle* h = new (std::nothrow) mvd_handle();
+  if (!h) {
+    g_err = "host allocation failed";
+    return MVD_ENOMEM;
+  }
+  const int rc = guard(nullptr, [&] { create_blocked_impl(h, p, o, tiles, halo); });
+  if (rc != MVD_OK) {
+    h->release();
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MVD_OK;
+}
+
+int mvd_blocking(const mvd_handle* h, int* tiles, int* halo, int* dims) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    const Block& B = h->blocks[0];
+    if (tiles) tiles[a] = h->blocked ? h->tl.tiles[a] : 1;
+    if (halo) halo[a] = h->blocked ? h->tl.halo[a] : 0;
+    if (dims) dims[a] = h->blocked ? h->tl.dims[a] : (a == 0 ? B.ux : a == 1 ? B.uy : B.uz);
+  }
+  return MVD_OK;
 }
 
 int mvd_iterate(mvd_handle* h, int n, int variant) {

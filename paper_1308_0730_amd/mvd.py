@@ -91,6 +91,9 @@ def lib():
     L.mvd_compound_kernel.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int, C.c_int,
                                       C.c_void_p, C.POINTER(C.c_int)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
+    L.mvd_create_blocked.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int)]
+    L.mvd_blocking.argtypes = [H, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.mvd_iterate_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Options), C.c_void_p, C.c_int, C.c_int,
                                       C.c_void_p]
     L.mvd_version.restype = C.c_char_p
@@ -100,7 +103,8 @@ def lib():
                  "mvd_set_estimate",
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
-                 "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc"):
+                 "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc",
+                 "mvd_create_blocked", "mvd_blocking"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -207,13 +211,14 @@ class Deconvolver:
 
     Deconvolver(views, psfs, weights=None, lam=0.0)              plain form
     Deconvolver.batch([(views, psfs, weights), ...], lam=0.0)    batched form
+    Deconvolver.blocked(views, psfs, weights, tiles, halo)       block-wise form
 
     Volumes are (nz, ny, nx) float32; PSFs (kz, ky, kx).  Inputs may be numpy
     arrays (copied from host memory) or CUDA tensors (device memory).
     """
 
     def __init__(self, views=None, psfs=None, weights=None, lam=0.0, eps_scale=0.0, use_graphs=True,
-                 tile_config=0, device=None, boundary="circular", _blocks=None):
+                 tile_config=0, device=None, boundary="circular", _blocks=None, _blocking=None):
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
@@ -243,7 +248,13 @@ class Deconvolver:
             ms = [_Marshalled(v, p, w, dev, on_device) for (v, p, w) in blocks]
             arr = (Problem * len(ms))(*[m.problem for m in ms])
             h = C.c_void_p()
-            rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, C.byref(opts))
+            if _blocking is None:
+                rc = lib().mvd_create_batch(C.byref(h), len(ms), arr, C.byref(opts))
+            else:
+                tiles, halo = _blocking
+                t = None if tiles is None else (C.c_int * 3)(*tiles)
+                hl = None if halo is None else (C.c_int * 3)(*halo)
+                rc = lib().mvd_create_blocked(C.byref(h), arr, C.byref(opts), t, hl)
         if rc != MVD_OK:
             self._h = None
             raise MVDError(rc, lib().mvd_last_error(None).decode())
@@ -256,6 +267,20 @@ class Deconvolver:
     @classmethod
     def batch(cls, blocks, **kw):
         return cls(_blocks=[(b[0], b[1], b[2] if len(b) > 2 else None) for b in blocks], **kw)
+
+    @classmethod
+    def blocked(cls, views, psfs, weights=None, tiles=None, halo=None, **kw):
+        """Block-wise form: the volume (any extents) in blocks per axis
+        (x, y, z) (None or 0 on an axis: as few as the transform lengths
+        allow), each with `halo` voxels per side (None: twice the largest PSF
+        radius, the exact choice)."""
+        return cls(views, psfs, weights, _blocking=(tiles, halo), **kw)
+
+    def blocking(self):
+        """(tiles, halo, volume dims), each (x, y, z)."""
+        t, h, d = (C.c_int * 3)(), (C.c_int * 3)(), (C.c_int * 3)()
+        _check(lib().mvd_blocking(self._h, t, h, d), self._h)
+        return tuple(t), tuple(h), tuple(d)
 
     def iterate(self, n, variant="eff"):
         _check(lib().mvd_iterate(self._h, int(n), _variant(variant)), self._h)

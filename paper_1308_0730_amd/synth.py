@@ -275,6 +275,18 @@ def config4(n_blocks=48, dims_override=None):
     return blocks
 
 
+def larva(dims=(1640, 1070, 345), n_blobs=6000, n_views=4):
+    """Block-wise workload at the size of the paper's largest four-view
+    dataset (an L1 larva, 1640x1070x345, four views, Optimization II,
+    lambda 0): blobs filling an ellipsoidal body (radius U[0, 1] of the
+    semi-axes 0.4 dims), views at 90 deg steps about y, 21x21x31 PSFs
+    (sigma_xy 1.0, sigma_z 3.5), Poisson in photon units.  The extents are
+    not 5-smooth and y is beyond one transform: the volume is processed in
+    blocks."""
+    return make_problem(dims, n_blobs, [0.0, 90.0, 180.0, 270.0][:n_views], (21, 21, 31), 1.0, 3.5,
+                        SEED_BASE + 5, variant=3, n_iter=10, shell=(0.0, 1.0))
+
+
 def config5_theta(seed=SEED_BASE + 4):
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
     true = np.tile(np.array([1.2, 4.0]), (4, 1))
