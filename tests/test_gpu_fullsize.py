@@ -111,3 +111,50 @@ def test_batched_blocks_view_update_sampled(mvd):
         e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         print(f"block {i} {b.dims}: sampled view-update rel_l2={e:.3e}")
         assert e <= 1e-5
+
+
+def test_embryo_trajectory(mvd, embryo):
+    """The whole benchmark run (10 iterations of Optimization I over six
+    views, with the overlap weights and lambda) against the FP64 oracle
+    after every iteration: <= 1e-5 after the first, <= 1e-4 after each
+    later one."""
+    s = embryo
+    pb = O.Problem(s.views, s.psfs, s.weights, s.lam)
+    psi = pb.psi0()
+    with mvd.Deconvolver(s.views, s.psfs, s.weights, lam=s.lam) as d:
+        print("launch shapes", tuned(d, O.OPT1), flush=True)
+        for it in range(s.n_iter):
+            psi = pb.iterate(psi, 1, O.OPT1)
+            d.iterate(1, O.OPT1)
+            e = O.rel_l2(d.estimate().cpu().numpy().astype(np.float64), psi)
+            print(f"iteration {it + 1}: rel_l2={e:.3e}", flush=True)
+            assert e <= (1e-5 if it == 0 else 1e-4), (it, e)
+
+
+# batched blocks covering the length classes of the column passes (y and z
+# up to 128 and up to 256), odd and even half-rows (75, 125) and the longest
+# half-row (128)
+BATCH_CHECKED = [6, 12, 11, 42, 0, 47]
+
+
+def test_batched_trajectory(mvd):
+    """All 48 blocks of the batched workload at their full sizes in one
+    handle, in the launch shapes the benchmark times (autotuned), 10
+    iterations of the efficient update; six blocks that span the column
+    passes' length classes and the half-row lengths are checked against the
+    FP64 oracle after every iteration (<= 1e-5 after the first, <= 1e-4
+    after each later one)."""
+    blocks = synth.config4()
+    pbs = {i: O.Problem(blocks[i].views, blocks[i].psfs) for i in BATCH_CHECKED}
+    psis = {i: pb.psi0() for i, pb in pbs.items()}
+    with mvd.Deconvolver.batch([(b.views, b.psfs, b.weights) for b in blocks]) as d:
+        print("launch shapes", tuned(d, O.EFF), flush=True)
+        for it in range(10):
+            d.iterate(1, O.EFF)
+            worst = 0.0
+            for i, pb in pbs.items():
+                psis[i] = pb.iterate(psis[i], 1, O.EFF)
+                e = O.rel_l2(d.estimate(i).cpu().numpy().astype(np.float64), psis[i])
+                worst = max(worst, e)
+                assert e <= (1e-5 if it == 0 else 1e-4), (it, i, blocks[i].dims, e)
+            print(f"iteration {it + 1}: worst rel_l2 over blocks {BATCH_CHECKED} = {worst:.3e}", flush=True)

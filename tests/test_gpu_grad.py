@@ -1,6 +1,10 @@
 """Differentiated form on the GPU: loss and gradients through the unrolled
 sequential RL run (hand-written adjoint passes) against the FP64 oracle
-gradient, and the PSF-parameter gradient against finite differences."""
+gradient, and the PSF-parameter gradient against finite differences.
+
+Tolerances (relative L2 against the FP64 oracle gradient): GRAD = 5e-5 on
+the small cases, where the measured errors are 1e-7 to 6e-6 (an order of
+magnitude of margin, half the 1e-4 target); 1e-4 at the 128^3 workload."""
 import numpy as np
 import pytest
 import torch
@@ -32,6 +36,9 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
+GRAD = 5e-5
+
+
 @pytest.mark.parametrize("weighted,lam,dims", [(False, 0.0, (40, 36, 30)), (True, 0.02, (40, 36, 30)),
                                                (True, 0.02, (64, 20, 24))])
 def test_gradient_matches_oracle(mvd, weighted, lam, dims):
@@ -49,9 +56,9 @@ def test_gradient_matches_oracle(mvd, weighted, lam, dims):
     print(f"loss {l2:.8e} vs {L:.8e}; psi0 grad rel {rel(gpsi2, gpsi):.2e}; "
           f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gp2, gP)]}")
     assert abs(l2 - L) <= 1e-5 * L
-    assert rel(gpsi2, gpsi) <= 2e-4
+    assert rel(gpsi2, gpsi) <= GRAD
     for a, b in zip(gp2, gP):
-        assert rel(a, b) <= 2e-4
+        assert rel(a, b) <= GRAD
 
 
 def grad_case(weighted, seed=5, dims=(40, 36, 30)):
@@ -86,9 +93,9 @@ def test_backward_matches_oracle_vjp(mvd, weighted, lam, dims):
           f"psi_n rel {rel(e, psi_n):.2e}")
     assert none is None
     assert rel(e, psi_n) <= 1e-5
-    assert rel(gpsi2, gpsi) <= 2e-4
+    assert rel(gpsi2, gpsi) <= GRAD
     for a, b, c in zip(gp2, gP, gp3):
-        assert rel(a, b) <= 2e-4
+        assert rel(a, b) <= GRAD
         assert np.array_equal(a, c)
 
 
@@ -111,10 +118,10 @@ def test_deconvolve_layer_under_a_torch_loss(mvd):
         gbar = (2.0 * (out.detach() - truth) * mask).cpu().numpy().astype(np.float64)
     psi_n, gpsi, gP = O.vjp(s.views, psfs, n, psi0.astype(np.float64), gbar)
     assert rel(out.detach().cpu().numpy(), psi_n) <= 1e-5
-    assert rel(p0.grad.cpu().numpy(), gpsi) <= 2e-4
+    assert rel(p0.grad.cpu().numpy(), gpsi) <= GRAD
     for a, b in zip(ps, gP):
         assert a.grad.dtype == torch.float64
-        assert rel(a.grad.numpy(), b) <= 2e-4
+        assert rel(a.grad.numpy(), b) <= GRAD
 
 
 def test_forward_only_loss(mvd):
@@ -170,6 +177,6 @@ def test_config5_theta_gradient(mvd):
     print(f"loss {L2:.8e} vs {Lo:.8e}; psi0 grad rel {rel(gpsi2, gpsio):.2e}; "
           f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gP2, gPo)]}")
     assert abs(L - Lo) <= 1e-4 * Lo and abs(L2 - Lo) <= 1e-4 * Lo
-    assert rel(gpsi2, gpsio) <= 1e-3
+    assert rel(gpsi2, gpsio) <= 1e-4
     for a, b in zip(gP2, gPo):
-        assert rel(a, b) <= 1e-3
+        assert rel(a, b) <= 1e-4
