@@ -131,9 +131,10 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(blocks, meta, budget_s=25.0):
-    """The FP64 oracle on this host: view-updates of the same workload until
-    about budget_s of work, scaled to voxel-view updates per second."""
+def cpu_baseline(blocks, meta, budget_s=60.0):
+    """The FP64 oracle on this host: the view-updates of the same workload
+    (the whole run, or as many as fit in about budget_s), scaled to
+    voxel-view updates per second."""
     from oracle import mvd_oracle as O
     s = blocks[0]
     pb = O.Problem(s.views, s.psfs, s.weights, meta["lam"])
@@ -153,8 +154,8 @@ def cpu_baseline(blocks, meta, budget_s=25.0):
             break
     return {"value": V * n / el / 1e9, "unit": "Gvox/s", "cores": os.cpu_count(), "cpu_model": cpu_model(),
             "kind": "oracle",
-            "sample": f"{n} view-update(s) of block 0 of the same workload in FP64 (scipy.fft, all host cores), "
-                      f"{el:.1f} s"}
+            "sample": f"{n} of the run's {pb.n * meta['iterations']} view-updates of block 0 of the same "
+                      f"workload in FP64 (scipy.fft, all host cores), {el:.1f} s"}
 
 
 def batched_form(steps, warmup):
@@ -170,18 +171,31 @@ def batched_form(steps, warmup):
     vox = sum(int(np.prod(b.dims)) for b in blocks) * len(blocks[0].views) * its
     b = mvd.Deconvolver.batch([(x.views, x.psfs, x.weights) for x in blocks])
     b.iterate(1, var)
-    tune.autotune(b, var, iters=1, cache_path=None)
+    tune.autotune(b, var, iters=1, cache_path=None, runs=its)
     for _ in range(warmup):
         b.iterate(its, var)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(b.stream)
     for _ in range(steps):
         b.iterate(its, var)
-    e1.record()
+    e1.record(b.stream)
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1) / steps
     tiles = b.tiles()
+    schedule = b.schedule()
+    # roofline of the dominant pass kind: every launch of that pass over all
+    # blocks (one pass-major iteration, HIP events around each pass)
+    prof = b.profile(1, var)
+    by = pass_bytes(blocks, False)
+    total = {k: prof[k][0] * prof[k][1] for k in PASS_NAMES}
+    dom = max(total, key=total.get)
+    ach = by[dom] / (prof[dom][0] / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("batched48", dom), "kernel": dom,
+            "bytes_per_launch": by[dom], "avg_launch_ms": round(prof[dom][0], 5),
+            "note": "one pass over all 48 blocks (its launches per lane and length) timed as one launch"}
+    run_bytes = sum(by[k] * prof[k][1] for k in PASS_NAMES) * its  # the profile ran one iteration
     b.close()
     del b
     plains = [mvd.Deconvolver(x.views, x.psfs, x.weights) for x in blocks]
@@ -203,7 +217,9 @@ def batched_form(steps, warmup):
         d.close()
     return {"workload": meta["workload"], "blocks": len(blocks), "voxel_view_updates_per_step": vox,
             "batched": {"ms_per_step": round(ms_b, 3), "value": round(vox / ms_b / 1e6, 3), "unit": "Gvox/s",
-                        "tiles": list(tiles)},
+                        "tiles": list(tiles), "schedule": schedule,
+                        "algorithmic_GBps": round(run_bytes / (ms_b / 1e3) / 1e9, 1)},
+            "roofline": roof,
             "plain_loop": {"ms_per_step": round(ms_p, 3), "value": round(vox / ms_p / 1e6, 3), "unit": "Gvox/s"},
             "batched_speedup": round(ms_p / ms_b, 3)}
 
@@ -219,19 +235,23 @@ def grad_form(steps, warmup):
     vox = int(np.prod(s.dims)) * len(s.views) * its
     d = mvd.Deconvolver(s.views, s.psfs)
     res = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for name, grads in (("forward", False), ("forward_backward", True)):
         for _ in range(warmup):
             d.loss_grad(its, None, grad_psf=grads, grad_psi0=grads)
-        t0 = time.perf_counter()
+        e0.record(d.stream)
         for _ in range(steps):
             loss, _, _ = d.loss_grad(its, None, grad_psf=grads, grad_psi0=grads)
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        e1.record(d.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
         res[name] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3), "unit": "Gvox/s",
                      "loss": loss}
     d.close()
     res["backward_over_forward"] = round(res["forward_backward"]["ms_per_step"] / res["forward"]["ms_per_step"], 3)
     res["workload"] = "128^3, 4 views, 25^3 PSFs, 8 RL iterations, loss sum_v |psi_8 (x) P_v - phi_v|^2"
-    res["note"] = "host wall clock per call (each call synchronises; the PSF gradients' normalisation Jacobian runs on the host)"
+    res["note"] = ("HIP events on the handle's stream around the calls (each call synchronises; the PSF "
+                   "gradients' normalisation Jacobian runs on the host between device work)")
     return res
 
 
@@ -260,7 +280,7 @@ def linear_form(steps, warmup):
     print(f"[bench] linear workload generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     its, var, n = 10, "opt1", len(s.views)
     with mvd.Deconvolver(s.views, s.psfs, s.weights, lam=0.0006, boundary="linear") as d:
-        d.iterate(1, var)  # sensitivities, compound kernels, graph
+        d.iterate(1, var)  # compound kernels, graph
         tune.autotune(d, var, iters=1, cache_path=None)
         for _ in range(warmup):
             d.iterate(its, var)
@@ -279,6 +299,75 @@ def linear_form(steps, warmup):
                         "lambda 0.0006, Optimization I, 10 iterations",
             "grid": list(grid), "ms_per_step": round(ms, 3), "value": round(vox / (ms / 1e3) / 1e9, 3),
             "unit": "Gvox/s", "grid_value": round(gvox / (ms / 1e3) / 1e9, 3)}
+
+
+def small_form(steps, warmup):
+    """The two small plain workloads (cache-resident; the 64^3 one is
+    launch-bound): 64^3 with two views, 5 iterations of the efficient update,
+    and 128^3 with four views, 20 iterations."""
+    import torch
+    from paper_1308_0730_amd import mvd, tune
+    out = {}
+    for cfg, name in ((1, "tiny64"), (2, "cube128")):
+        blocks, meta = workload(cfg)
+        s = blocks[0]
+        its, var = meta["iterations"], meta["variant"]
+        with mvd.Deconvolver(s.views, s.psfs, s.weights, lam=meta["lam"]) as d:
+            d.iterate(1, var)
+            tune.autotune(d, var, iters=2, cache_path=None)
+            for _ in range(warmup):
+                d.iterate(its, var)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(d.stream)
+            for _ in range(steps):
+                d.iterate(its, var)
+            e1.record(d.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            vox = int(np.prod(s.dims)) * len(s.views) * its
+            out[name] = {"workload": meta["workload"], "ms_per_step": round(ms, 4),
+                         "value": round(vox / (ms / 1e3) / 1e9, 3), "unit": "Gvox/s",
+                         "us_per_view_update": round(ms * 1e3 / (len(s.views) * its), 2), "tiles": list(d.tiles())}
+    return out
+
+
+def blocked_form(steps, warmup):
+    """The block-wise form at the size of the paper's largest four-view
+    dataset: 1640x1070x345 (an L1 larva), four views at 90 deg, 21x21x31
+    PSFs, Optimization II, lambda 0, 10 iterations; the volume is not a
+    transform length along any axis and y is beyond one, so it runs as two
+    1728x576x405 blocks with a halo of twice the PSF radius.  value counts
+    the volume's voxels, grid_value the block grids'."""
+    import torch
+    from paper_1308_0730_amd import mvd, synth, tune
+    t0 = time.time()
+    s = synth.larva()
+    print(f"[bench] block-wise workload generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    its, var, n = 10, "opt2", len(s.views)
+    dev = [torch.from_numpy(v).cuda() for v in s.views]
+    with mvd.Deconvolver.blocked(dev, s.psfs) as d:
+        del dev
+        d.iterate(1, var)
+        tune.autotune(d, var, iters=1, cache_path=None)
+        for _ in range(warmup):
+            d.iterate(its, var)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(d.stream)
+        for _ in range(steps):
+            d.iterate(its, var)
+        e1.record(d.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tiles, halo, dims = d.blocking()
+        grid = d.grid_dims(0)
+        nb = tiles[0] * tiles[1] * tiles[2]
+    vox = int(np.prod(s.dims)) * n * its
+    gvox = int(np.prod(grid)) * nb * n * its
+    return {"workload": "block-wise: 1640x1070x345, 4 views at 90 deg, 21x21x31 PSFs, Optimization II, "
+                        "lambda 0, 10 iterations",
+            "blocks": list(tiles), "halo": list(halo), "grid": list(grid), "ms_per_step": round(ms, 3),
+            "value": round(vox / (ms / 1e3) / 1e9, 3), "unit": "Gvox/s",
+            "grid_value": round(gvox / (ms / 1e3) / 1e9, 3)}
 
 
 def spim_form():
@@ -330,12 +419,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--cpu-budget", type=float, default=60.0)
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched (48 blocks, against the plain form looped over them), the "
+                    help="skip the batched (48 blocks, against the plain form looped over them), the small "
+                         "plain workloads (64^3, 128^3), the block-wise (1640x1070x345), the "
                          "differentiated (forward against forward + backward), the convergence "
                          "(every scheme x variant to one distance from the ground truth), the "
                          "linear-boundary, the simulated-SPIM and the PSF-refinement measurements")
@@ -376,7 +466,7 @@ def main():
         d.set_tiles(*[int(x) for x in args.tiles.split(",")])
     elif not args.no_tune:
         from paper_1308_0730_amd import tune
-        tune.autotune(d, meta["variant"], iters=1, cache_path=None, verbose=True)
+        tune.autotune(d, meta["variant"], iters=1, cache_path=None, verbose=True, runs=meta["iterations"])
     tiles = d.tiles()
     launch = {}
     for i, (k, c) in enumerate(zip(("x", "y", "z"), tiles)):
@@ -434,6 +524,8 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("batched", lambda: batched_form(max(1, args.steps // 2), 1)),
+                         ("small", lambda: small_form(max(3, args.steps), 1)),
+                         ("blocked", lambda: blocked_form(max(1, args.steps // 2), 1)),
                          ("grad", lambda: grad_form(3, 1)), ("convergence", convergence_form),
                          ("linear", lambda: linear_form(max(1, args.steps // 2), 1)),
                          ("spim", spim_form), ("psf_refine", psf_refine_form)):

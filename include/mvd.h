@@ -294,6 +294,28 @@ int mvd_tile_shape(int kind, int cfg, int* threads, int* per_tile, int* max_len,
 int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z);
 int mvd_get_tiles(const mvd_handle* h, int* cfg);
 
+/* Schedule of a multi-block handle's runs (the autotuner's other knob).
+ * Blocks are independent, so every schedule gives the same results; they
+ * differ in what the memory-side cache holds between passes.
+ *   MVD_SCHEDULE_PASS_MAJOR  each pass covers every block of a stream lane
+ *                            (one launch per lane and length or length
+ *                            class), one graph per iteration (the default)
+ *   MVD_SCHEDULE_BLOCK_MAJOR each lane takes its blocks one at a time: a
+ *                            block's view-updates of an iteration, then the
+ *                            next block
+ *   MVD_SCHEDULE_RUN_MAJOR   each lane takes its blocks one at a time for
+ *                            the whole run: all n iterations of a block,
+ *                            then the next; one graph per run
+ * The block-major schedules take effect with the per-length plans for all
+ * three pass kinds and two or more blocks (otherwise runs are pass-major);
+ * mvd_profile always runs pass-major.  mvd_get_schedule returns the
+ * current one. */
+#define MVD_SCHEDULE_PASS_MAJOR 0
+#define MVD_SCHEDULE_BLOCK_MAJOR 1
+#define MVD_SCHEDULE_RUN_MAJOR 2
+int mvd_set_schedule(mvd_handle* h, int schedule);
+int mvd_get_schedule(const mvd_handle* h);
+
 /* Overlap numbers for mvd_normalize_weights (section on partially
  * overlapping data). */
 #define MVD_OVERLAP_ONE 0  /* 1: the safe choice */

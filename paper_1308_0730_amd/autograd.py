@@ -29,15 +29,17 @@ class MVDLoss(torch.autograd.Function):
         want_p = any(ctx.needs_input_grad[3:])
         want_psi = ctx.needs_input_grad[2]
         loss, gp, gpsi = handle.loss_grad(n_iter, psi0, grad_psf=want_p, grad_psi0=want_psi)
-        ctx.gp = None if gp is None else [torch.from_numpy(g).to(p.dtype) for g, p in zip(gp, psfs)]
-        ctx.gpsi = gpsi
+        # gradients come back on the device and in the dtype of each input
+        ctx.gp = None if gp is None else [torch.from_numpy(g).to(dtype=p.dtype, device=p.device)
+                                          for g, p in zip(gp, psfs)]
+        ctx.gpsi = None if gpsi is None else gpsi.to(dtype=psi0.dtype, device=psi0.device)
         return torch.tensor(loss, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, gout):
-        gpsi = None if ctx.gpsi is None else (ctx.gpsi * float(gout)).to(torch.float32)
+        gpsi = None if ctx.gpsi is None else ctx.gpsi * gout.to(ctx.gpsi.device)
         n_psf = len(ctx.needs_input_grad) - 3
-        gps = (None,) * n_psf if ctx.gp is None else tuple(gout * g for g in ctx.gp)
+        gps = (None,) * n_psf if ctx.gp is None else tuple(g * gout.to(g.device) for g in ctx.gp)
         return (None, None, gpsi) + gps
 
 
@@ -52,7 +54,8 @@ class MVDDeconvolve(torch.autograd.Function):
         ctx.handle, ctx.n_iter, ctx.host = handle, int(n_iter), host
         ctx.psi0 = psi0.detach()
         ctx.meta = [(p.dtype, p.device) for p in psfs]
-        return out
+        ctx.psi_meta = (psi0.dtype, psi0.device)
+        return out.to(dtype=psi0.dtype, device=psi0.device)
 
     @staticmethod
     def backward(ctx, gout):
@@ -64,7 +67,7 @@ class MVDDeconvolve(torch.autograd.Function):
         gps = (None,) * len(ctx.meta) if gp is None else \
             tuple(torch.from_numpy(g).to(dtype=dt, device=dev) for g, (dt, dev) in zip(gp, ctx.meta))
         if gpsi is not None:
-            gpsi = gpsi.to(ctx.psi0.dtype)
+            gpsi = gpsi.to(dtype=ctx.psi_meta[0], device=ctx.psi_meta[1])
         return (None, None, gpsi) + gps
 
 

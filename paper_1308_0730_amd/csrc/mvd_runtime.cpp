@@ -134,6 +134,14 @@ struct mvd_handle {
   JobDesc* d_jobs_k[3] = {nullptr, nullptr, nullptr};
   std::vector<int> order[3];
   std::vector<Group> groups[3];
+  // per pass kind and block: the one-block group of that block in the
+  // sorted job order (the block-major schedules), set with the per-length
+  // plans of all three kinds
+  std::vector<Group> bgroups[3];
+  // MVD_SCHEDULE_*: the order in which a multi-block handle's lanes take the
+  // passes of a run, and the graphs of whole runs (key: variant, n)
+  int schedule = 0;
+  std::map<std::pair<int, int>, hipGraphExec_t> run_exec;
   FftPlan* d_plans = nullptr;
   float2* d_tw = nullptr;
   Partial* d_parts = nullptr;
@@ -210,6 +218,8 @@ struct mvd_handle {
         (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
+    for (auto& kv : run_exec) (void)hipGraphExecDestroy(kv.second);
+    run_exec.clear();
     if (cap) (void)hipDeviceSynchronize();
     for (void* p : allocs) {
       if (alloc && free_fn)
@@ -475,6 +485,21 @@ void build_jobs(mvd_handle* h) {
   HIPCHECK(hipStreamSynchronize(h->stream));
 }
 
+// Drop every cached graph (launch shapes, kernel spectra or the schedule
+// changed).
+void drop_graphs(mvd_handle* h) {
+  bool any = false;
+  for (auto& g : h->exec) any |= g != nullptr;
+  if (any || !h->run_exec.empty()) HIPCHECK(hipStreamSynchronize(h->stream));
+  for (auto& g : h->exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  for (auto& kv : h->run_exec) (void)hipGraphExecDestroy(kv.second);
+  h->run_exec.clear();
+}
+
 // Select the launch shapes of the three pass kinds; recomputes the grids,
 // grows the partials buffer and drops the cached graphs.
 bool cfg_fits(const mvd_handle* h, int kind, int c) {
@@ -531,18 +556,27 @@ void set_tiles(mvd_handle* h, int cx, int cy, int cz) {
     if (tiles > 0x7fffffff) bad("too many tiles");
     g[k] = (int)tiles;
   }
+  for (int k = 0; k < 3; ++k) {
+    h->bgroups[k].clear();
+    if (c[k] != mvd_exact_cfg(k)) continue;
+    h->bgroups[k].resize(h->blocks.size());
+    int64_t off = 0;
+    const auto& ord = h->order[k];
+    for (size_t i = 0; i < ord.size(); ++i) {
+      const int b = ord[i];
+      const int len = job_len(h->blocks[b], k);
+      const int t = mvd_tiles(h->jobs[b], k, mvd_exact_param(k, len));
+      h->bgroups[k][b] = mvd_handle::Group{len, (int)i, 1, t, (int)off, h->block_lane[b], -1};
+      off += t;
+    }
+  }
   const int gx = g[0], gy = g[1], gz = g[2];
   if ((size_t)h->nviews * gx > h->parts_cap) {
     h->d_parts = (Partial*)h->dalloc((size_t)h->nviews * gx * sizeof(Partial));
     h->parts_cap = (size_t)h->nviews * gx;
     HIPCHECK(hipMemsetAsync(h->d_parts, 0, h->parts_cap * sizeof(Partial), h->stream));
   }
-  for (auto& g : h->exec)
-    if (g) {
-      HIPCHECK(hipStreamSynchronize(h->stream));
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  drop_graphs(h);
   h->cfg_x = cx;
   h->cfg_y = cy;
   h->cfg_z = cz;
@@ -1187,6 +1221,71 @@ void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t =
   }
 }
 
+// One view-update of block b alone on stream s (the block-major schedules):
+// every pass launches the per-length plan over that block only.
+void enqueue_view_block(mvd_handle* h, hipStream_t s, int variant, int v, int b) {
+  const int role = variant == MVD_RL ? ROLE_P : variant;
+  const int conj_back = variant == MVD_RL ? 1 : 0;
+  Partial* parts = h->d_parts + (size_t)v * h->grid_x;
+  const auto& gx = h->bgroups[PASS_X][b];
+  const auto& gy = h->bgroups[PASS_Y][b];
+  const auto& gz = h->bgroups[PASS_Z][b];
+  auto y = [&](int inv) { HIPCHECK(mvd_launch_y_exact(group_args(h, s, PASS_Y, gy), gy.len, inv, v)); };
+  auto z = [&](int r, int cj) {
+    HIPCHECK(mvd_launch_z_exact(group_args(h, s, PASS_Z, gz), gz.len, v, r, cj, 0));
+  };
+  auto x = [&](int mode) {
+    HIPCHECK(mvd_launch_x_exact(group_args(h, s, PASS_X, gx), gx.len, mode, v, parts + gx.part_off, h->d_flags,
+                                XOPT_SPEC));
+  };
+  y(0);
+  z(ROLE_P, 0);
+  y(1);
+  x(1);
+  y(0);
+  z(role, conj_back);
+  y(1);
+  x(2);
+}
+
+bool block_major(const mvd_handle* h) {
+  if (h->schedule == MVD_SCHEDULE_PASS_MAJOR || h->blocks.size() < 2 || h->blocked || h->no_alloc) return false;
+  for (int k = 0; k < 3; ++k)
+    if (h->bgroups[k].size() != h->blocks.size()) return false;
+  return true;
+}
+
+// n iterations with a block-major schedule: every lane's stream takes its
+// blocks one at a time (MVD_SCHEDULE_BLOCK_MAJOR: each block's view-updates
+// of one iteration, then the next block; MVD_SCHEDULE_RUN_MAJOR: all n
+// iterations of a block, then the next), so the few blocks in flight, one
+// per lane, keep their spectra, views and estimates in the memory-side
+// cache from pass to pass.  Blocks are independent, so any such order gives
+// the same results; the lanes are forked once and joined at the end.
+void enqueue_run_blocks(mvd_handle* h, hipStream_t s, int variant, int n) {
+  HIPCHECK(hipEventRecord(h->ev_fork, s));
+  for (int l = 0; l < mvd_handle::kSide; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
+  for (int l = 0; l <= mvd_handle::kSide; ++l) {
+    hipStream_t sl = l ? h->side[l - 1] : s;
+    std::vector<int> mine;
+    for (int b = 0; b < (int)h->blocks.size(); ++b)
+      if (h->block_lane[b] == l) mine.push_back(b);
+    if (h->schedule == MVD_SCHEDULE_RUN_MAJOR) {
+      for (int b : mine)
+        for (int i = 0; i < n; ++i)
+          for (int v = 0; v < h->nviews; ++v) enqueue_view_block(h, sl, variant, v, b);
+    } else {
+      for (int i = 0; i < n; ++i)
+        for (int b : mine)
+          for (int v = 0; v < h->nviews; ++v) enqueue_view_block(h, sl, variant, v, b);
+    }
+  }
+  for (int l = 0; l < mvd_handle::kSide; ++l) {
+    HIPCHECK(hipEventRecord(h->ev_join[l], h->side[l]));
+    HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l], 0));
+  }
+}
+
 // One combined update (eq. 51): every view's back-projected ratio is taken
 // from the same psi.  The x/y-stage spectrum of psi is computed once and
 // saved; per view the blur's z pass reads it, the ratio and the
@@ -1280,12 +1379,47 @@ void reduce_stats(mvd_handle* h, hipStream_t s) {
                              T.sink_cnt, T.sink_cnt + h->nviews, s));
 }
 
+// The graph of a whole block-major run of n iterations (one launch per run).
+hipGraphExec_t run_graph_for(mvd_handle* h, int variant, int n) {
+  const auto key = std::make_pair(variant, n);
+  auto it = h->run_exec.find(key);
+  if (it != h->run_exec.end()) return it->second;
+  hipGraph_t g = nullptr;
+  HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue_run_blocks(h, h->cap, variant, n);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(h->cap, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHECK(e);
+  // a few run lengths are kept (a caller stepping through n = 1, 2, ...
+  // would otherwise grow the cache without bound)
+  if (h->run_exec.size() >= 4) {
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    for (auto& kv : h->run_exec) (void)hipGraphExecDestroy(kv.second);
+    h->run_exec.clear();
+  }
+  h->run_exec[key] = ex;
+  return ex;
+}
+
 void iterate_impl(mvd_handle* h, int n, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (n < 0) bad("n must be >= 0");
   if (n == 0) return;
   prepare_run(h, variant);
-  if (h->use_graphs) {
+  if (block_major(h)) {
+    if (h->use_graphs)
+      HIPCHECK(hipGraphLaunch(run_graph_for(h, variant, n), h->stream));
+    else
+      enqueue_run_blocks(h, h->stream, variant, n);
+  } else if (h->use_graphs) {
     hipGraphExec_t ex = graph_for(h, variant);
     for (int i = 0; i < n; ++i) HIPCHECK(hipGraphLaunch(ex, h->stream));
   } else {
@@ -2163,6 +2297,20 @@ int mvd_set_tiles(mvd_handle* h, int cfg_x, int cfg_y, int cfg_z) {
   }
   return guard(h, [&] { set_tiles(h, cfg_x, cfg_y, cfg_z); });
 }
+
+int mvd_set_schedule(mvd_handle* h, int schedule) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (schedule < MVD_SCHEDULE_PASS_MAJOR || schedule > MVD_SCHEDULE_RUN_MAJOR) bad("unknown schedule");
+    if (schedule != h->schedule) drop_graphs(h);
+    h->schedule = schedule;
+  });
+}
+
+int mvd_get_schedule(const mvd_handle* h) { return h ? h->schedule : MVD_EINVAL; }
 
 int mvd_get_tiles(const mvd_handle* h, int* cfg) {
   if (!h || !cfg) {

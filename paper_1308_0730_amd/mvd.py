@@ -93,6 +93,8 @@ def lib():
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_create_blocked.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]
+    L.mvd_set_schedule.argtypes = [H, C.c_int]
+    L.mvd_get_schedule.argtypes = [H]
     L.mvd_blocking.argtypes = [H, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.mvd_iterate_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Options), C.c_void_p, C.c_int, C.c_int,
                                       C.c_void_p]
@@ -104,7 +106,7 @@ def lib():
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
                  "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc",
-                 "mvd_create_blocked", "mvd_blocking"):
+                 "mvd_create_blocked", "mvd_blocking", "mvd_set_schedule", "mvd_get_schedule"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -379,6 +381,19 @@ class Deconvolver:
             gp_ptrs = (C.c_void_p * len(gps))(*[x.ctypes.data for x in gps])
         gpsi = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if grad_psi0 else None
         return src, gps, gp_ptrs, gpsi
+
+    SCHEDULES = {"pass": 0, "block": 1, "run": 2}
+
+    def set_schedule(self, schedule):
+        """'pass' (each pass over every block of a lane), 'block' (a lane's
+        blocks one at a time per iteration) or 'run' (a lane's blocks one at
+        a time for the whole run); same results, different cache use."""
+        sch = self.SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        _check(lib().mvd_set_schedule(self._h, sch), self._h)
+        return self
+
+    def schedule(self):
+        return {v: k for k, v in self.SCHEDULES.items()}[lib().mvd_get_schedule(self._h)]
 
     def tiles(self):
         """Current launch-shape candidates (x, y, z)."""

@@ -4,11 +4,13 @@ For each pass kind (x rows, y columns, z columns) every launch-shape
 candidate that holds the handle's longest transform is timed with the
 library's per-launch HIP-event profiler, one kind at a time with the other
 two held at their current choice; the fastest stays selected.  A handle of
-several blocks then times whole iterations with that choice against the
-per-length plans for all three kinds, which alone let each block lane run
-its view-updates without joining the other lanes after every pass (a gain
-the per-pass profile cannot see), and keeps the faster.  The estimates are
-restored afterwards.  Results are cached in a JSON file keyed by GPU
+several blocks then times whole runs (`runs` iterations) with that choice
+against the per-length plans for all three kinds under each schedule (pass
+major, block major, run major: with the per-length plans each block lane
+runs its blocks without joining the other lanes after every pass, and the
+block-major schedules keep a few blocks in the memory-side cache from pass
+to pass, gains the per-pass profile cannot see), and keeps the fastest.
+The estimates are restored afterwards.  Results are cached in a JSON file keyed by GPU
 architecture, volume dims, view count and variant.
 """
 from __future__ import annotations
@@ -38,14 +40,17 @@ def _load(path):
         return {}
 
 
-def autotune(d, variant="eff", iters=1, cache_path=DEFAULT_CACHE, use_cache=True, verbose=False):
-    """Select the fastest launch shapes for handle d; returns (x, y, z) and
-    the per-candidate timings (ms per launch of the kind's passes)."""
+def autotune(d, variant="eff", iters=1, cache_path=DEFAULT_CACHE, use_cache=True, verbose=False, runs=1):
+    """Select the fastest launch shapes (and, for several blocks, schedule)
+    for handle d; returns (x, y, z) and the per-candidate timings (ms per
+    launch of the kind's passes; ms per run of `runs` iterations)."""
     key = _key(d, variant)
     cache = _load(cache_path) if cache_path else {}
     if use_cache and key in cache:
         d.set_tiles(*cache[key]["tiles"])
+        d.set_schedule(cache[key].get("schedule", "pass"))
         return tuple(cache[key]["tiles"]), cache[key].get("timings", {})
+    d.set_schedule("pass")
     lens = d.max_lengths()
     best = list(d.tiles())
     timings = {}
@@ -67,22 +72,27 @@ def autotune(d, variant="eff", iters=1, cache_path=DEFAULT_CACHE, use_cache=True
                       flush=True)
         best[kind] = min(res, key=res.get)
         timings[str(kind)] = {str(c): t for c, t in res.items()}
+    schedule = "pass"
     if len(d.dims) > 1:
         exact = [_per_length_candidate(k, lens[k]) for k in range(3)]
-        if None not in exact and exact != best:
-            t_best = _iteration_ms(d, best, variant)
-            t_exact = _iteration_ms(d, exact, variant)
-            timings["iteration"] = {"tuned": t_best, "per_length": t_exact}
-            if verbose:
-                print(f"[tune] whole iteration: {best} {t_best:.4f} ms, per-length {exact} {t_exact:.4f} ms",
-                      file=sys.stderr, flush=True)
-            if t_exact < t_best:
-                best = exact
+        if None not in exact:
+            trials = [(best, "pass")] if exact != best else []
+            trials += [(exact, sch) for sch in ("pass", "block", "run")]
+            res = {}
+            for tiles, sch in trials:
+                res[(tuple(tiles), sch)] = _run_ms(d, tiles, sch, variant, runs)
+                if verbose:
+                    print(f"[tune] whole run of {runs}: tiles {tiles} schedule {sch}: "
+                          f"{res[(tuple(tiles), sch)]:.4f} ms", file=sys.stderr, flush=True)
+            (tiles, schedule) = min(res, key=res.get)
+            best = list(tiles)
+            timings["run"] = {f"{list(t)}/{sch}": ms for (t, sch), ms in res.items()}
     d.set_tiles(*best)
+    d.set_schedule(schedule)
     for b, e in enumerate(saved):
         d.set_estimate(e, b)
     if cache_path:
-        cache[key] = {"tiles": best, "timings": timings}
+        cache[key] = {"tiles": best, "schedule": schedule, "timings": timings}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
@@ -96,13 +106,16 @@ def _per_length_candidate(kind, max_len):
     return None
 
 
-def _iteration_ms(d, tiles, variant, reps=2):
-    """Device time of one iteration (graph replay) with the given shapes."""
+def _run_ms(d, tiles, schedule, variant, runs, reps=2):
+    """Device time of a run of `runs` iterations (graph replay) with the
+    given shapes and schedule."""
     d.set_tiles(*tiles)
-    d.iterate(1, variant)  # builds the graph
+    d.set_schedule(schedule)
+    d.iterate(runs, variant)  # builds the graphs
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(d.stream)
-    d.iterate(reps, variant)
+    for _ in range(reps):
+        d.iterate(runs, variant)
     e1.record(d.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps

@@ -148,3 +148,29 @@ def test_batched_columns_above_512(mvd):
             d.iterate(2, O.EFF)
             np.testing.assert_array_equal(got[i], d.estimate().cpu().numpy())
 
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_schedules_give_the_same_results(mvd, graphs):
+    """Pass-major, block-major and run-major schedules (blocks on several
+    lanes, repeated and different sizes) give the same estimates bitwise,
+    over runs of one and of three iterations, with and without graphs; the
+    flux statistics of the last iteration agree too."""
+    dims = [(40, 36, 30), (48, 40, 36), (40, 36, 30), (64, 64, 48), (20, 18, 16), (32, 32, 32)]
+    blocks = [block(d, 700 + i) for i, d in enumerate(dims)]
+    out = {}
+    with mvd.Deconvolver.batch(blocks, lam=0.01, use_graphs=graphs) as b:
+        b.set_tiles(*tiles_of(mvd, b.max_lengths(), -1))
+        start = [b.estimate(i).clone() for i in range(len(dims))]
+        for sch in ("pass", "block", "run"):
+            b.set_schedule(sch)
+            assert b.schedule() == sch
+            for i in range(len(dims)):
+                b.set_estimate(start[i], block=i)
+            b.iterate(1, O.OPT1)
+            b.iterate(3, O.OPT1)
+            out[sch] = ([b.estimate(i).cpu().numpy() for i in range(len(dims))], b.stats()["flux"])
+    for sch in ("block", "run"):
+        for a, r in zip(out[sch][0], out["pass"][0]):
+            np.testing.assert_array_equal(a, r)
+        np.testing.assert_allclose(out[sch][1], out["pass"][1], rtol=1e-12)

@@ -180,3 +180,25 @@ def test_config5_theta_gradient(mvd):
     assert rel(gpsi2, gpsio) <= 1e-4
     for a, b in zip(gP2, gPo):
         assert rel(a, b) <= 1e-4
+
+
+def test_autograd_gradients_follow_each_inputs_device(mvd):
+    """PSFs as CUDA tensors and psi0 as a CPU tensor: MVDLoss and
+    MVDDeconvolve return every gradient on its input's device and dtype,
+    with the values of the run on the default devices."""
+    from paper_1308_0730_amd.autograd import MVDDeconvolve, MVDLoss
+    s, psfs, _, psi0, _ = grad_case(False, seed=7)
+    n = 2
+    with mvd.Deconvolver(s.views, psfs) as d:
+        for fn in (MVDLoss, MVDDeconvolve):
+            grads = []
+            for psi_dev, psf_dev in (("cuda", "cpu"), ("cpu", "cuda")):
+                p0 = torch.from_numpy(psi0).to(psi_dev).requires_grad_(True)
+                ps = [torch.from_numpy(p.astype(np.float64)).to(psf_dev).requires_grad_(True) for p in psfs]
+                out = fn.apply(d, n, p0, *ps)
+                (out if fn is MVDLoss else (out * out).sum()).backward()
+                assert p0.grad.device.type == psi_dev and p0.grad.dtype == torch.float32
+                assert all(p.grad.device.type == psf_dev and p.grad.dtype == torch.float64 for p in ps)
+                grads.append([p0.grad.cpu().numpy()] + [p.grad.cpu().numpy() for p in ps])
+            for a, b in zip(*grads):
+                np.testing.assert_allclose(a, b, rtol=1e-6, atol=0)
