@@ -60,15 +60,33 @@ def workload(cfg):
     raise SystemExit(f"unknown config {cfg}")
 
 
+def workload_shapes(cfg):
+    """(dims, PSF shapes (kz, ky, kx), weighted) of every block of a
+    workload, without rendering it."""
+    from paper_1308_0730_amd import synth
+    if cfg == 1:
+        return [((64, 64, 64), [(17, 17, 17)] * 2)], False
+    if cfg == 2:
+        return [((128, 128, 128), [(25, 25, 25)] * 4)], False
+    if cfg == 3:
+        return [((512, 512, 256), [(41, 31, 31)] * 6)], True
+    if cfg == 4:
+        dims, _ = synth.config4_dims()
+        return [(d, [(17, 17, 17)] * 4) for d in dims], False
+    raise SystemExit(f"unknown config {cfg}")
+
+
 def pass_bytes(blocks, weighted):
-    """Algorithmic HBM bytes of one launch of each pass kind (all blocks)."""
+    """Algorithmic HBM bytes of one launch of each pass kind (all blocks);
+    blocks: workload blocks, or (dims, PSF shapes) pairs."""
     out = dict.fromkeys(PASS_NAMES, 0.0)
     for b in blocks:
-        nx, ny, nz = b.dims
+        dims, shapes = (b.dims, [p.shape for p in b.psfs]) if hasattr(b, "dims") else b
+        nx, ny, nz = dims
         V = nx * ny * nz
         S = ((nx // 2) * ny * nz + ny * nz) * 8.0  # half spectrum, complex float32
         # kernel planes: x/y-stage spectrum on the common odd z window
-        kz = max(p.shape[0] | 1 for p in b.psfs)
+        kz = max(sh[0] | 1 for sh in shapes)
         Hk = ((nx // 2) * ny * kz + ny * kz) * 8.0
         out["y_forward"] += 2 * S
         out["y_inverse"] += 2 * S
@@ -97,6 +115,108 @@ def measured_traffic(name, kernel):
         return None
     m = re.search(rf"^{kernel}:\s*([0-9.eE+]+)\s*bytes_per_launch", txt, re.M)
     return float(m.group(1)) if m else None
+
+
+# ---- rocprofv3 summaries (the text files under profiles/) -----------------
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def pass_of_kernel(name):
+    """The pass kind a library kernel implements (None for other kernels)."""
+    m = re.search(r"k_(ypass|zconv|xpass)(?:_ct|_class)?<(\w+)", name)
+    if not m:
+        return None
+    kind, arg = m.group(1), m.group(2)
+    if kind == "ypass":
+        return "y_inverse" if arg == "true" else "y_forward"
+    if kind == "zconv":
+        return "z_product"
+    return {"0": "x_forward", "1": "x_ratio", "2": "x_update"}.get(arg)
+
+
+def _short(name, n=150):
+    name = re.sub(r"\(.*\)$", "", name)
+    name = re.sub(r"((?:mvdk::)?ColPlan<[^>]*>, )+(?:mvdk::)?ColPlan<[^>]*>", "ColPlan<L>...", name)
+    return name if len(name) <= n else name[:n] + "..."
+
+
+def summarize_kernel_trace(d, title, command, top=20):
+    """Kernel statistics (name, calls, total, average, percent) and the
+    launch resources of the listed kernels, from a --kernel-trace --stats
+    run."""
+    stats = _csv_rows(d, "kernel_stats.csv")
+    trace = _csv_rows(d, "kernel_trace.csv")
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in stats) / 1e6
+    lines = [f"# rocprofv3 kernel statistics: {title}", f"# command: {command}",
+             f"# source_hash: {source_hash()}", "# name | calls | total_ms | average_us | percent"]
+    for r in stats[:top]:
+        lines.append(f"{_short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}")
+    if len(stats) > top:
+        lines.append(f"# ... {len(stats) - top} more kernels; all kernels total {total:.2f} ms")
+    lines.append("# resources of the kernels above: name | grid | workgroup | vgpr | lds_bytes | scratch_bytes")
+    seen = set()
+    names = {r["Name"] for r in stats[:top]}
+    for r in trace:
+        n = r["Kernel_Name"]
+        if n in names and n not in seen:
+            seen.add(n)
+            lines.append(f"{_short(n)} | {r['Grid_Size_X']} | {r['Workgroup_Size_X']} | {r['VGPR_Count']} | "
+                         f"{r['LDS_Block_Size']} | {r['Scratch_Size']}")
+    return "\n".join(lines)
+
+
+def summarize_counters(fetch_dir, write_dir, cfg, iterations, title, commands):
+    """HBM bytes per pass launch (one pass over every block) from a
+    FETCH_SIZE run and a WRITE_SIZE run, each scaled by what the counter
+    reads for the 1 GiB device copy of --copy-calibration; iterations: the
+    iterations the profiled command ran (a pass launch count per kind)."""
+    shapes, weighted = workload_shapes(cfg)
+    views = len(shapes[0][1])
+    alg = pass_bytes(shapes, weighted)
+    per_vu = {"y_forward": 2, "y_inverse": 2, "z_product": 2, "x_ratio": 1, "x_update": 1}
+    tot, cal, kern = {}, {}, {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r["Counter_Name"] == cname]
+        cal[cname] = max(float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"])
+        acc = dict.fromkeys(PASS_NAMES, 0.0)
+        for r in rows:
+            k = pass_of_kernel(r["Kernel_Name"])
+            if k in acc:
+                acc[k] += float(r["Counter_Value"])
+                kern.setdefault(k, set()).add(_short(r["Kernel_Name"], 80))
+        tot[cname] = acc
+    f_fac = (1 << 20) / cal["FETCH_SIZE"]
+    w_fac = (1 << 20) / cal["WRITE_SIZE"]
+    lines = [f"# HBM traffic per launch from rocprofv3 counters: {title}",
+             "# commands (two passes, one counter each):"] + [f"#   {c}" for c in commands] + [
+             f"# calibration: a 1 GiB device copy reads FETCH_SIZE = {cal['FETCH_SIZE']:.0f} KiB and "
+             f"WRITE_SIZE = {cal['WRITE_SIZE']:.0f} KiB,",
+             f"#   so fetch bytes = FETCH_SIZE * 1024 * {f_fac:.4f} and write bytes = WRITE_SIZE * 1024 * {w_fac:.4f}",
+             f"# a launch is one pass over every block; launches = {iterations} iterations x {views} views x "
+             "passes of the kind per view-update",
+             f"source_hash: {source_hash()}",
+             "# pass: measured_bytes_per_launch | fetch_bytes | write_bytes | algorithmic_bytes | launches | kernels"]
+    for k in PASS_NAMES:
+        n = iterations * views * per_vu[k]
+        fb = tot["FETCH_SIZE"][k] * 1024 * f_fac / n
+        wb = tot["WRITE_SIZE"][k] * 1024 * w_fac / n
+        ks = sorted(kern.get(k, ()))
+        kdesc = ks[0] if len(ks) == 1 else f"{len(ks)} kernels"
+        lines.append(f"{k}: {fb + wb:.4e} bytes_per_launch | {fb:.4e} | {wb:.4e} | {alg[k]:.4e} | {n} | {kdesc}")
+    return "\n".join(lines)
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
@@ -423,6 +543,8 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
+    ap.add_argument("--schedule", type=str, default=None, choices=("pass", "block", "run"),
+                    help="force the schedule of a multi-block handle")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched (48 blocks, against the plain form looped over them), the small "
                          "plain workloads (64^3, 128^3), the block-wise (1640x1070x345), the "
@@ -431,7 +553,21 @@ def main():
                          "linear-boundary, the simulated-SPIM and the PSF-refinement measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
+                    help="print the kernel-statistics summary of a rocprofv3 --kernel-trace --stats run (CSV)")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "TITLE", "COMMANDS"),
+                    help="print the HBM-traffic summary of a FETCH_SIZE and a WRITE_SIZE rocprofv3 run (CSV) of "
+                         "--config; COMMANDS separated by ';;'")
+    ap.add_argument("--counted-iterations", type=int, default=12,
+                    help="iterations the profiled command ran (1 at create + steps x iterations + profile iterations)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_kernel_trace(*args.summarize_trace))
+        return
+    if args.summarize_counters:
+        fd, wd, title, cmds = args.summarize_counters
+        print(summarize_counters(fd, wd, args.config, args.counted_iterations, title, cmds.split(";;")))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU form",
               file=sys.stderr)
@@ -464,10 +600,13 @@ def main():
     t0 = time.time()
     if args.tiles:
         d.set_tiles(*[int(x) for x in args.tiles.split(",")])
+        if args.schedule:
+            d.set_schedule(args.schedule)
     elif not args.no_tune:
         from paper_1308_0730_amd import tune
         tune.autotune(d, meta["variant"], iters=1, cache_path=None, verbose=True, runs=meta["iterations"])
     tiles = d.tiles()
+    schedule = d.schedule()
     launch = {}
     for i, (k, c) in enumerate(zip(("x", "y", "z"), tiles)):
         sh = mvd.tile_shape(i, c)
@@ -545,7 +684,8 @@ def main():
                    "views": n_views, "iterations": its,
                    "variant": meta["variant"], "lambda": meta["lam"], "weights": weighted,
                    "voxel_view_updates_per_step": vox_updates},
-        "roofline": roof, "passes": passes, "launch": launch, "cpu_baseline": cpu, "forms": forms,
+        "roofline": roof, "passes": passes, "launch": launch, "schedule": schedule, "cpu_baseline": cpu,
+        "forms": forms,
         "stats": {"flux_last_iteration": st["flux"], "ratio_clamps": st["ratio_clamps"],
                   "neg_clamps": st["neg_clamps"], "nonfinite": st["nonfinite"]},
     }

@@ -46,3 +46,47 @@ def test_measured_traffic_only_for_the_profiled_sources(monkeypatch):
     monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
     assert bench.measured_traffic("embryo512", "z_product") is None
     assert bench.measured_traffic("no_such_workload", "z_product") is None
+
+
+def test_pass_of_kernel_names():
+    names = {
+        "void mvdk::k_ypass_ct<false, 512, 16, 512, 8, 8, 8>(JobDesc const*, int)": "y_forward",
+        "void mvdk::k_ypass_class<true, 256, 16, 256, mvdk::ColPlan<135, 15, 9>>(JobDesc const*)": "y_inverse",
+        "void mvdk::k_ypass<false, 256, 16, 512>(JobDesc const*)": "y_forward",
+        "void mvdk::k_zconv_ct<256, 16, 256, 16, 16>(JobDesc const*)": "z_product",
+        "void mvdk::k_zconv_class<128, 16, 128, mvdk::ColPlan<50, 10, 5>>(JobDesc const*)": "z_product",
+        "void mvdk::k_xpass_ct<1, 4, 2, 256, 8, 8, 4>(JobDesc const*)": "x_ratio",
+        "void mvdk::k_xpass<2, 2, 4, 256>(JobDesc const*)": "x_update",
+        "void mvdk::k_xpass_ct<0, 2, 4, 256, 16, 16>(JobDesc const*)": "x_forward",
+        "k_check(float const*, long)": None,
+        "__amd_rocclr_copyBuffer": None,
+    }
+    for n, k in names.items():
+        assert bench.pass_of_kernel(n) == k, n
+
+
+def test_counter_summary_scales_by_the_copy(tmp_path):
+    """Synthetic counter files: a 1 GiB copy that FETCH_SIZE reads as half
+    its bytes; the summary doubles fetch counts, divides by the pass
+    launches (iterations x views x passes per view-update) and lists the
+    algorithmic bytes of the workload."""
+    import csv
+    V = 64 * 64 * 64
+    S = (32 * 64 * 64 + 64 * 64) * 8
+    for cname, copy_kib, per in (("FETCH_SIZE", 524288, 0.5), ("WRITE_SIZE", 1048576, 1.0)):
+        d = tmp_path / cname
+        d.mkdir()
+        with open(d / "run_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writerow(["__amd_rocclr_copyBuffer", cname, copy_kib])
+            # 2 iterations x 2 views x 2 y-forward passes, each moving S bytes each way
+            for _ in range(8):
+                w.writerow(["void mvdk::k_ypass_ct<false, 64, 16, 64, 8, 8>(x)", cname, S * per / 1024])
+    txt = bench.summarize_counters(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"), 1, 2, "t", ["a", "b"])
+    line = [l for l in txt.splitlines() if l.startswith("y_forward:")][0]
+    fields = [x.strip() for x in line.split("|")]
+    measured = float(fields[0].split()[1])
+    assert abs(measured - 2 * S) / (2 * S) < 1e-3
+    assert abs(float(fields[3]) - 2 * S) <= 1e-4 * 2 * S
+    assert fields[4] == "8"
