@@ -367,6 +367,21 @@ def grad_form(steps, warmup):
         ms = e0.elapsed_time(e1) / steps
         res[name] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3), "unit": "Gvox/s",
                      "loss": loss}
+    # the layer form (autograd's MVDDeconvolve): a recorded forward returning
+    # psi_n, then the vector-Jacobian product of a seed over that record
+    seed = torch.ones(s.views[0].shape, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        _, tok = d.forward_recorded(its)
+        d.backward_recorded(tok, seed)
+    e0.record(d.stream)
+    for _ in range(steps):
+        _, tok = d.forward_recorded(its)
+        d.backward_recorded(tok, seed)
+    e1.record(d.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["layer_forward_backward"] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3),
+                                     "unit": "Gvox/s"}
     d.close()
     res["backward_over_forward"] = round(res["forward_backward"]["ms_per_step"] / res["forward"]["ms_per_step"], 3)
     res["workload"] = "128^3, 4 views, 25^3 PSFs, 8 RL iterations, loss sum_v |psi_8 (x) P_v - phi_v|^2"

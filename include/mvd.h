@@ -270,6 +270,24 @@ int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0
 int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, const float* grad_psi_n,
                  int grad_psi_n_kind, double* const* grad_psf, float* grad_psi0, int grad_kind);
 
+/* The recorded form of the same product, for callers that run the forward
+ * themselves and differentiate later (autograd): mvd_forward_recorded runs n
+ * iterations from psi0 (NULL: the flat start) keeping one checkpoint per
+ * iteration, leaves psi = psi_n, synchronises and returns a token of the
+ * recorded run in *token; mvd_backward_recorded(token, grad_psi_n, ...)
+ * returns dL/dG_v and dL/dpsi0 as mvd_backward does, without running the
+ * forward from psi0 again (the reverse sweep recomputes each iteration from
+ * its checkpoint, except the last one, whose intermediates are still held).
+ * The record stays valid for further backward calls until a call changes
+ * the estimate, the PSFs or the weights (mvd_iterate, mvd_view_update,
+ * mvd_set_estimate, mvd_set_psfs, mvd_normalize_weights, mvd_profile,
+ * mvd_loss_grad, mvd_backward, another mvd_forward_recorded): then
+ * MVD_ESTATE.  Same restrictions as mvd_loss_grad (single block, circular
+ * boundary, MVD_RL). */
+int mvd_forward_recorded(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, int64_t* token);
+int mvd_backward_recorded(mvd_handle* h, int64_t token, const float* grad_psi_n, int grad_psi_n_kind,
+                          double* const* grad_psf, float* grad_psi0, int grad_kind);
+
 /* Replace the PSFs of a single-block handle (same count; extents may change
  * within the volume): recomputes their spectra; compound kernels are rebuilt
  * on their next use.  For PSF refinement loops. */

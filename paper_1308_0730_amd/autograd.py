@@ -6,8 +6,10 @@ passes:
     returns L = sum_v |psi_n (x) P_v - phi_v|^2; its gradients with respect
     to the PSF values and psi0 come from the same library call;
   * MVDDeconvolve: forward returns psi_n itself, so any loss written in torch
-    can follow it; backward is the library's vector-Jacobian product
-    (mvd_backward), which recomputes the run from psi0 with checkpoints.
+    can follow it; the forward records its checkpoints in the handle
+    (mvd_forward_recorded) and backward is the library's vector-Jacobian
+    product over that record (mvd_backward_recorded), or, if the handle has
+    run something else in between, over a recomputed run (mvd_backward).
 psf_from_theta builds the anisotropic Gaussian PSF of a view from
 (sigma_xy, sigma_z) in torch, so gradients reach the PSF parameters through
 autograd.
@@ -48,10 +50,8 @@ class MVDDeconvolve(torch.autograd.Function):
     def forward(ctx, handle, n_iter, psi0, *psfs):
         host = [p.detach().to("cpu", torch.float32).numpy() for p in psfs]
         handle.set_psfs(host)
-        handle.set_estimate(psi0.detach())
-        handle.iterate(int(n_iter), "rl")
-        out = handle.estimate().clone()
-        ctx.handle, ctx.n_iter, ctx.host = handle, int(n_iter), host
+        out, token = handle.forward_recorded(int(n_iter), psi0.detach())
+        ctx.handle, ctx.n_iter, ctx.host, ctx.token = handle, int(n_iter), host, token
         ctx.psi0 = psi0.detach()
         ctx.meta = [(p.dtype, p.device) for p in psfs]
         ctx.psi_meta = (psi0.dtype, psi0.device)
@@ -62,8 +62,14 @@ class MVDDeconvolve(torch.autograd.Function):
         want_p = any(ctx.needs_input_grad[3:])
         want_psi = ctx.needs_input_grad[2]
         h = ctx.handle
-        h.set_psfs(ctx.host)  # the handle may have run other PSFs since the forward pass
-        gp, gpsi = h.backward(ctx.n_iter, ctx.psi0, gout, grad_psf=want_p, grad_psi0=want_psi)
+        try:
+            gp, gpsi = h.backward_recorded(ctx.token, gout, grad_psf=want_p, grad_psi0=want_psi)
+        except mvd.MVDError as e:
+            if e.code != mvd.MVD_ESTATE:
+                raise
+            # the handle ran other work since the forward pass: recompute
+            h.set_psfs(ctx.host)
+            gp, gpsi = h.backward(ctx.n_iter, ctx.psi0, gout, grad_psf=want_p, grad_psi0=want_psi)
         gps = (None,) * len(ctx.meta) if gp is None else \
             tuple(torch.from_numpy(g).to(dtype=dt, device=dev) for g, (dt, dev) in zip(gp, ctx.meta))
         if gpsi is not None:

@@ -173,6 +173,12 @@ struct mvd_handle {
   // row plan (0: runtime plans) and their grid
   int gx_rows = 0, gx_grid = 0;
   bool grad_ready = false;
+  // the recorded run of the differentiated form: its checkpoints are valid
+  // while rec_token is non-zero (any call that changes the estimate, the
+  // PSFs or the weights clears it); inter_iter is the iteration whose
+  // intermediates (b, q, c, psi and the spectra per view) are stored
+  int64_t rec_token = 0, rec_count = 0;
+  int rec_n = 0, rec_variant = 0, inter_iter = -1;
   int grad_ckpt_cap = 0;
   float* g_ckpt = nullptr;                 // checkpoints, one volume per iteration
   float *g_b = nullptr, *g_q = nullptr, *g_c = nullptr, *g_psi = nullptr;  // [view][V]
@@ -1413,6 +1419,7 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (n < 0) bad("n must be >= 0");
   if (n == 0) return;
+  h->rec_token = 0;
   prepare_run(h, variant);
   if (block_major(h)) {
     if (h->use_graphs)
@@ -1430,6 +1437,7 @@ void iterate_impl(mvd_handle* h, int n, int variant) {
 }
 
 void iterate_combined_impl(mvd_handle* h, int n, int variant, int mean) {
+  h->rec_token = 0;
   if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (mean != MVD_MEAN_GEOMETRIC && mean != MVD_MEAN_ARITHMETIC) bad("mean must be MVD_MEAN_GEOMETRIC or MVD_MEAN_ARITHMETIC");
   if (n < 0) bad("n must be >= 0");
@@ -1595,38 +1603,139 @@ void x_init_rt(mvd_handle* h) {
 // seed == nullptr: the loss sum_v |psi_n (x) P_v - phi_v|^2 and its
 // gradients; otherwise the vector-Jacobian product with seed = d/dpsi_n
 // (seed_kind host or device) and no loss.
-void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
-                    double* const* grad_psf, float* grad_psi0, int grad_kind, const float* seed = nullptr,
-                    int seed_kind = MVD_MEM_HOST) {
+void set_estimate_impl(mvd_handle* h, const float* src, int src_kind, int block);
+
+// Forward run of the differentiated form: n iterations from psi0 (NULL: the
+// flat start) with one checkpoint per iteration; the intermediates of the
+// last iteration stay stored.  Leaves psi = psi_n (also kept in g_psiT) and
+// records the run.
+void grad_forward_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind) {
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "the differentiated form runs with the circular boundary only");
   if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
   if (variant != MVD_RL) bad("gradients are available for MVD_RL");
   if (n < 0) bad("n must be >= 0");
-  if (!seed && !loss) bad("loss is NULL");
-  if (seed && seed_kind != MVD_MEM_HOST && seed_kind != MVD_MEM_DEVICE) bad("grad_psi_n_kind must be host or device");
-  if (grad_psi0 && grad_kind != MVD_MEM_HOST && grad_kind != MVD_MEM_DEVICE) bad("grad_kind must be host or device");
   Block& B = h->blocks[0];
-  const int N = h->nviews;
-  const size_t V = B.V, S = B.spec_elems;
+  const size_t V = B.V;
   hipStream_t st = h->stream;
+  h->rec_token = 0;
   grad_setup(h, std::max(n, 1));
   if (psi0) {
     HIPCHECK(hipStreamSynchronize(st));
-    const int rc = mvd_set_estimate(h, psi0, psi0_kind, 0);
-    if (rc != MVD_OK) throw Error(rc, h->err);
+    set_estimate_impl(h, psi0, psi0_kind, 0);
   } else {
     HIPCHECK(mvd_launch_fill(B.psi, B.V, (float)B.s, st));
   }
   HIPCHECK(mvd_launch_set_int(h->d_flags, 0, st));
-  const bool want_grad = grad_psf || grad_psi0;
-  // forward with one checkpoint per iteration
   x_init_rt(h);
   for (int i = 0; i < n; ++i) {
     HIPCHECK(hipMemcpyAsync(h->g_ckpt + (size_t)i * V, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-    for (int v = 0; v < N; ++v) grad_forward_view(h, v);
+    for (int v = 0; v < h->nviews; ++v) grad_forward_view(h, v);
   }
   HIPCHECK(hipMemcpyAsync(h->g_psiT, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  h->inter_iter = n - 1;
+  h->rec_n = n;
+  h->rec_variant = variant;
+  h->rec_token = ++h->rec_count;
+  h->spec_valid = false;
+  h->iterations = n;
+}
+
+// Reverse sweep over the recorded run: g_gbar holds dL/dpsi_n on entry and
+// dL/dpsi_0 on exit; each iteration is recomputed from its checkpoint
+// (unless its intermediates are the stored ones), then the adjoints of its
+// view-updates run in reverse order, accumulating the PSF cross-spectra
+// (g_acc must hold the loss's own contribution, or zeros).  Gradients go to
+// the caller's buffers; psi is left at psi_n.
+void grad_reverse_impl(mvd_handle* h, double* const* grad_psf, float* grad_psi0, int grad_kind) {
+  Block& B = h->blocks[0];
+  const int N = h->nviews, n = h->rec_n;
+  const size_t V = B.V, S = B.spec_elems;
+  hipStream_t st = h->stream;
+  for (int i = n - 1; i >= 0; --i) {
+    if (i != h->inter_iter) {
+      HIPCHECK(hipMemcpyAsync(B.psi, h->g_ckpt + (size_t)i * V, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+      x_init_rt(h);
+      for (int v = 0; v < N; ++v) grad_forward_view(h, v);
+      h->inter_iter = i;
+    }
+    for (int v = N - 1; v >= 0; --v) grad_adjoint_view(h, v);
+  }
+  if (grad_psi0)
+    HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
+                            grad_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+  if (grad_psf) {
+    // the windowed inverse DFT of each view's cross-spectrum, on the device
+    // in FP64 (z, then y, then x stage); the normalisation on the host
+    auto table = [&](double2*& dst, int len) {
+      if (dst) return;
+      const auto t = mvdh::twiddles(len);
+      dst = (double2*)h->dalloc(t.size() * sizeof(double2));
+      HIPCHECK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    };
+    table(h->g_twz, B.nz);
+    table(h->g_twy, B.ny);
+    table(h->g_twx, B.nx);
+    size_t t1n = 0, t2n = 0, gn = 0;
+    for (int v = 0; v < N; ++v) {
+      const mvdh::Kern& P = B.P[v];
+      t1n = std::max(t1n, (size_t)(B.M + 1) * B.ny * P.kz);
+      t2n = std::max(t2n, (size_t)(B.M + 1) * P.ky * P.kz);
+      gn = std::max(gn, (size_t)P.kx * P.ky * P.kz);
+    }
+    auto grow = [&](auto*& p, size_t& cap, size_t cnt, size_t elem) {
+      if (cnt <= cap) return;
+      p = (std::remove_reference_t<decltype(p)>)h->dalloc(cnt * elem);
+      cap = cnt;
+    };
+    grow(h->g_t1, h->g_t1_cap, t1n, sizeof(double2));
+    grow(h->g_t2, h->g_t2_cap, t2n, sizeof(double2));
+    grow(h->g_gw, h->g_gw_cap, gn, sizeof(double));
+    const double invV = 1.0 / (double)B.V;
+    for (int v = 0; v < N; ++v) {
+      if (!grad_psf[v]) continue;
+      const mvdh::Kern& P = B.P[v];
+      HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.Mp, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
+      HIPCHECK(mvd_launch_idft_yx(h->g_t1, B.M, B.nx, B.ny, P.kx, P.ky, P.kz, h->g_twx, h->g_twy, h->g_t2,
+                                  h->g_gw, st));
+      std::vector<double> g((size_t)P.kx * P.ky * P.kz);
+      HIPCHECK(hipMemcpyAsync(g.data(), h->g_gw, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      for (double& x : g) x *= invV;
+      // through the normalisation P = G / sum G, then drop the odd padding
+      double dot = 0;
+      for (size_t j = 0; j < g.size(); ++j) dot += g[j] * P.a[j];
+      const auto& d = B.psf_dims[v];
+      for (int z = 0; z < d[2]; ++z)
+        for (int y = 0; y < d[1]; ++y)
+          for (int x = 0; x < d[0]; ++x)
+            grad_psf[v][((size_t)z * d[1] + y) * d[0] + x] =
+                (g[((size_t)z * P.ky + y) * P.kx + x] - dot) / B.psf_sum[v];
+    }
+  }
+  // leave psi at the end of the run
+  HIPCHECK(hipMemcpyAsync(B.psi, h->g_psiT, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  h->spec_valid = false;
+  h->iterations = n;
+  if (read_flag(h)) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
+}
+
+// seed == nullptr: the loss sum_v |psi_n (x) P_v - phi_v|^2 and its
+// gradients; otherwise the vector-Jacobian product with seed = d/dpsi_n
+// (recomputing the forward run from psi0).
+void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, double* loss,
+                    double* const* grad_psf, float* grad_psi0, int grad_kind, const float* seed = nullptr,
+                    int seed_kind = MVD_MEM_HOST) {
+  if (!seed && !loss) bad("loss is NULL");
+  if (seed && seed_kind != MVD_MEM_HOST && seed_kind != MVD_MEM_DEVICE) bad("grad_psi_n_kind must be host or device");
+  if (grad_psi0 && grad_kind != MVD_MEM_HOST && grad_kind != MVD_MEM_DEVICE) bad("grad_kind must be host or device");
+  grad_forward_impl(h, n, variant, psi0, psi0_kind);
+  Block& B = h->blocks[0];
+  const int N = h->nviews;
+  const size_t V = B.V, S = B.spec_elems;
+  hipStream_t st = h->stream;
+  const bool want_grad = grad_psf || grad_psi0;
   // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed, or the
   // caller's seed
   HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)N * S * sizeof(double2), st));
@@ -1657,79 +1766,41 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
     HIPCHECK(hipMemcpyAsync(lv.data(), h->g_loss, N * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   if (want_grad) {
-    // reverse sweep: recompute each iteration from its checkpoint, then the
-    // adjoints of its view-updates in reverse order
-    for (int i = n - 1; i >= 0; --i) {
-      HIPCHECK(hipMemcpyAsync(B.psi, h->g_ckpt + (size_t)i * V, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-      x_init_rt(h);
-      for (int v = 0; v < N; ++v) grad_forward_view(h, v);
-      for (int v = N - 1; v >= 0; --v) grad_adjoint_view(h, v);
-    }
-    if (grad_psi0)
-      HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
-                              grad_kind == MVD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
-    if (grad_psf) {
-      // the windowed inverse DFT of each view's cross-spectrum, on the device
-      // in FP64 (z, then y, then x stage); the normalisation on the host
-      auto table = [&](double2*& dst, int n) {
-        if (dst) return;
-        const auto t = mvdh::twiddles(n);
-        dst = (double2*)h->dalloc(t.size() * sizeof(double2));
-        HIPCHECK(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-      };
-      table(h->g_twz, B.nz);
-      table(h->g_twy, B.ny);
-      table(h->g_twx, B.nx);
-      size_t t1n = 0, t2n = 0, gn = 0;
-      for (int v = 0; v < N; ++v) {
-        const mvdh::Kern& P = B.P[v];
-        t1n = std::max(t1n, (size_t)(B.M + 1) * B.ny * P.kz);
-        t2n = std::max(t2n, (size_t)(B.M + 1) * P.ky * P.kz);
-        gn = std::max(gn, (size_t)P.kx * P.ky * P.kz);
-      }
-      auto grow = [&](auto*& p, size_t& cap, size_t n, size_t elem) {
-        if (n <= cap) return;
-        p = (std::remove_reference_t<decltype(p)>)h->dalloc(n * elem);
-        cap = n;
-      };
-      grow(h->g_t1, h->g_t1_cap, t1n, sizeof(double2));
-      grow(h->g_t2, h->g_t2_cap, t2n, sizeof(double2));
-      grow(h->g_gw, h->g_gw_cap, gn, sizeof(double));
-      const double invV = 1.0 / (double)B.V;
-      for (int v = 0; v < N; ++v) {
-        if (!grad_psf[v]) continue;
-        const mvdh::Kern& P = B.P[v];
-        HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.Mp, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
-        HIPCHECK(mvd_launch_idft_yx(h->g_t1, B.M, B.nx, B.ny, P.kx, P.ky, P.kz, h->g_twx, h->g_twy, h->g_t2,
-                                    h->g_gw, st));
-        std::vector<double> g((size_t)P.kx * P.ky * P.kz);
-        HIPCHECK(hipMemcpyAsync(g.data(), h->g_gw, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHECK(hipStreamSynchronize(st));
-        for (double& x : g) x *= invV;
-        // through the normalisation P = G / sum G, then drop the odd padding
-        double dot = 0;
-        for (size_t j = 0; j < g.size(); ++j) dot += g[j] * P.a[j];
-        const auto& d = B.psf_dims[v];
-        for (int z = 0; z < d[2]; ++z)
-          for (int y = 0; y < d[1]; ++y)
-            for (int x = 0; x < d[0]; ++x)
-              grad_psf[v][((size_t)z * d[1] + y) * d[0] + x] =
-                  (g[((size_t)z * P.ky + y) * P.kx + x] - dot) / B.psf_sum[v];
-      }
-    }
+    const int64_t token = h->rec_token;
+    grad_reverse_impl(h, grad_psf, grad_psi0, grad_kind);
+    h->rec_token = token;
+  } else {
+    HIPCHECK(hipMemcpyAsync(B.psi, h->g_psiT, V * sizeof(float), hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    h->spec_valid = false;
+    if (read_flag(h)) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
   }
-  // leave psi at the end of the run
-  HIPCHECK(hipMemcpyAsync(B.psi, h->g_psiT, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-  HIPCHECK(hipStreamSynchronize(st));
   double L = 0;
   for (double x : lv) L += x;
   if (loss) *loss = L;
-  h->spec_valid = false;
-  h->iterations = n;
-  if (read_flag(h)) throw Error(MVD_ENONFINITE, "the estimate became non-finite");
+}
+
+// The vector-Jacobian product over the run recorded by mvd_forward_recorded
+// (token), without recomputing the forward run from psi0.
+void backward_recorded_impl(mvd_handle* h, int64_t token, const float* seed, int seed_kind, double* const* grad_psf,
+                            float* grad_psi0, int grad_kind) {
+  if (!seed) bad("grad_psi_n is NULL");
+  if (seed_kind != MVD_MEM_HOST && seed_kind != MVD_MEM_DEVICE) bad("grad_psi_n_kind must be host or device");
+  if (grad_psi0 && grad_kind != MVD_MEM_HOST && grad_kind != MVD_MEM_DEVICE) bad("grad_kind must be host or device");
+  if (token <= 0 || token != h->rec_token)
+    throw Error(MVD_ESTATE, "no recorded run with this token (a later call changed the estimate, PSFs or weights)");
+  Block& B = h->blocks[0];
+  const size_t V = B.V, S = B.spec_elems;
+  hipStream_t st = h->stream;
+  HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)h->nviews * S * sizeof(double2), st));
+  HIPCHECK(hipMemcpyAsync(h->g_gbar, seed, V * sizeof(float),
+                          seed_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+  grad_reverse_impl(h, grad_psf, grad_psi0, grad_kind);
+  h->rec_token = token;
 }
 
 void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims, int mem_kind) {
+  h->rec_token = 0;
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "mvd_set_psfs takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "mvd_set_psfs runs with the circular boundary only");
   if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
@@ -1784,6 +1855,7 @@ void set_psfs_impl(mvd_handle* h, const float* const* psfs, const int* psf_dims,
 // Limit every voxel's summed weight to the overlap number of its block (see
 // mvd_weights.hip); m per block into m_out when given.
 void normalize_weights_impl(mvd_handle* h, int mode, double value, double* m_out) {
+  h->rec_token = 0;
   if (mode < MVD_OVERLAP_ONE || mode > MVD_OVERLAP_USER) bad("mode must be one of the MVD_OVERLAP_* values");
   if (mode == MVD_OVERLAP_USER && !(value > 0 && std::isfinite(value))) bad("the user overlap must be finite and > 0");
   for (const auto& B : h->blocks)
@@ -1884,6 +1956,8 @@ int get_estimate_impl(mvd_handle* h, float* dst, int dst_kind, int block) {
 // Replace the estimate of a block (checked finite and >= 0); resets the
 // iteration count and the non-finite flag.  Synchronises.
 void set_estimate_impl(mvd_handle* h, const float* src, int src_kind, int block) {
+  h->rec_token = 0;
+  h->inter_iter = -1;
   Block& B = const_cast<Block&>(block_of(h, block));
   if (!src) bad("src is NULL");
   if (src_kind != MVD_MEM_HOST && src_kind != MVD_MEM_DEVICE) bad("src_kind must be host or device");
@@ -2226,6 +2300,7 @@ int mvd_view_update(mvd_handle* h, int view, int variant) {
   }
   return guard(h, [&] {
     if (view < 0 || view >= h->nviews) bad("view index out of range");
+    h->rec_token = 0;
     prepare_run(h, variant);
     enqueue_view(h, h->stream, variant, view);
   });
@@ -2239,6 +2314,7 @@ int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls) {
   return guard(h, [&] {
     if (n < 1) bad("n must be >= 1");
     if (!avg_ms || !calls) bad("avg_ms and calls are required");
+    h->rec_token = 0;
     prepare_run(h, variant);
     PassTimer t;
     t.s = h->stream;
@@ -2279,6 +2355,35 @@ int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_
     if (!grad_psi_n) bad("grad_psi_n is NULL");
     loss_grad_impl(h, n, variant, psi0, psi0_kind, nullptr, grad_psf, grad_psi0, grad_kind, grad_psi_n,
                    grad_psi_n_kind);
+  });
+}
+
+int mvd_forward_recorded(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, int64_t* token) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    if (!token) bad("token is NULL");
+    *token = 0;
+    grad_forward_impl(h, n, variant, psi0, psi0_kind);
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (read_flag(h)) {
+      h->rec_token = 0;
+      throw Error(MVD_ENONFINITE, "the estimate became non-finite");
+    }
+    *token = h->rec_token;
+  });
+}
+
+int mvd_backward_recorded(mvd_handle* h, int64_t token, const float* grad_psi_n, int grad_psi_n_kind,
+                          double* const* grad_psf, float* grad_psi0, int grad_kind) {
+  if (!h) {
+    g_err = "handle is NULL";
+    return MVD_EINVAL;
+  }
+  return guard(h, [&] {
+    backward_recorded_impl(h, token, grad_psi_n, grad_psi_n_kind, grad_psf, grad_psi0, grad_kind);
   });
 }
 

@@ -93,6 +93,9 @@ def lib():
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_create_blocked.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]
+    L.mvd_forward_recorded.argtypes = [H, C.c_int, C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int64)]
+    L.mvd_backward_recorded.argtypes = [H, C.c_int64, C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.c_void_p,
+                                        C.c_int]
     L.mvd_set_schedule.argtypes = [H, C.c_int]
     L.mvd_get_schedule.argtypes = [H]
     L.mvd_blocking.argtypes = [H, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -106,7 +109,8 @@ def lib():
                  "mvd_stats", "mvd_synchronize", "mvd_destroy", "mvd_compound_kernel", "mvd_kernel_spectrum",
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
                  "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc",
-                 "mvd_create_blocked", "mvd_blocking", "mvd_set_schedule", "mvd_get_schedule"):
+                 "mvd_create_blocked", "mvd_blocking", "mvd_set_schedule", "mvd_get_schedule",
+                 "mvd_forward_recorded", "mvd_backward_recorded"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -362,6 +366,34 @@ class Deconvolver:
         rc = lib().mvd_backward(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
                                 C.c_void_p(g.data_ptr()), MEM_DEVICE, _ptr_array(gp_ptrs),
                                 None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
+        _check(rc, self._h)
+        return gps, gpsi
+
+    def forward_recorded(self, n, psi0=None):
+        """n RL iterations from psi0 (None: flat start) with one checkpoint
+        per iteration; returns (psi_n as a CUDA tensor, token of the
+        recorded run for backward_recorded)."""
+        src, _, _, _ = self._grad_buffers(psi0, False, False, None)
+        tok = C.c_int64()
+        rc = lib().mvd_forward_recorded(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()),
+                                        MEM_DEVICE, C.byref(tok))
+        _check(rc, self._h)
+        return self.estimate(), tok.value
+
+    def backward_recorded(self, token, grad_psi_n, grad_psf=True, grad_psi0=True, psf_shapes=None):
+        """Vector-Jacobian product over the run recorded with `token`:
+        (dL/dpsf list of float64 arrays or None, dL/dpsi0 CUDA tensor or
+        None).  MVDError(MVD_ESTATE) if a later call changed the estimate,
+        PSFs or weights."""
+        nx, ny, nz = self.dims[0]
+        _, gps, gp_ptrs, gpsi = self._grad_buffers(None, grad_psf, grad_psi0, psf_shapes)
+        g = grad_psi_n.detach().to(self.device, torch.float32).contiguous() if isinstance(grad_psi_n, torch.Tensor) \
+            else torch.from_numpy(np.ascontiguousarray(np.asarray(grad_psi_n, np.float32))).to(self.device)
+        if tuple(g.shape) != (nz, ny, nx):
+            raise ValueError(f"grad_psi_n has shape {tuple(g.shape)}, expected {(nz, ny, nx)}")
+        rc = lib().mvd_backward_recorded(self._h, int(token), C.c_void_p(g.data_ptr()), MEM_DEVICE,
+                                         _ptr_array(gp_ptrs), None if gpsi is None else C.c_void_p(gpsi.data_ptr()),
+                                         MEM_DEVICE)
         _check(rc, self._h)
         return gps, gpsi
 

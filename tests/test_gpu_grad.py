@@ -202,3 +202,30 @@ def test_autograd_gradients_follow_each_inputs_device(mvd):
                 grads.append([p0.grad.cpu().numpy()] + [p.grad.cpu().numpy() for p in ps])
             for a, b in zip(*grads):
                 np.testing.assert_allclose(a, b, rtol=1e-6, atol=0)
+
+
+def test_recorded_backward_equals_backward(mvd):
+    """mvd_forward_recorded + mvd_backward_recorded (no forward run from psi0
+    in the backward) give mvd_backward's psi_n and gradients bitwise; the
+    record serves a second seed; a call that changes the estimate voids it
+    (MVD_ESTATE)."""
+    s, psfs, w, psi0, rng = grad_case(True)
+    n = 3
+    g1 = rng.normal(size=psi0.shape).astype(np.float32)
+    g2 = rng.normal(size=psi0.shape).astype(np.float32)
+    with mvd.Deconvolver(s.views, psfs, w, lam=0.02) as d:
+        ref1 = d.backward(n, psi0, g1)
+        psi_ref = d.estimate().cpu().numpy()
+        ref2 = d.backward(n, psi0, g2)
+        psi_n, tok = d.forward_recorded(n, psi0)
+        np.testing.assert_array_equal(psi_n.cpu().numpy(), psi_ref)
+        for g, ref in ((g1, ref1), (g2, ref2)):
+            gp, gpsi = d.backward_recorded(tok, g)
+            np.testing.assert_array_equal(gpsi.cpu().numpy(), ref[1].cpu().numpy())
+            for a, b in zip(gp, ref[0]):
+                np.testing.assert_array_equal(a, b)
+            np.testing.assert_array_equal(d.estimate().cpu().numpy(), psi_ref)
+        d.iterate(1, O.RL)
+        with pytest.raises(mvd.MVDError) as e:
+            d.backward_recorded(tok, g1)
+        assert e.value.code == mvd.MVD_ESTATE
