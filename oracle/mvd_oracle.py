@@ -540,14 +540,73 @@ def circ_corr_window(f, g, shape):
     return r[np.ix_(iz, iy, ix)]
 
 
+def compound_kernel_vjp(P, v, variant, Kbar):
+    """Adjoint of the compound kernel construction (see compound_kernel):
+    given Kbar = dL/dK_v on K_v's window, returns dL/dP_w for every
+    prepared (normalised, odd) PSF P_w.  The steps of the construction are
+    taken backwards: the normalisation K = U / sum U, the pointwise product
+    U = P_v* . prod_w A_w, each factor A_w = crop(P_v* * P_w * P_w*) (EFF) or
+    crop(P_v* * P_w) (OPT1), the full linear convolutions (adjoint: 'valid'
+    correlations with the other operand) and the mirror."""
+    n = len(P)
+    Kbar = np.asarray(Kbar, dtype=np.float64)
+    gP = [np.zeros_like(p) for p in P]
+    Pv_m = mirror(P[v])
+    if variant == RL or n == 1:
+        gP[v] += mirror(Kbar)
+        return gP
+    if variant == OPT2:
+        U = Pv_m ** n
+        Ubar = (Kbar - np.sum(Kbar * U) / U.sum()) / U.sum()
+        gP[v] += mirror(Ubar * n * Pv_m ** (n - 1))
+        return gP
+    # forward, keeping the pieces
+    g1, full, A = {}, {}, {}
+    for w in range(n):
+        if w == v:
+            continue
+        g1[w] = conv_full(Pv_m, P[w])
+        full[w] = conv_full(g1[w], mirror(P[w])) if variant == EFF else g1[w]
+        A[w] = crop_center(full[w], Pv_m.shape)
+    U = Pv_m.copy()
+    for w in A:
+        U = U * A[w]
+    S = U.sum()
+    K = U / S
+    # K = U / S
+    Ubar = (Kbar - np.sum(Kbar * K)) / S
+    # U = Pv_m . prod A_w
+    Pv_m_bar = Ubar * np.prod([A[w] for w in A], axis=0)
+    for w in A:
+        others = np.prod([A[u] for u in A if u != w], axis=0) if len(A) > 1 else 1.0
+        Abar = Ubar * Pv_m * others
+        # A = crop(full): the adjoint pads into the full support
+        fbar = np.zeros_like(full[w])
+        pads = [((nf - na) // 2) for nf, na in zip(full[w].shape, Abar.shape)]
+        fbar[pads[0]:pads[0] + Abar.shape[0], pads[1]:pads[1] + Abar.shape[1],
+             pads[2]:pads[2] + Abar.shape[2]] = Abar
+        if variant == EFF:
+            # full = g1 * mirror(P_w)
+            g1bar = signal.correlate(fbar, mirror(P[w]), mode="valid", method="direct")
+            gP[w] += mirror(signal.correlate(fbar, g1[w], mode="valid", method="direct"))
+        else:
+            g1bar = fbar
+        # g1 = Pv_m * P_w
+        Pv_m_bar = Pv_m_bar + signal.correlate(g1bar, P[w], mode="valid", method="direct")
+        gP[w] += signal.correlate(g1bar, Pv_m, mode="valid", method="direct")
+    gP[v] += mirror(Pv_m_bar)
+    return gP
+
+
 def loss_value(psi, views, P):
     return float(sum(np.sum((circ_conv(psi, p) - np.asarray(phi, np.float64)) ** 2) for p, phi in zip(P, views)))
 
 
-def _taped_run(pb, n_iter, psi0):
-    """The sequential RL run (K_v = P_v*) keeping every view-update's
-    intermediates for the reverse sweep."""
+def _taped_run(pb, n_iter, psi0, variant=RL):
+    """The sequential run (back-projection kernels K_v of the variant)
+    keeping every view-update's intermediates for the reverse sweep."""
     P = pb.P
+    K = pb.kernels(variant)
     psi = np.asarray(psi0, dtype=np.float64).copy()
     tape = []
     for _ in range(n_iter):
@@ -555,7 +614,7 @@ def _taped_run(pb, n_iter, psi0):
             w = None if pb.weights is None else pb.weights[v]
             b = circ_conv(psi, P[v])
             q = pb.views[v] / np.maximum(b, pb.eps)
-            c = circ_conv(q, mirror(P[v]))
+            c = circ_conv(q, K[v])
             u = psi * np.maximum(c, 0.0)
             t = tikhonov(u, pb.lam_p)
             new = t if w is None else psi + w * (t - psi)
@@ -564,15 +623,17 @@ def _taped_run(pb, n_iter, psi0):
     return psi, tape
 
 
-def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
-    """Loss and its gradients for the sequential RL update (K_v = P_v*).
+def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0, variant=RL):
+    """Loss and its gradients for the sequential update with the variant's
+    back-projection kernels (RL: K_v = P_v*; the compound kernels depend on
+    every PSF).
 
     Returns (L, dL/dpsi0, [dL/dpsf_v]) with each PSF gradient on the raw
     input extents of psfs[v]."""
     pb = Problem(views, psfs, weights, lam)
     P = pb.P
     N = pb.n
-    psi, tape = _taped_run(pb, n_iter, psi0)
+    psi, tape = _taped_run(pb, n_iter, psi0, variant)
     L = 0.0
     gpsi = np.zeros_like(psi)
     gP = [np.zeros_like(p) for p in P]
@@ -581,29 +642,33 @@ def loss_and_grad(views, psfs, n_iter, psi0, weights=None, lam=0.0):
         L += float(np.sum(r * r))
         gpsi += circ_conv(2.0 * r, mirror(P[v]))
         gP[v] += circ_corr_window(2.0 * r, psi, P[v].shape)
-    gpsi, out = _reverse(pb, psfs, tape, gpsi, gP)
+    gpsi, out = _reverse(pb, psfs, tape, gpsi, gP, variant)
     return L, gpsi, out
 
 
-def vjp(views, psfs, n_iter, psi0, gbar, weights=None, lam=0.0):
+def vjp(views, psfs, n_iter, psi0, gbar, weights=None, lam=0.0, variant=RL):
     """Vector-Jacobian product of the unrolled run: for a given gbar (the
     gradient of some scalar with respect to psi_n), the gradients of
     <gbar, psi_n> with respect to psi0 and to the raw PSF values.
 
     Returns (psi_n, d/dpsi0, [d/dpsf_v])."""
     pb = Problem(views, psfs, weights, lam)
-    psi, tape = _taped_run(pb, n_iter, psi0)
+    psi, tape = _taped_run(pb, n_iter, psi0, variant)
     gP = [np.zeros_like(p) for p in pb.P]
-    gpsi, out = _reverse(pb, psfs, tape, np.asarray(gbar, dtype=np.float64).copy(), gP)
+    gpsi, out = _reverse(pb, psfs, tape, np.asarray(gbar, dtype=np.float64).copy(), gP, variant)
     return psi, gpsi, out
 
 
-def _reverse(pb, psfs, tape, gpsi, gP):
+def _reverse(pb, psfs, tape, gpsi, gP, variant=RL):
     """Reverse sweep over the taped view-updates from the seed gpsi = d/dpsi_n
-    (and PSF gradients gP accumulated so far, on the padded odd boxes), then
-    through the normalisation of eq. 3 onto the raw PSF extents."""
+    (and PSF gradients gP accumulated so far, on the padded odd boxes); the
+    gradients of the back-projection kernels go through the compound kernel
+    construction (compound_kernel_vjp), then everything through the
+    normalisation of eq. 3 onto the raw PSF extents."""
     P = pb.P
     N = pb.n
+    K = pb.kernels(variant)
+    gK = [np.zeros_like(k) for k in K]
     for (v, psi_in, b, q, c, u, w) in reversed(tape):
         g = gpsi
         tbar = g if w is None else w * g
@@ -611,13 +676,17 @@ def _reverse(pb, psfs, tape, gpsi, gP):
         ubar = tbar * dT
         gdirect = ubar * np.maximum(c, 0.0) + (0.0 if w is None else (1.0 - w) * g)
         cbar = ubar * psi_in * (c > 0)
-        # c = q (x) P_v*: adjoint in q is a convolution with P_v; in the kernel
-        # K = P_v*, K[c + j] gets sum_x cbar(x) q(x - j), i.e. P_v[c - j]
-        qbar = circ_conv(cbar, P[v])
-        gP[v] += mirror(circ_corr_window(cbar, q, P[v].shape))
+        # c = q (x) K_v: the adjoint in q is a convolution with K_v*, in the
+        # kernel K_v[c + j] gets sum_x cbar(x) q(x - j)
+        qbar = circ_conv(cbar, mirror(K[v]))
+        gK[v] += circ_corr_window(cbar, q, K[v].shape)
         bbar = np.where(b > pb.eps, -qbar * q / b, 0.0)
         gP[v] += circ_corr_window(bbar, psi_in, P[v].shape)
         gpsi = gdirect + circ_conv(bbar, mirror(P[v]))
+    # the back-projection kernels are functions of the PSFs
+    for v in range(N):
+        for w, g in enumerate(compound_kernel_vjp(P, v, variant, gK[v])):
+            gP[w] += g
     # through the normalisation P = G / sum(G) and the odd padding
     out = []
     for v in range(N):
@@ -629,10 +698,10 @@ def _reverse(pb, psfs, tape, gpsi, gP):
     return gpsi, out
 
 
-def loss_of(views, psfs, n_iter, psi0, weights=None, lam=0.0):
+def loss_of(views, psfs, n_iter, psi0, weights=None, lam=0.0, variant=RL):
     """The loss alone (forward), for finite differences."""
     pb = Problem(views, psfs, weights, lam)
-    psi = pb.iterate(np.asarray(psi0, dtype=np.float64), n_iter, RL)
+    psi = pb.iterate(np.asarray(psi0, dtype=np.float64), n_iter, variant)
     return loss_value(psi, pb.views, pb.P)
 
 
