@@ -382,6 +382,18 @@ def grad_form(steps, warmup):
     ms = e0.elapsed_time(e1) / steps
     res["layer_forward_backward"] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3),
                                      "unit": "Gvox/s"}
+    # the same loss and gradients through the efficient update (eq. 222):
+    # the compound kernels' gradients go through their construction
+    for _ in range(warmup):
+        d.loss_grad(its, None, variant="eff")
+    e0.record(d.stream)
+    for _ in range(steps):
+        loss, _, _ = d.loss_grad(its, None, variant="eff")
+    e1.record(d.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["eff_forward_backward"] = {"ms_per_step": round(ms, 3), "value": round(vox / ms / 1e6, 3),
+                                   "unit": "Gvox/s", "loss": loss}
     d.close()
     res["backward_over_forward"] = round(res["forward_backward"]["ms_per_step"] / res["forward"]["ms_per_step"], 3)
     res["workload"] = "128^3, 4 views, 25^3 PSFs, 8 RL iterations, loss sum_v |psi_8 (x) P_v - phi_v|^2"

@@ -241,7 +241,10 @@ int mvd_view_update(mvd_handle* h, int view, int variant);
 #define MVD_PASS_KINDS 5
 int mvd_profile(mvd_handle* h, int n, int variant, double* avg_ms, int* calls);
 
-/* Differentiated form (single-block handles, MVD_RL).  Runs n iterations
+/* Differentiated form (single-block handles, any variant: for the compound
+ * variants the back-projection kernels K_v are functions of every PSF and
+ * their gradients are propagated through the construction, as in
+ * mvd_compound_kernel_vjp).  Runs n iterations
  * from psi0 (NULL: the flat start s; psi0_kind host or device), keeping one
  * checkpoint per iteration, and returns the loss
  *   L = sum_v sum_x (psi_n (x) P_v - phi_v)^2
@@ -266,7 +269,7 @@ int mvd_loss_grad(mvd_handle* h, int n, int variant, const float* psi0, int psi0
  * reverse mode of the view-update of eq. 15 with weights and Tikhonov,
  * iterated.  Recomputes the forward run from psi0 (NULL: the flat start),
  * leaves psi = psi_n; synchronises.  MVD_EINVAL if grad_psi_n is NULL,
- * MVD_ESTATE for batched or linear-boundary handles, MVD_RL only. */
+ * MVD_ESTATE for batched, linear-boundary or block-wise handles. */
 int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, const float* grad_psi_n,
                  int grad_psi_n_kind, double* const* grad_psf, float* grad_psi0, int grad_kind);
 
@@ -283,7 +286,7 @@ int mvd_backward(mvd_handle* h, int n, int variant, const float* psi0, int psi0_
  * mvd_set_estimate, mvd_set_psfs, mvd_normalize_weights, mvd_profile,
  * mvd_loss_grad, mvd_backward, another mvd_forward_recorded): then
  * MVD_ESTATE.  Same restrictions as mvd_loss_grad (single block, circular
- * boundary, MVD_RL). */
+ * boundary). */
 int mvd_forward_recorded(mvd_handle* h, int n, int variant, const float* psi0, int psi0_kind, int64_t* token);
 int mvd_backward_recorded(mvd_handle* h, int64_t token, const float* grad_psi_n, int grad_psi_n_kind,
                           double* const* grad_psf, float* grad_psi0, int grad_kind);
@@ -389,6 +392,15 @@ const char* mvd_last_error(const mvd_handle* h);
  * the padded window; out_dims (may be NULL) receives its {kx, ky, kz}. */
 int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_dims, int v,
                         int variant, double* out, int* out_dims);
+
+/* Adjoint of mvd_compound_kernel (FP64, host): given kbar = dL/dK_v on the
+ * padded odd window of P_v, grad_out[w] (n_views pointers, each the padded
+ * odd window of P_w, kx*ky*kz doubles) receives dL/dP_w with respect to the
+ * normalised PSFs (before the normalisation's own Jacobian), for every w
+ * (zero where K_v does not depend on P_w).  The back-propagation of the
+ * construction of eq. 222 (EFF), eq. 230 (OPT1) and eq. 240 (OPT2). */
+int mvd_compound_kernel_vjp(int n_views, const float* const* psfs, const int* psf_dims, int v, int variant,
+                            const double* kbar, double* const* grad_out);
 
 /* Spectrum of a centred odd kernel on the volume grid, as the handle stores
  * it: H[kz][ky][kx] = (1/V) sum_d K[c+d] exp(-2 pi i k.d / n) for

@@ -587,13 +587,13 @@ def compound_kernel_vjp(P, v, variant, Kbar):
              pads[2]:pads[2] + Abar.shape[2]] = Abar
         if variant == EFF:
             # full = g1 * mirror(P_w)
-            g1bar = signal.correlate(fbar, mirror(P[w]), mode="valid", method="direct")
-            gP[w] += mirror(signal.correlate(fbar, g1[w], mode="valid", method="direct"))
+            g1bar = signal.correlate(fbar, mirror(P[w]), mode="valid", method="fft")
+            gP[w] += mirror(signal.correlate(fbar, g1[w], mode="valid", method="fft"))
         else:
             g1bar = fbar
         # g1 = Pv_m * P_w
-        Pv_m_bar = Pv_m_bar + signal.correlate(g1bar, P[w], mode="valid", method="direct")
-        gP[w] += signal.correlate(g1bar, Pv_m, mode="valid", method="direct")
+        Pv_m_bar = Pv_m_bar + signal.correlate(g1bar, P[w], mode="valid", method="fft")
+        gP[w] += signal.correlate(g1bar, Pv_m, mode="valid", method="fft")
     gP[v] += mirror(Pv_m_bar)
     return gP
 

@@ -10,6 +10,9 @@ passes:
     (mvd_forward_recorded) and backward is the library's vector-Jacobian
     product over that record (mvd_backward_recorded), or, if the handle has
     run something else in between, over a recomputed run (mvd_backward).
+n_iter is the number of iterations, or a pair (n, variant) for runs with a
+compound back-projection kernel ("eff", "opt1", "opt2"; the default is RL),
+whose gradients also flow through the kernels' construction.
 psf_from_theta builds the anisotropic Gaussian PSF of a view from
 (sigma_xy, sigma_z) in torch, so gradients reach the PSF parameters through
 autograd.
@@ -24,13 +27,18 @@ import torch
 from . import mvd
 
 
+def _run(n_iter):
+    return (int(n_iter[0]), n_iter[1]) if isinstance(n_iter, (tuple, list)) else (int(n_iter), "rl")
+
+
 class MVDLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, handle, n_iter, psi0, *psfs):
         handle.set_psfs([p.detach().to("cpu", torch.float32).numpy() for p in psfs])
         want_p = any(ctx.needs_input_grad[3:])
         want_psi = ctx.needs_input_grad[2]
-        loss, gp, gpsi = handle.loss_grad(n_iter, psi0, grad_psf=want_p, grad_psi0=want_psi)
+        n, variant = _run(n_iter)
+        loss, gp, gpsi = handle.loss_grad(n, psi0, grad_psf=want_p, grad_psi0=want_psi, variant=variant)
         # gradients come back on the device and in the dtype of each input
         ctx.gp = None if gp is None else [torch.from_numpy(g).to(dtype=p.dtype, device=p.device)
                                           for g, p in zip(gp, psfs)]
@@ -50,8 +58,9 @@ class MVDDeconvolve(torch.autograd.Function):
     def forward(ctx, handle, n_iter, psi0, *psfs):
         host = [p.detach().to("cpu", torch.float32).numpy() for p in psfs]
         handle.set_psfs(host)
-        out, token = handle.forward_recorded(int(n_iter), psi0.detach())
-        ctx.handle, ctx.n_iter, ctx.host, ctx.token = handle, int(n_iter), host, token
+        n, variant = _run(n_iter)
+        out, token = handle.forward_recorded(n, psi0.detach(), variant=variant)
+        ctx.handle, ctx.n_iter, ctx.variant, ctx.host, ctx.token = handle, n, variant, host, token
         ctx.psi0 = psi0.detach()
         ctx.meta = [(p.dtype, p.device) for p in psfs]
         ctx.psi_meta = (psi0.dtype, psi0.device)
@@ -69,7 +78,8 @@ class MVDDeconvolve(torch.autograd.Function):
                 raise
             # the handle ran other work since the forward pass: recompute
             h.set_psfs(ctx.host)
-            gp, gpsi = h.backward(ctx.n_iter, ctx.psi0, gout, grad_psf=want_p, grad_psi0=want_psi)
+            gp, gpsi = h.backward(ctx.n_iter, ctx.psi0, gout, grad_psf=want_p, grad_psi0=want_psi,
+                                  variant=ctx.variant)
         gps = (None,) * len(ctx.meta) if gp is None else \
             tuple(torch.from_numpy(g).to(dtype=dt, device=dev) for g, (dt, dev) in zip(gp, ctx.meta))
         if gpsi is not None:

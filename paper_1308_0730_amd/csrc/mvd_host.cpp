@@ -224,6 +224,122 @@ Kern compound_kernel(const std::vector<Kern>& P, int v, int variant) {
   return K;
 }
 
+std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P, int v, int variant,
+                                                     const std::vector<double>& Kbar) {
+  const int n = (int)P.size();
+  std::vector<std::vector<double>> g(n);
+  for (int w = 0; w < n; ++w) g[w].assign(P[w].a.size(), 0.0);
+  const Kern Mv = mirror(P[v]);
+  if (Kbar.size() != Mv.a.size()) throw std::invalid_argument("Kbar does not have the kernel's window");
+  // dst += mirror(src) on the window of P[v]
+  auto add_mirror_v = [&](std::vector<double>& dst, const std::vector<double>& src) {
+    Kern t = Mv;
+    t.a = src;
+    const Kern m = mirror(t);
+    for (size_t i = 0; i < dst.size(); ++i) dst[i] += m.a[i];
+  };
+  if (variant == 0 || n == 1) {
+    add_mirror_v(g[v], Kbar);
+    return g;
+  }
+  const size_t nk = Mv.a.size();
+  if (variant == 3) {
+    // K = U / sum U with U = Mv^n
+    std::vector<double> U(nk);
+    double S = 0;
+    for (size_t i = 0; i < nk; ++i) S += (U[i] = std::pow(Mv.a[i], n));
+    double kk = 0;
+    for (size_t i = 0; i < nk; ++i) kk += Kbar[i] * U[i] / S;
+    std::vector<double> Mbar(nk);
+    for (size_t i = 0; i < nk; ++i) Mbar[i] = (Kbar[i] - kk) / S * n * std::pow(Mv.a[i], n - 1);
+    add_mirror_v(g[v], Mbar);
+    return g;
+  }
+  if (variant != 1 && variant != 2) throw std::invalid_argument("unknown variant");
+  const bool eff = variant == 1;
+  int mx = 0, my = 0, mz = 0;
+  for (int w = 0; w < n; ++w) {
+    mx = std::max(mx, P[w].kx);
+    my = std::max(my, P[w].ky);
+    mz = std::max(mz, P[w].kz);
+  }
+  // large enough that circular equals linear for the correlations below
+  const int gx = P[v].kx + 2 * mx, gy = P[v].ky + 2 * my, gz = P[v].kz + 2 * mz;
+  const std::vector<cd> Fv = dft_grid(P[v], gx, gy, gz);
+  std::vector<std::vector<cd>> Sw(n);
+  std::vector<std::vector<double>> fac(n);
+  parallel_for(n, [&](int w) {
+    if (w == v) return;
+    Sw[w] = dft_grid(P[w], gx, gy, gz);
+    std::vector<cd> X(Fv.size());
+    for (size_t i = 0; i < X.size(); ++i) {
+      cd s = std::conj(Fv[i]) * Sw[w][i];  // P_v* (x) P_w
+      if (eff) s *= std::conj(Sw[w][i]);   // (x) P_w*
+      X[i] = s;
+    }
+    fac[w] = idft_window(X, gx, gy, gz, Mv.kx, Mv.ky, Mv.kz);
+  });
+  // K = U / sum U, U = Mv . prod_w fac_w
+  std::vector<double> U = Mv.a;
+  for (int w = 0; w < n; ++w)
+    if (w != v)
+      for (size_t i = 0; i < nk; ++i) U[i] *= fac[w][i];
+  double S = 0;
+  for (double x : U) S += x;
+  double kk = 0;
+  for (size_t i = 0; i < nk; ++i) kk += Kbar[i] * U[i] / S;
+  std::vector<double> Ubar(nk);
+  for (size_t i = 0; i < nk; ++i) Ubar[i] = (Kbar[i] - kk) / S;
+  // the direct factor Mv
+  std::vector<double> Mbar_v(nk);
+  for (size_t i = 0; i < nk; ++i) {
+    double p = Ubar[i];
+    for (int w = 0; w < n; ++w)
+      if (w != v) p *= fac[w][i];
+    Mbar_v[i] = p;
+  }
+  // each partner factor fac_w = crop(Mv (x) P_w (x) Mw) (EFF) or crop(Mv (x) P_w)
+  // (OPT1): with T = dL/dfac_w, the correlations of T with the other operands
+  std::vector<std::vector<double>> mv_part(n), pw_part(n), mw_part(n);
+  parallel_for(n, [&](int w) {
+    if (w == v) return;
+    Kern T = Mv;
+    for (size_t i = 0; i < nk; ++i) {
+      double p = Ubar[i] * Mv.a[i];
+      for (int u = 0; u < n; ++u)
+        if (u != v && u != w) p *= fac[u][i];
+      T.a[i] = p;
+    }
+    const std::vector<cd> Th = dft_grid(T, gx, gy, gz);
+    std::vector<cd> X(Th.size());
+    // Mv: correlation with P_w (x) Mw (EFF, a real spectrum |S_w|^2) or P_w
+    for (size_t i = 0; i < X.size(); ++i)
+      X[i] = eff ? Th[i] * std::norm(Sw[w][i]) : Th[i] * std::conj(Sw[w][i]);
+    mv_part[w] = idft_window(X, gx, gy, gz, Mv.kx, Mv.ky, Mv.kz);
+    // P_w: correlation with Mv (x) Mw (EFF) or Mv
+    for (size_t i = 0; i < X.size(); ++i) X[i] = eff ? Th[i] * Fv[i] * Sw[w][i] : Th[i] * Fv[i];
+    pw_part[w] = idft_window(X, gx, gy, gz, P[w].kx, P[w].ky, P[w].kz);
+    if (eff) {
+      // Mw: correlation with Mv (x) P_w
+      for (size_t i = 0; i < X.size(); ++i) X[i] = Th[i] * Fv[i] * std::conj(Sw[w][i]);
+      mw_part[w] = idft_window(X, gx, gy, gz, P[w].kx, P[w].ky, P[w].kz);
+    }
+  });
+  for (int w = 0; w < n; ++w) {
+    if (w == v) continue;
+    for (size_t i = 0; i < nk; ++i) Mbar_v[i] += mv_part[w][i];
+    for (size_t i = 0; i < g[w].size(); ++i) g[w][i] += pw_part[w][i];
+    if (eff) {
+      Kern t = P[w];
+      t.a = mw_part[w];
+      const Kern m = mirror(t);
+      for (size_t i = 0; i < g[w].size(); ++i) g[w][i] += m.a[i];
+    }
+  }
+  add_mirror_v(g[v], Mbar_v);
+  return g;
+}
+
 std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny) {
   const int M = nx / 2;
   const auto tx = twiddles(nx), ty = twiddles(ny);

@@ -34,6 +34,13 @@ Kern mirror(const Kern& k);
 // convolution, then cropped to the window.
 Kern compound_kernel(const std::vector<Kern>& P, int v, int variant);
 
+// Adjoint of compound_kernel: given Kbar = dL/dK_v on K_v's window (the
+// window of P_v), dL/dP_w for every prepared PSF (same extents as P[w].a;
+// zero for PSFs K_v does not depend on).  FP64, by the same direct DFTs on
+// a grid where circular equals linear convolution.
+std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P, int v, int variant,
+                                                     const std::vector<double>& Kbar);
+
 // Stages x and y of the spectrum of a centred kernel on a volume grid:
 // A2[dz][ky][kx], kx in [0, nx/2], for every kernel plane dz.
 std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny);

@@ -184,6 +184,7 @@ struct mvd_handle {
   float *g_b = nullptr, *g_q = nullptr, *g_c = nullptr, *g_psi = nullptr;  // [view][V]
   float2 *g_spsi = nullptr, *g_sq = nullptr, *g_sT = nullptr;  // spectra [view][spec]
   double2* g_acc = nullptr;                // PSF cross-spectra [view][spec], FP64
+  double2* g_acck = nullptr;               // compound variants: back-projection kernel cross-spectra
   float *g_gbar = nullptr, *g_part = nullptr, *g_psiT = nullptr;
   Partial* g_parts = nullptr;              // [view][x tiles]
   double* g_loss = nullptr;
@@ -1544,17 +1545,23 @@ void grad_y(mvd_handle* h, int inv, int v) {
     HIPCHECK(mvd_launch_y(args(h, h->stream, h->rt_grid[1]), h->rt_cfg[1], inv, v));
 }
 
-void grad_zext(mvd_handle* h, int v, int conjH, float2* s_out, const float2* s_in, double2* acc, int acc_mode) {
+void grad_zext(mvd_handle* h, int v, int conjH, float2* s_out, const float2* s_in, double2* acc, int acc_mode,
+               int role = ROLE_P) {
   const int nz = h->blocks[0].nz, p = mvd_exact_param(PASS_Z, nz);
   if (p > 0)
-    HIPCHECK(mvd_launch_zext_exact(args(h, h->stream, mvd_tiles(h->jobs[0], PASS_Z, p)), nz, v, ROLE_P, conjH, s_out,
+    HIPCHECK(mvd_launch_zext_exact(args(h, h->stream, mvd_tiles(h->jobs[0], PASS_Z, p)), nz, v, role, conjH, s_out,
                                    s_in, acc, acc_mode));
   else
-    HIPCHECK(mvd_launch_zext(args(h, h->stream, h->rt_grid[2]), h->rt_cfg[2], v, ROLE_P, conjH, s_out, s_in, acc,
+    HIPCHECK(mvd_launch_zext(args(h, h->stream, h->rt_grid[2]), h->rt_cfg[2], v, role, conjH, s_out, s_in, acc,
                              acc_mode));
 }
 
-void grad_forward_view(mvd_handle* h, int v) {
+// The back-projection kernel of a variant as the z pass applies it: RL the
+// conjugated PSF spectrum (K_v = P_v*), otherwise the compound spectrum.
+int back_role(int variant) { return variant == MVD_RL ? ROLE_P : variant; }
+int back_conj(int variant) { return variant == MVD_RL ? 1 : 0; }
+
+void grad_forward_view(mvd_handle* h, int v, int variant) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
   const AdjPtrs ap = adj_ptrs(h, v);
@@ -1564,22 +1571,28 @@ void grad_forward_view(mvd_handle* h, int v) {
   grad_y(h, 1, v);
   grad_x(h, 3, v, parts, ap);
   grad_y(h, 0, v);
-  grad_zext(h, v, 1, h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0);
+  grad_zext(h, v, back_conj(variant), h->g_sq + (size_t)v * B.spec_elems, nullptr, nullptr, 0, back_role(variant));
   grad_y(h, 1, v);
   grad_x(h, 4, v, parts, ap);
 }
 
 // Adjoint of view-update v: g_gbar holds dL/dpsi' on entry and dL/dpsi on exit.
-void grad_adjoint_view(mvd_handle* h, int v) {
+// The back-projection's kernel term conj(Cbar) Q goes to the PSF's
+// cross-spectrum for RL (K_v = P_v*: the mirrored term is a PSF gradient)
+// and to the kernel's own cross-spectrum for the compound variants.
+void grad_adjoint_view(mvd_handle* h, int v, int variant) {
   const Block& B = h->blocks[0];
   hipStream_t s = h->stream;
   const AdjPtrs ap = adj_ptrs(h, v);
   double2* acc = h->g_acc + (size_t)v * B.spec_elems;
+  double2* acck = variant == MVD_RL ? acc : h->g_acck + (size_t)v * B.spec_elems;
   // cbar and the direct part of psibar
   grad_x(h, 5, v, nullptr, ap);
-  // qbar = cbar (x) P_v, with A_v += conj(Cbar) Q
+  // qbar = cbar (x) K_v* (the adjoint of the back-projection), with
+  // acc += conj(Cbar) Q
   grad_y(h, 0, v);
-  grad_zext(h, v, 0, nullptr, h->g_sq + (size_t)v * B.spec_elems, acc, 1);
+  grad_zext(h, v, 1 - back_conj(variant), nullptr, h->g_sq + (size_t)v * B.spec_elems, acck, 1,
+            back_role(variant));
   grad_y(h, 1, v);
   // bbar
   grad_x(h, 6, v, nullptr, ap);
@@ -1613,13 +1626,17 @@ void grad_forward_impl(mvd_handle* h, int n, int variant, const float* psi0, int
   if (h->blocks.size() != 1) throw Error(MVD_ESTATE, "the differentiated form takes a single-block handle");
   if (h->linear) throw Error(MVD_ESTATE, "the differentiated form runs with the circular boundary only");
   if (h->blocked) throw Error(MVD_ESTATE, "the block-wise form runs the sequential scheme only");
-  if (variant != MVD_RL) bad("gradients are available for MVD_RL");
+  if (variant < MVD_RL || variant > MVD_OPT2) bad("variant must be MVD_RL, MVD_EFF, MVD_OPT1 or MVD_OPT2");
   if (n < 0) bad("n must be >= 0");
   Block& B = h->blocks[0];
   const size_t V = B.V;
   hipStream_t st = h->stream;
   h->rec_token = 0;
   grad_setup(h, std::max(n, 1));
+  if (variant != MVD_RL) {
+    ensure_role(h, back_role(variant));
+    if (!h->g_acck) h->g_acck = (double2*)h->dalloc((size_t)h->nviews * B.spec_elems * sizeof(double2));
+  }
   if (psi0) {
     HIPCHECK(hipStreamSynchronize(st));
     set_estimate_impl(h, psi0, psi0_kind, 0);
@@ -1630,7 +1647,7 @@ void grad_forward_impl(mvd_handle* h, int n, int variant, const float* psi0, int
   x_init_rt(h);
   for (int i = 0; i < n; ++i) {
     HIPCHECK(hipMemcpyAsync(h->g_ckpt + (size_t)i * V, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
-    for (int v = 0; v < h->nviews; ++v) grad_forward_view(h, v);
+    for (int v = 0; v < h->nviews; ++v) grad_forward_view(h, v, variant);
   }
   HIPCHECK(hipMemcpyAsync(h->g_psiT, B.psi, V * sizeof(float), hipMemcpyDeviceToDevice, st));
   h->inter_iter = n - 1;
@@ -1656,10 +1673,10 @@ void grad_reverse_impl(mvd_handle* h, double* const* grad_psf, float* grad_psi0,
     if (i != h->inter_iter) {
       HIPCHECK(hipMemcpyAsync(B.psi, h->g_ckpt + (size_t)i * V, V * sizeof(float), hipMemcpyDeviceToDevice, st));
       x_init_rt(h);
-      for (int v = 0; v < N; ++v) grad_forward_view(h, v);
+      for (int v = 0; v < N; ++v) grad_forward_view(h, v, h->rec_variant);
       h->inter_iter = i;
     }
-    for (int v = N - 1; v >= 0; --v) grad_adjoint_view(h, v);
+    for (int v = N - 1; v >= 0; --v) grad_adjoint_view(h, v, h->rec_variant);
   }
   if (grad_psi0)
     HIPCHECK(hipMemcpyAsync(grad_psi0, h->g_gbar, V * sizeof(float),
@@ -1692,16 +1709,40 @@ void grad_reverse_impl(mvd_handle* h, double* const* grad_psf, float* grad_psi0,
     grow(h->g_t2, h->g_t2_cap, t2n, sizeof(double2));
     grow(h->g_gw, h->g_gw_cap, gn, sizeof(double));
     const double invV = 1.0 / (double)B.V;
-    for (int v = 0; v < N; ++v) {
-      if (!grad_psf[v]) continue;
-      const mvdh::Kern& P = B.P[v];
-      HIPCHECK(mvd_launch_idft_z(h->g_acc + (size_t)v * S, B.M, B.Mp, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
+    // a cross-spectrum's windowed inverse DFT on the window of P_v
+    auto window_of = [&](const double2* A, const mvdh::Kern& P) {
+      HIPCHECK(mvd_launch_idft_z(A, B.M, B.Mp, B.ny, B.nz, P.kz, h->g_twz, h->g_t1, st));
       HIPCHECK(mvd_launch_idft_yx(h->g_t1, B.M, B.nx, B.ny, P.kx, P.ky, P.kz, h->g_twx, h->g_twy, h->g_t2,
                                   h->g_gw, st));
       std::vector<double> g((size_t)P.kx * P.ky * P.kz);
       HIPCHECK(hipMemcpyAsync(g.data(), h->g_gw, g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHECK(hipStreamSynchronize(st));
       for (double& x : g) x *= invV;
+      return g;
+    };
+    // dL/dP_v on the padded boxes: the blur terms (and for RL the mirrored
+    // back-projection terms) ...
+    const bool compound = h->rec_variant != MVD_RL;
+    std::vector<std::vector<double>> gP(N);
+    for (int v = 0; v < N; ++v)
+      if (grad_psf[v] || compound) gP[v] = window_of(h->g_acc + (size_t)v * S, B.P[v]);
+    // ... and for the compound variants the kernel gradients (the
+    // accumulated term is the mirrored dL/dK_v) through the construction of
+    // every K_v from all PSFs
+    if (compound) {
+      for (int v = 0; v < N; ++v) {
+        mvdh::Kern t = B.P[v];
+        t.a = window_of(h->g_acck + (size_t)v * S, B.P[v]);
+        const mvdh::Kern Kbar = mvdh::mirror(t);
+        const auto add = mvdh::compound_kernel_vjp(B.P, v, h->rec_variant, Kbar.a);
+        for (int w = 0; w < N; ++w)
+          for (size_t j = 0; j < add[w].size(); ++j) gP[w][j] += add[w][j];
+      }
+    }
+    for (int v = 0; v < N; ++v) {
+      if (!grad_psf[v]) continue;
+      const mvdh::Kern& P = B.P[v];
+      const std::vector<double>& g = gP[v];
       // through the normalisation P = G / sum G, then drop the odd padding
       double dot = 0;
       for (size_t j = 0; j < g.size(); ++j) dot += g[j] * P.a[j];
@@ -1739,6 +1780,7 @@ void loss_grad_impl(mvd_handle* h, int n, int variant, const float* psi0, int ps
   // loss sum_v |psi_T (x) P_v - phi_v|^2 and its adjoint seed, or the
   // caller's seed
   HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)N * S * sizeof(double2), st));
+  if (h->g_acck) HIPCHECK(hipMemsetAsync(h->g_acck, 0, (size_t)N * S * sizeof(double2), st));
   if (seed)
     HIPCHECK(hipMemcpyAsync(h->g_gbar, seed, V * sizeof(float),
                             seed_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
@@ -1793,6 +1835,7 @@ void backward_recorded_impl(mvd_handle* h, int64_t token, const float* seed, int
   const size_t V = B.V, S = B.spec_elems;
   hipStream_t st = h->stream;
   HIPCHECK(hipMemsetAsync(h->g_acc, 0, (size_t)h->nviews * S * sizeof(double2), st));
+  if (h->g_acck) HIPCHECK(hipMemsetAsync(h->g_acck, 0, (size_t)h->nviews * S * sizeof(double2), st));
   HIPCHECK(hipMemcpyAsync(h->g_gbar, seed, V * sizeof(float),
                           seed_kind == MVD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
   grad_reverse_impl(h, grad_psf, grad_psi0, grad_kind);
@@ -2480,6 +2523,29 @@ int mvd_compound_kernel(int n_views, const float* const* psfs, const int* psf_di
       out_dims[1] = K.ky;
       out_dims[2] = K.kz;
     }
+  });
+}
+
+int mvd_compound_kernel_vjp(int n_views, const float* const* psfs, const int* psf_dims, int v, int variant,
+                            const double* kbar, double* const* grad_out) {
+  return guard(nullptr, [&] {
+    if (n_views < 1 || n_views > MVD_MAX_VIEWS) bad("n_views must be in [1, 64]");
+    if (!psfs || !psf_dims || !kbar || !grad_out) bad("psfs, psf_dims, kbar and grad_out are required");
+    if (v < 0 || v >= n_views) bad("v out of range");
+    if (variant < MVD_RL || variant > MVD_OPT2) bad("unknown variant");
+    std::vector<mvdh::Kern> P;
+    for (int i = 0; i < n_views; ++i) {
+      if (!psfs[i] || !grad_out[i]) bad("PSF or gradient pointer is NULL");
+      const int* k = psf_dims + 3 * i;
+      try {
+        P.push_back(mvdh::prepare_psf(psfs[i], k[0], k[1], k[2]));
+      } catch (const std::invalid_argument& e) {
+        bad(e.what());
+      }
+    }
+    const std::vector<double> kb(kbar, kbar + P[v].a.size());
+    const auto g = mvdh::compound_kernel_vjp(P, v, variant, kb);
+    for (int i = 0; i < n_views; ++i) std::memcpy(grad_out[i], g[i].data(), g[i].size() * sizeof(double));
   });
 }
 

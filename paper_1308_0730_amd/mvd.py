@@ -90,6 +90,8 @@ def lib():
     L.mvd_last_error.restype = C.c_char_p
     L.mvd_compound_kernel.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int, C.c_int,
                                       C.c_void_p, C.POINTER(C.c_int)]
+    L.mvd_compound_kernel_vjp.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_int), C.c_int, C.c_int,
+                                          C.c_void_p, C.POINTER(C.c_void_p)]
     L.mvd_kernel_spectrum.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]
     L.mvd_create_blocked.argtypes = [C.POINTER(H), C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]
@@ -110,7 +112,7 @@ def lib():
                  "mvd_view_update", "mvd_profile", "mvd_set_tiles", "mvd_get_tiles", "mvd_tile_candidates",
                  "mvd_tile_shape", "mvd_loss_grad", "mvd_backward", "mvd_set_psfs", "mvd_iterate_noalloc",
                  "mvd_create_blocked", "mvd_blocking", "mvd_set_schedule", "mvd_get_schedule",
-                 "mvd_forward_recorded", "mvd_backward_recorded"):
+                 "mvd_forward_recorded", "mvd_backward_recorded", "mvd_compound_kernel_vjp"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -339,20 +341,20 @@ class Deconvolver:
         self._psf_shapes = [p.shape for p in ps]
         return self
 
-    def loss_grad(self, n, psi0=None, grad_psf=True, grad_psi0=True, psf_shapes=None):
+    def loss_grad(self, n, psi0=None, grad_psf=True, grad_psi0=True, psf_shapes=None, variant="rl"):
         """Loss sum_v |psi_n (x) P_v - phi_v|^2 after n RL iterations from psi0
         (None: flat start) and, optionally, its gradients: a list of float64
         arrays shaped like the PSFs, and a CUDA tensor shaped like the volume.
         Returns (loss, grad_psfs or None, grad_psi0 or None)."""
         src, gps, gp_ptrs, gpsi = self._grad_buffers(psi0, grad_psf, grad_psi0, psf_shapes)
         loss = C.c_double()
-        rc = lib().mvd_loss_grad(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
+        rc = lib().mvd_loss_grad(self._h, int(n), _variant(variant), None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
                                  C.byref(loss), _ptr_array(gp_ptrs),
                                  None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
         _check(rc, self._h)
         return loss.value, gps, gpsi
 
-    def backward(self, n, psi0, grad_psi_n, grad_psf=True, grad_psi0=True, psf_shapes=None):
+    def backward(self, n, psi0, grad_psi_n, grad_psf=True, grad_psi0=True, psf_shapes=None, variant="rl"):
         """Vector-Jacobian product of n RL iterations from psi0 (None: flat
         start): for grad_psi_n = dL/dpsi_n of any scalar L, returns
         (dL/dpsf list of float64 arrays or None, dL/dpsi0 CUDA tensor or None).
@@ -363,19 +365,19 @@ class Deconvolver:
             else torch.from_numpy(np.ascontiguousarray(np.asarray(grad_psi_n, np.float32))).to(self.device)
         if tuple(g.shape) != (nz, ny, nx):
             raise ValueError(f"grad_psi_n has shape {tuple(g.shape)}, expected {(nz, ny, nx)}")
-        rc = lib().mvd_backward(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
+        rc = lib().mvd_backward(self._h, int(n), _variant(variant), None if src is None else C.c_void_p(src.data_ptr()), MEM_DEVICE,
                                 C.c_void_p(g.data_ptr()), MEM_DEVICE, _ptr_array(gp_ptrs),
                                 None if gpsi is None else C.c_void_p(gpsi.data_ptr()), MEM_DEVICE)
         _check(rc, self._h)
         return gps, gpsi
 
-    def forward_recorded(self, n, psi0=None):
+    def forward_recorded(self, n, psi0=None, variant="rl"):
         """n RL iterations from psi0 (None: flat start) with one checkpoint
         per iteration; returns (psi_n as a CUDA tensor, token of the
         recorded run for backward_recorded)."""
         src, _, _, _ = self._grad_buffers(psi0, False, False, None)
         tok = C.c_int64()
-        rc = lib().mvd_forward_recorded(self._h, int(n), RL, None if src is None else C.c_void_p(src.data_ptr()),
+        rc = lib().mvd_forward_recorded(self._h, int(n), _variant(variant), None if src is None else C.c_void_p(src.data_ptr()),
                                         MEM_DEVICE, C.byref(tok))
         _check(rc, self._h)
         return self.estimate(), tok.value
@@ -539,6 +541,22 @@ def compound_kernel(psfs, v, variant):
                                    _variant(variant), out.ctypes.data, od)
     _check(rc)
     return out
+
+
+def compound_kernel_vjp(psfs, v, variant, kbar):
+    """dL/dP_w (normalised, odd-padded PSFs) of every view from dL/dK_v, by
+    the library's host code (FP64)."""
+    ps = [np.ascontiguousarray(np.asarray(p, np.float32)) for p in psfs]
+    n = len(ps)
+    ptrs = (C.c_void_p * n)(*[p.ctypes.data for p in ps])
+    dims = (C.c_int * (3 * n))(*sum([[p.shape[2], p.shape[1], p.shape[0]] for p in ps], []))
+    kb = np.ascontiguousarray(np.asarray(kbar, np.float64))
+    outs = [np.zeros((p.shape[0] | 1, p.shape[1] | 1, p.shape[2] | 1), np.float64) for p in ps]
+    optrs = (C.c_void_p * n)(*[o.ctypes.data for o in outs])
+    rc = lib().mvd_compound_kernel_vjp(n, C.cast(ptrs, C.POINTER(C.c_void_p)), C.cast(dims, C.POINTER(C.c_int)), v,
+                                       _variant(variant), kb.ctypes.data, C.cast(optrs, C.POINTER(C.c_void_p)))
+    _check(rc)
+    return outs
 
 
 def kernel_spectrum(K, dims):

@@ -229,3 +229,46 @@ def test_recorded_backward_equals_backward(mvd):
         with pytest.raises(mvd.MVDError) as e:
             d.backward_recorded(tok, g1)
         assert e.value.code == mvd.MVD_ESTATE
+
+
+@pytest.mark.parametrize("variant", [O.EFF, O.OPT1, O.OPT2])
+def test_compound_variant_gradients_match_oracle(mvd, variant):
+    """Runs with compound back-projection kernels: loss and gradients, and
+    the vector-Jacobian product, against the oracle's (whose kernel
+    gradients go through the construction of eq. 222/230/240; pinned by
+    finite differences), with weights and lambda."""
+    s, psfs, w, psi0, rng = grad_case(True)
+    n = 2
+    L, gpsi, gP = O.loss_and_grad(s.views, psfs, n, psi0.astype(np.float64), w, 0.02, variant)
+    gbar = rng.normal(size=psi0.shape).astype(np.float32)
+    psi_n, vpsi, vP = O.vjp(s.views, psfs, n, psi0.astype(np.float64), gbar.astype(np.float64), w, 0.02, variant)
+    with mvd.Deconvolver(s.views, psfs, w, lam=0.02) as d:
+        l2, gp2, gpsi2 = d.loss_grad(n, psi0, variant=variant)
+        vp2, vpsi2 = d.backward(n, psi0, gbar, variant=variant)
+        e = d.estimate().cpu().numpy()
+    print(f"loss {l2:.8e} vs {L:.8e}; psi0 grad rel {rel(gpsi2.cpu().numpy(), gpsi):.2e}; "
+          f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gp2, gP)]}; "
+          f"vjp psi0 {rel(vpsi2.cpu().numpy(), vpsi):.2e} psf {[f'{rel(a, b):.2e}' for a, b in zip(vp2, vP)]}")
+    assert abs(l2 - L) <= 1e-5 * L
+    assert rel(e, psi_n) <= 1e-5
+    assert rel(gpsi2.cpu().numpy(), gpsi) <= GRAD and rel(vpsi2.cpu().numpy(), vpsi) <= GRAD
+    for a, b in zip(gp2 + vp2, gP + vP):
+        assert rel(a, b) <= GRAD
+
+
+def test_config5_efficient_update_gradient(mvd):
+    """The 128^3 four-view workload with 25^3 PSFs, 8 iterations of the
+    efficient update (EFF, eq. 222): loss, PSF and psi0 gradients against the
+    FP64 oracle (<= 1e-4)."""
+    s = synth.config5()
+    psi0 = np.full(s.views[0].shape, float(np.mean([v.mean() for v in s.views])), np.float32)
+    with mvd.Deconvolver(s.views, s.psfs) as d:
+        L2, gP2, gpsi2 = d.loss_grad(8, psi0, variant=O.EFF)
+        gpsi2 = gpsi2.cpu().numpy()
+    Lo, gpsio, gPo = O.loss_and_grad(s.views, s.psfs, 8, psi0.astype(np.float64), variant=O.EFF)
+    print(f"loss {L2:.8e} vs {Lo:.8e}; psi0 grad rel {rel(gpsi2, gpsio):.2e}; "
+          f"psf grad rel {[f'{rel(a, b):.2e}' for a, b in zip(gP2, gPo)]}")
+    assert abs(L2 - Lo) <= 1e-4 * Lo
+    assert rel(gpsi2, gpsio) <= 1e-4
+    for a, b in zip(gP2, gPo):
+        assert rel(a, b) <= 1e-4
