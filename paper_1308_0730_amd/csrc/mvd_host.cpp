@@ -224,35 +224,42 @@ Kern compound_kernel(const std::vector<Kern>& P, int v, int variant) {
   return K;
 }
 
-std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P, int v, int variant,
-                                                     const std::vector<double>& Kbar) {
+std::vector<std::vector<double>> compound_kernels_vjp(const std::vector<Kern>& P, int variant,
+                                                      const std::vector<std::vector<double>>& Kbar) {
   const int n = (int)P.size();
   std::vector<std::vector<double>> g(n);
   for (int w = 0; w < n; ++w) g[w].assign(P[w].a.size(), 0.0);
-  const Kern Mv = mirror(P[v]);
-  if (Kbar.size() != Mv.a.size()) throw std::invalid_argument("Kbar does not have the kernel's window");
+  if ((int)Kbar.size() != n) throw std::invalid_argument("one Kbar per view");
+  for (int v = 0; v < n; ++v)
+    if (!Kbar[v].empty() && Kbar[v].size() != P[v].a.size())
+      throw std::invalid_argument("Kbar does not have the kernel's window");
   // dst += mirror(src) on the window of P[v]
-  auto add_mirror_v = [&](std::vector<double>& dst, const std::vector<double>& src) {
-    Kern t = Mv;
+  auto add_mirror = [&](std::vector<double>& dst, const Kern& shape, const std::vector<double>& src) {
+    Kern t = shape;
     t.a = src;
     const Kern m = mirror(t);
     for (size_t i = 0; i < dst.size(); ++i) dst[i] += m.a[i];
   };
   if (variant == 0 || n == 1) {
-    add_mirror_v(g[v], Kbar);
+    for (int v = 0; v < n; ++v)
+      if (!Kbar[v].empty()) add_mirror(g[v], P[v], Kbar[v]);
     return g;
   }
-  const size_t nk = Mv.a.size();
   if (variant == 3) {
     // K = U / sum U with U = Mv^n
-    std::vector<double> U(nk);
-    double S = 0;
-    for (size_t i = 0; i < nk; ++i) S += (U[i] = std::pow(Mv.a[i], n));
-    double kk = 0;
-    for (size_t i = 0; i < nk; ++i) kk += Kbar[i] * U[i] / S;
-    std::vector<double> Mbar(nk);
-    for (size_t i = 0; i < nk; ++i) Mbar[i] = (Kbar[i] - kk) / S * n * std::pow(Mv.a[i], n - 1);
-    add_mirror_v(g[v], Mbar);
+    for (int v = 0; v < n; ++v) {
+      if (Kbar[v].empty()) continue;
+      const Kern Mv = mirror(P[v]);
+      const size_t nk = Mv.a.size();
+      std::vector<double> U(nk);
+      double S = 0;
+      for (size_t i = 0; i < nk; ++i) S += (U[i] = std::pow(Mv.a[i], n));
+      double kk = 0;
+      for (size_t i = 0; i < nk; ++i) kk += Kbar[v][i] * U[i] / S;
+      std::vector<double> Mbar(nk);
+      for (size_t i = 0; i < nk; ++i) Mbar[i] = (Kbar[v][i] - kk) / S * n * std::pow(Mv.a[i], n - 1);
+      add_mirror(g[v], P[v], Mbar);
+    }
     return g;
   }
   if (variant != 1 && variant != 2) throw std::invalid_argument("unknown variant");
@@ -263,81 +270,114 @@ std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P,
     my = std::max(my, P[w].ky);
     mz = std::max(mz, P[w].kz);
   }
-  // large enough that circular equals linear for the correlations below
-  const int gx = P[v].kx + 2 * mx, gy = P[v].ky + 2 * my, gz = P[v].kz + 2 * mz;
-  const std::vector<cd> Fv = dft_grid(P[v], gx, gy, gz);
-  std::vector<std::vector<cd>> Sw(n);
-  std::vector<std::vector<double>> fac(n);
-  parallel_for(n, [&](int w) {
-    if (w == v) return;
-    Sw[w] = dft_grid(P[w], gx, gy, gz);
-    std::vector<cd> X(Fv.size());
-    for (size_t i = 0; i < X.size(); ++i) {
-      cd s = std::conj(Fv[i]) * Sw[w][i];  // P_v* (x) P_w
-      if (eff) s *= std::conj(Sw[w][i]);   // (x) P_w*
-      X[i] = s;
-    }
-    fac[w] = idft_window(X, gx, gy, gz, Mv.kx, Mv.ky, Mv.kz);
+  // Per view v, one grid on which circular equals linear convolution for
+  // every term below: the autocorrelation P_w (x) P_w* fits (2 k_max - 1),
+  // and the window of K_v correlated with a partner term of radius up to
+  // r_v + r_w (or 2 r_w) never wraps (k_v + k_max).
+  struct Grid {
+    int x, y, z;
+  };
+  std::vector<Grid> grid(n);
+  for (int v = 0; v < n; ++v)
+    grid[v] = {std::max(P[v].kx + mx, 2 * mx - 1), std::max(P[v].ky + my, 2 * my - 1),
+               std::max(P[v].kz + mz, 2 * mz - 1)};
+  // spectra of every PSF on every view's grid, and the partner factors
+  std::vector<std::vector<std::vector<cd>>> Sp(n, std::vector<std::vector<cd>>(n));
+  parallel_for(n * n, [&](int i) {
+    const int v = i / n, w = i % n;
+    if (!Kbar[v].empty()) Sp[v][w] = dft_grid(P[w], grid[v].x, grid[v].y, grid[v].z);
   });
-  // K = U / sum U, U = Mv . prod_w fac_w
-  std::vector<double> U = Mv.a;
-  for (int w = 0; w < n; ++w)
-    if (w != v)
-      for (size_t i = 0; i < nk; ++i) U[i] *= fac[w][i];
-  double S = 0;
-  for (double x : U) S += x;
-  double kk = 0;
-  for (size_t i = 0; i < nk; ++i) kk += Kbar[i] * U[i] / S;
-  std::vector<double> Ubar(nk);
-  for (size_t i = 0; i < nk; ++i) Ubar[i] = (Kbar[i] - kk) / S;
-  // the direct factor Mv
-  std::vector<double> Mbar_v(nk);
-  for (size_t i = 0; i < nk; ++i) {
-    double p = Ubar[i];
-    for (int w = 0; w < n; ++w)
-      if (w != v) p *= fac[w][i];
-    Mbar_v[i] = p;
-  }
-  // each partner factor fac_w = crop(Mv (x) P_w (x) Mw) (EFF) or crop(Mv (x) P_w)
-  // (OPT1): with T = dL/dfac_w, the correlations of T with the other operands
-  std::vector<std::vector<double>> mv_part(n), pw_part(n), mw_part(n);
-  parallel_for(n, [&](int w) {
-    if (w == v) return;
-    Kern T = Mv;
-    for (size_t i = 0; i < nk; ++i) {
-      double p = Ubar[i] * Mv.a[i];
-      for (int u = 0; u < n; ++u)
-        if (u != v && u != w) p *= fac[u][i];
-      T.a[i] = p;
+  std::vector<std::vector<std::vector<double>>> fac(n, std::vector<std::vector<double>>(n));
+  parallel_for(n * n, [&](int i) {
+    const int v = i / n, w = i % n;
+    if (w == v || Kbar[v].empty()) return;
+    const auto& Fv = Sp[v][v];
+    const auto& Sw = Sp[v][w];
+    std::vector<cd> X(Fv.size());
+    for (size_t k = 0; k < X.size(); ++k) {
+      cd t = std::conj(Fv[k]) * Sw[k];  // P_v* (x) P_w
+      if (eff) t *= std::conj(Sw[k]);   // (x) P_w*
+      X[k] = t;
     }
-    const std::vector<cd> Th = dft_grid(T, gx, gy, gz);
+    fac[v][w] = idft_window(X, grid[v].x, grid[v].y, grid[v].z, P[v].kx, P[v].ky, P[v].kz);
+  });
+  // K_v = U / sum U, U = Mv . prod_w fac_w: dL/dU, and the direct factor's term
+  std::vector<std::vector<double>> Ubar(n), Mbar(n);
+  std::vector<Kern> Mv(n);
+  for (int v = 0; v < n; ++v) {
+    if (Kbar[v].empty()) continue;
+    Mv[v] = mirror(P[v]);
+    const size_t nk = Mv[v].a.size();
+    std::vector<double> U = Mv[v].a;
+    for (int w = 0; w < n; ++w)
+      if (w != v)
+        for (size_t i = 0; i < nk; ++i) U[i] *= fac[v][w][i];
+    double S = 0;
+    for (double x : U) S += x;
+    double kk = 0;
+    for (size_t i = 0; i < nk; ++i) kk += Kbar[v][i] * U[i] / S;
+    Ubar[v].resize(nk);
+    for (size_t i = 0; i < nk; ++i) Ubar[v][i] = (Kbar[v][i] - kk) / S;
+    Mbar[v].resize(nk);
+    for (size_t i = 0; i < nk; ++i) {
+      double p = Ubar[v][i];
+      for (int w = 0; w < n; ++w)
+        if (w != v) p *= fac[v][w][i];
+      Mbar[v][i] = p;
+    }
+  }
+  // each partner factor fac_w = crop(Mv (x) P_w (x) Mw) (EFF) or crop(Mv (x)
+  // P_w) (OPT1): with T = dL/dfac_w, the correlations of T with the other
+  // operands (on the grid of v)
+  std::vector<std::vector<double>> mv_part(n * n), pw_part(n * n), mw_part(n * n);
+  parallel_for(n * n, [&](int i) {
+    const int v = i / n, w = i % n;
+    if (w == v || Kbar[v].empty()) return;
+    const size_t nk = Mv[v].a.size();
+    const Grid& G = grid[v];
+    Kern T = Mv[v];
+    for (size_t k = 0; k < nk; ++k) {
+      double p = Ubar[v][k] * Mv[v].a[k];
+      for (int u = 0; u < n; ++u)
+        if (u != v && u != w) p *= fac[v][u][k];
+      T.a[k] = p;
+    }
+    const std::vector<cd> Th = dft_grid(T, G.x, G.y, G.z);
+    const auto& Fv = Sp[v][v];
+    const auto& Sw = Sp[v][w];
     std::vector<cd> X(Th.size());
     // Mv: correlation with P_w (x) Mw (EFF, a real spectrum |S_w|^2) or P_w
-    for (size_t i = 0; i < X.size(); ++i)
-      X[i] = eff ? Th[i] * std::norm(Sw[w][i]) : Th[i] * std::conj(Sw[w][i]);
-    mv_part[w] = idft_window(X, gx, gy, gz, Mv.kx, Mv.ky, Mv.kz);
+    for (size_t k = 0; k < X.size(); ++k) X[k] = eff ? Th[k] * std::norm(Sw[k]) : Th[k] * std::conj(Sw[k]);
+    mv_part[i] = idft_window(X, G.x, G.y, G.z, P[v].kx, P[v].ky, P[v].kz);
     // P_w: correlation with Mv (x) Mw (EFF) or Mv
-    for (size_t i = 0; i < X.size(); ++i) X[i] = eff ? Th[i] * Fv[i] * Sw[w][i] : Th[i] * Fv[i];
-    pw_part[w] = idft_window(X, gx, gy, gz, P[w].kx, P[w].ky, P[w].kz);
+    for (size_t k = 0; k < X.size(); ++k) X[k] = eff ? Th[k] * Fv[k] * Sw[k] : Th[k] * Fv[k];
+    pw_part[i] = idft_window(X, G.x, G.y, G.z, P[w].kx, P[w].ky, P[w].kz);
     if (eff) {
       // Mw: correlation with Mv (x) P_w
-      for (size_t i = 0; i < X.size(); ++i) X[i] = Th[i] * Fv[i] * std::conj(Sw[w][i]);
-      mw_part[w] = idft_window(X, gx, gy, gz, P[w].kx, P[w].ky, P[w].kz);
+      for (size_t k = 0; k < X.size(); ++k) X[k] = Th[k] * Fv[k] * std::conj(Sw[k]);
+      mw_part[i] = idft_window(X, G.x, G.y, G.z, P[w].kx, P[w].ky, P[w].kz);
     }
   });
-  for (int w = 0; w < n; ++w) {
-    if (w == v) continue;
-    for (size_t i = 0; i < nk; ++i) Mbar_v[i] += mv_part[w][i];
-    for (size_t i = 0; i < g[w].size(); ++i) g[w][i] += pw_part[w][i];
-    if (eff) {
-      Kern t = P[w];
-      t.a = mw_part[w];
-      const Kern m = mirror(t);
-      for (size_t i = 0; i < g[w].size(); ++i) g[w][i] += m.a[i];
+  for (int v = 0; v < n; ++v) {
+    if (Kbar[v].empty()) continue;
+    for (int w = 0; w < n; ++w) {
+      if (w == v) continue;
+      const int i = v * n + w;
+      for (size_t k = 0; k < Mbar[v].size(); ++k) Mbar[v][k] += mv_part[i][k];
+      for (size_t k = 0; k < g[w].size(); ++k) g[w][k] += pw_part[i][k];
+      if (eff) add_mirror(g[w], P[w], mw_part[i]);
     }
+    add_mirror(g[v], P[v], Mbar[v]);
   }
-  add_mirror_v(g[v], Mbar_v);
   return g;
+}
+
+std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P, int v, int variant,
+                                                     const std::vector<double>& Kbar) {
+  std::vector<std::vector<double>> all(P.size());
+  all[v] = Kbar;
+  if (Kbar.size() != P[v].a.size()) throw std::invalid_argument("Kbar does not have the kernel's window");
+  return compound_kernels_vjp(P, variant, all);
 }
 
 std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny) {

@@ -40,6 +40,10 @@ Kern compound_kernel(const std::vector<Kern>& P, int v, int variant);
 // a grid where circular equals linear convolution.
 std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P, int v, int variant,
                                                      const std::vector<double>& Kbar);
+// The same for every view's kernel at once (Kbar[v] empty: no gradient for
+// K_v): the sum over v of the gradients, computed in parallel.
+std::vector<std::vector<double>> compound_kernels_vjp(const std::vector<Kern>& P, int variant,
+                                                      const std::vector<std::vector<double>>& Kbar);
 
 // Stages x and y of the spectrum of a centred kernel on a volume grid:
 // A2[dz][ky][kx], kx in [0, nx/2], for every kernel plane dz.

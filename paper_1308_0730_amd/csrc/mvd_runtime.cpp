@@ -1730,14 +1730,15 @@ void grad_reverse_impl(mvd_handle* h, double* const* grad_psf, float* grad_psi0,
     // accumulated term is the mirrored dL/dK_v) through the construction of
     // every K_v from all PSFs
     if (compound) {
+      std::vector<std::vector<double>> Kbar(N);
       for (int v = 0; v < N; ++v) {
         mvdh::Kern t = B.P[v];
         t.a = window_of(h->g_acck + (size_t)v * S, B.P[v]);
-        const mvdh::Kern Kbar = mvdh::mirror(t);
-        const auto add = mvdh::compound_kernel_vjp(B.P, v, h->rec_variant, Kbar.a);
-        for (int w = 0; w < N; ++w)
-          for (size_t j = 0; j < add[w].size(); ++j) gP[w][j] += add[w][j];
+        Kbar[v] = mvdh::mirror(t).a;
       }
+      const auto add = mvdh::compound_kernels_vjp(B.P, h->rec_variant, Kbar);
+      for (int w = 0; w < N; ++w)
+        for (size_t j = 0; j < add[w].size(); ++j) gP[w][j] += add[w][j];
     }
     for (int v = 0; v < N; ++v) {
       if (!grad_psf[v]) continue;
