@@ -20,9 +20,10 @@ Column length classes (lengths up to 48, 128, 256, between 256 and 512, 512,
 and above 512), each of one thread count and tile, for the kernels that serve blocks of several
 lengths in one launch.
 Row passes (x): every 5-smooth half-row length M in [4, 1024]; four waves per
-workgroup; each wave owns ceil(64 * largest radix / M) rows (at most 16, and
-at most 32 KB of rows per workgroup), so the largest-radix stage has a
-butterfly for nearly every lane.
+workgroup; each wave owns ceil(64 * largest radix / M) rows, so the
+largest-radix stage has a butterfly for nearly every lane, and where that
+is not exactly one round of butterflies at least 512 complex values (at most
+16 rows, and at most 32 KB of rows per workgroup).
 """
 import math
 import os
@@ -87,6 +88,8 @@ def flit(x):
     t = f"{x:.17g}"
     return (t if ("." in t or "e" in t) else t + ".0") + "f"
 ROW_LDS = 32 * 1024
+# at least this many complex values per wave (rows of short half-rows)
+ROW_ELEMS = 512
 
 
 def row_radices(M):
@@ -94,8 +97,18 @@ def row_radices(M):
 
 
 def row_rows(M):
+    """Rows per wave: enough for the largest-radix stage to give nearly every
+    lane a butterfly; where that count does not fill exactly one round of
+    64 butterflies, at least ROW_ELEMS complex values per wave (measured:
+    short half-rows such as 54, 108 and 125 points gain 5-24 % in the x
+    passes, those whose stage already fills one round, such as 64, 80 and
+    128, do not), within 16 rows and ROW_LDS bytes of rows per workgroup."""
     rmax = max(row_radices(M))
-    return max(1, min(16, -(-64 * rmax // M), ROW_LDS // (4 * M * 8)))
+    cap = max(1, min(16, ROW_LDS // (4 * M * 8)))
+    base = max(1, min(cap, -(-64 * rmax // M)))
+    if base * M == 64 * rmax:
+        return base
+    return max(base, min(cap, -(-ROW_ELEMS // M)))
 
 
 MAX_COL = 1024

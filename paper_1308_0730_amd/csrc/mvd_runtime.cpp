@@ -460,20 +460,23 @@ void build_jobs(mvd_handle* h) {
   }
   HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                           h->stream));
-  // block lanes: largest block first onto the least loaded lane
+  // block lanes: blocks of equal dims stay together (one launch per pass
+  // serves them all); the groups go largest first onto the least loaded lane
   const int nb = (int)h->blocks.size();
   h->block_lane.assign(nb, 0);
   {
-    std::vector<int> idx(nb);
-    for (int i = 0; i < nb; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return h->blocks[a].V > h->blocks[b].V; });
+    std::map<std::array<int, 3>, std::vector<int>> same;
+    for (int i = 0; i < nb; ++i) same[{h->blocks[i].nx, h->blocks[i].ny, h->blocks[i].nz}].push_back(i);
+    std::vector<std::pair<int64_t, const std::vector<int>*>> groups;
+    for (const auto& kv : same) groups.push_back({(int64_t)kv.second.size() * h->blocks[kv.second[0]].V, &kv.second});
+    std::stable_sort(groups.begin(), groups.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     int64_t load[1 + mvd_handle::kSide] = {};
-    for (int i : idx) {
+    for (const auto& g : groups) {
       int best = 0;
       for (int l = 1; l <= mvd_handle::kSide && !h->blocked && !h->no_alloc; ++l)
         if (load[l] < load[best]) best = l;
-      h->block_lane[i] = best;
-      load[best] += h->blocks[i].V;
+      for (int i : *g.second) h->block_lane[i] = best;
+      load[best] += g.first;
     }
   }
   for (int k = 0; k < 3; ++k) {
