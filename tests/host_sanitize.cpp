@@ -1,0 +1,100 @@
+// Host FP64 preparation code under AddressSanitizer and UBSan: PSF
+// preparation (odd and even extents, rejection of bad values), compound
+// kernels and their adjoint for every variant, kernel spectra, plans.
+// Built and run by tests/test_host_sanitize.py; exits non-zero on a failure.
+#include <cmath>
+#include <cstdio>
+#include <random>
+#include <stdexcept>
+#include <vector>
+
+#include "mvd_host.h"
+
+using namespace mvdh;
+
+static int fails = 0;
+#define CHECK(c)                                              \
+  do {                                                        \
+    if (!(c)) {                                               \
+      std::fprintf(stderr, "check failed: %s line %d\n", #c, __LINE__); \
+      ++fails;                                                \
+    }                                                         \
+  } while (0)
+
+int main() {
+  std::mt19937 rng(7);
+  std::uniform_real_distribution<float> u(0.01f, 1.0f);
+  const int ext[3][3] = {{5, 3, 7}, {4, 5, 3}, {3, 3, 6}};
+  std::vector<Kern> P;
+  for (auto& e : ext) {
+    std::vector<float> g((size_t)e[0] * e[1] * e[2]);
+    for (float& x : g) x = u(rng);
+    Kern K = prepare_psf(g.data(), e[0], e[1], e[2]);
+    CHECK(K.kx % 2 == 1 && K.ky % 2 == 1 && K.kz % 2 == 1);
+    double s = 0;
+    for (double a : K.a) s += a;
+    CHECK(std::fabs(s - 1.0) < 1e-12);
+    P.push_back(K);
+  }
+  // bad values are rejected
+  {
+    std::vector<float> g(27, 1.0f);
+    g[5] = -1.0f;
+    bool thrown = false;
+    try {
+      prepare_psf(g.data(), 3, 3, 3);
+    } catch (const std::invalid_argument&) {
+      thrown = true;
+    }
+    CHECK(thrown);
+    std::vector<float> z(8, 0.0f);
+    thrown = false;
+    try {
+      prepare_psf(z.data(), 2, 2, 2);
+    } catch (const std::invalid_argument&) {
+      thrown = true;
+    }
+    CHECK(thrown);
+  }
+  for (int variant = 0; variant < 4; ++variant)
+    for (int v = 0; v < 3; ++v) {
+      Kern K = compound_kernel(P, v, variant);
+      CHECK(K.kx == P[v].kx && K.ky == P[v].ky && K.kz == P[v].kz);
+      double s = 0;
+      for (double a : K.a) s += a;
+      CHECK(std::fabs(s - 1.0) < 1e-10);
+      std::vector<double> kbar(K.a.size());
+      for (size_t i = 0; i < kbar.size(); ++i) kbar[i] = std::sin(0.37 * (double)i);
+      const auto g = compound_kernel_vjp(P, v, variant, kbar);
+      CHECK(g.size() == 3);
+      for (int w = 0; w < 3; ++w) {
+        CHECK(g[w].size() == P[w].a.size());
+        for (double x : g[w]) CHECK(std::isfinite(x));
+      }
+      bool thrown = false;
+      try {
+        compound_kernel_vjp(P, v, variant, std::vector<double>(3, 0.0));
+      } catch (const std::invalid_argument&) {
+        thrown = true;
+      }
+      CHECK(thrown);
+    }
+  // spectra on a small grid and every plan factorisation up to 1024
+  {
+    const int nx = 20, ny = 12, nz = 10;
+    std::vector<float> main_out((size_t)nz * ny * (nx / 2) * 2), nyq((size_t)nz * ny * 2);
+    spectrum_host(P[0], nx, ny, nz, main_out.data(), nyq.data());
+    for (float x : main_out) CHECK(std::isfinite(x));
+    // DC term: the kernel's sum times 1/V
+    CHECK(std::fabs(main_out[0] - 1.0f / (nx * ny * nz)) < 1e-7f);
+    for (int n = 1; n <= 1024; ++n)
+      if (is_smooth5(n)) {
+        int prod = 1;
+        for (int r : factorize(n)) prod *= r;
+        CHECK(prod == n);
+      }
+  }
+  if (fails) std::fprintf(stderr, "%d failures\n", fails);
+  else std::printf("host sanitize: ok\n");
+  return fails ? 1 : 0;
+}
