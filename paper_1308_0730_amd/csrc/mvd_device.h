@@ -106,10 +106,17 @@ __device__ __forceinline__ void block_reduce(double& f, unsigned& a, unsigned& b
   }
 }
 
+// a / b for b >= 1 in magnitude or at least a normal float: the hardware
+// reciprocal (within 1 ulp) times a, instead of the correctly rounded
+// division's longer instruction sequence (the x passes are limited by their
+// vector instructions as much as by memory).
+__device__ __forceinline__ float fast_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // Tikhonov MAP step: the t >= 0 solving lamp t^2 + t = u, in the form
-// without cancellation.
+// without cancellation (hardware square root and reciprocal, each within
+// 1 ulp; the denominator is >= 1).
 __device__ __forceinline__ float tikhonov(float u, float lamp) {
-  return lamp > 0.f ? 2.f * u / (1.f + sqrtf(1.f + 4.f * lamp * u)) : u;
+  return lamp > 0.f ? fast_div(2.f * u, 1.f + __builtin_amdgcn_sqrtf(1.f + 4.f * lamp * u)) : u;
 }
 
 // Ratio of observed to expected for the two real values of a packed pair:
@@ -118,7 +125,7 @@ __device__ __forceinline__ float tikhonov(float u, float lamp) {
 __device__ __forceinline__ float2 ratio2(float2 phi, float2 b, float eps, unsigned& nclamp) {
   const bool dx = phi.x >= 0.f, dy = phi.y >= 0.f;
   nclamp += (dx && b.x < eps) + (dy && b.y < eps);
-  return make_float2(dx ? phi.x / fmaxf(b.x, eps) : 1.f, dy ? phi.y / fmaxf(b.y, eps) : 1.f);
+  return make_float2(dx ? fast_div(phi.x, fmaxf(b.x, eps)) : 1.f, dy ? fast_div(phi.y, fmaxf(b.y, eps)) : 1.f);
 }
 
 }  // namespace mvdk
