@@ -482,9 +482,10 @@ def blocked_form(steps, warmup):
     """The block-wise form at the size of the paper's largest four-view
     dataset: 1640x1070x345 (an L1 larva), four views at 90 deg, 21x21x31
     PSFs, Optimization II, lambda 0, 10 iterations; the volume is not a
-    transform length along any axis and y is beyond one, so it runs as two
-    1728x576x405 blocks with a halo of twice the PSF radius.  value counts
-    the volume's voxels, grid_value the block grids'."""
+    transform length along any axis and y is beyond one, so it runs in
+    blocks (the default blocking: 2x3x1 blocks on 864x400x405 grids) with a
+    halo of twice the PSF radius.  value counts the volume's voxels,
+    grid_value the block grids'."""
     import torch
     from paper_1308_0730_amd import mvd, synth, tune
     t0 = time.time()

@@ -193,15 +193,18 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
  *   p      the volume (dims any extents >= 1; views, PSFs and weights as for
  *          mvd_create; host or device memory)
  *   tiles  NULL or blocks per axis {tx, ty, tz}, each in [1, extent], or 0
- *          for the fewest blocks whose grid fits the transform lengths
- *          (nx <= 2 MVD_MAX_LEN, ny, nz <= MVD_MAX_LEN_YZ)
+ *          for the fewest blocks whose grid has nx <= 1024 and ny, nz <= 512
+ *          (the fastest transform kernels), else the fewest whose grid fits
+ *          the transform lengths (nx <= 2 MVD_MAX_LEN, ny, nz <=
+ *          MVD_MAX_LEN_YZ)
  *   halo   NULL (twice the largest odd-padded PSF radius per axis, the
  *          exact choice) or {hx, hy, hz} >= 0
  * MVD_EINVAL if a block's grid exceeds the transform lengths.  The handle
  * runs the sequential scheme (mvd_iterate, mvd_view_update, mvd_profile,
  * mvd_get_estimate and mvd_set_estimate of the whole volume as block 0,
- * mvd_stats with the flux of the volume; ratio and negativity clamps are
- * counted over the block grids); the combined updates, the differentiated
+ * mvd_stats with the flux of the volume; ratio clamps are counted over the
+ * block grids, negativity clamps over the blocks' own voxels); the combined
+ * updates, the differentiated
  * form, mvd_set_psfs and the weight normalisation return MVD_ESTATE.
  * mvd_grid_dims reports a block's grid; blocks share one set of kernel
  * planes. */

@@ -33,6 +33,24 @@ struct GRow {
   }
 };
 
+// Window row accessor (block-wise form): element pos of row `line` is the
+// pair of grid voxels x = 2 pos, 2 pos + 1 of that row, read from the volume
+// at (sx + x) mod vnx of the volume row whose offset the wave's table holds.
+struct WinRow {
+  const float* vol;
+  const int64_t* rows;  // the wave's rows: offset of volume voxel x = 0 of each
+  int sx, vnx, nrw;
+  static constexpr bool lds = false;
+  __device__ __forceinline__ float2 ld(int line, int pos) const {
+    if (line >= nrw) return make_float2(0.f, 0.f);
+    const float* r = vol + rows[line];
+    int x = sx + 2 * pos;
+    while (x >= vnx) x -= vnx;
+    const int x1 = x + 1 == vnx ? 0 : x + 1;
+    return make_float2(ldg(r + x), ldg(r + x1));
+  }
+};
+
 // Last forward z stage: multiply by the prefetched kernel spectrum (its
 // conjugate for the mirrored kernel) and store to the LDS tile.
 template <int TX, int MAXB, int R>
@@ -120,6 +138,12 @@ struct RowOp {
   const float2 (&pb)[MAXB][R];
   float* psi_rows;  // psi at row wrow0 (MODES 2, 4)
   float* acc_rows;  // the combined factor at row wrow0 (MODES 3, 4)
+  // block-wise form (MODE 2): the new psi of the own voxels, grid voxels
+  // [hx, hx + ex) of the rows whose volume offset own[] holds (-1: not an
+  // own row), goes to vol at own[line] + ox + x - hx; nothing else is written
+  float* vol;
+  const int64_t* own;
+  int ox, hx, ex;
   int nx, nrw;
   bool weighted, first, geo;
   float eps, lamp, inv_n;
@@ -133,7 +157,6 @@ struct RowOp {
     if (MODE == 1) {
       o = ratio2(pa[i][r], z, eps, ncr);
     } else if (MODE == 2) {
-      ncn += (z.x < 0.f) + (z.y < 0.f);
       const float2 p = pa[i][r];
       const float ux = p.x * (z.x > 0.f ? z.x : 0.f), uy = p.y * (z.y > 0.f ? z.y : 0.f);
       const float tx = tikhonov(ux, lamp), ty = tikhonov(uy, lamp);
@@ -142,9 +165,27 @@ struct RowOp {
       } else {
         o = make_float2(tx, ty);
       }
-      st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
-      flux += (double)o.x + (double)o.y;
-      bad |= !(isfinite(o.x) && isfinite(o.y));
+      if (vol) {
+        const int64_t b = own[line];
+        const int x = 2 * pos - hx;
+        if (b >= 0 && x >= 0 && x < ex) {
+          stg(vol + b + ox + x, o.x);
+          ncn += z.x < 0.f;
+          flux += (double)o.x;
+          bad |= !isfinite(o.x);
+        }
+        if (b >= 0 && x + 1 >= 0 && x + 1 < ex) {
+          stg(vol + b + ox + x + 1, o.y);
+          ncn += z.y < 0.f;
+          flux += (double)o.y;
+          bad |= !isfinite(o.y);
+        }
+      } else {
+        ncn += (z.x < 0.f) + (z.y < 0.f);
+        st2(psi_rows + (int64_t)line * nx + 2 * pos, o);
+        flux += (double)o.x + (double)o.y;
+        bad |= !(isfinite(o.x) && isfinite(o.y));
+      }
     } else {
       ncn += (z.x < 0.f) + (z.y < 0.f);
       const float cx = z.x > 0.f ? z.x : 0.f, cy = z.y > 0.f ? z.y : 0.f;
@@ -440,12 +481,36 @@ __global__ void __launch_bounds__(64 * WPB)
   __shared__ float2 s_pp[M];
   __shared__ double rf[WPB];
   __shared__ unsigned ra[WPB], rb[WPB];
+  // block-wise form: per row of the workgroup, the volume offset of its
+  // window row (MODE 0) or of its own row (MODE 2; -1 for halo rows)
+  constexpr bool WIN = MODE == 0 || MODE == 2;
+  __shared__ int64_t s_rows[WIN ? RW : 1];
   int local;
   const int jid = find_job(jobs, njobs, PASS_X, RW, local, true);
   if (jid < 0) return;
   const JobDesc& J = jobs[jid];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  if (MODE != 0 && v >= J.nviews) {
+  const bool win = WIN && J.vol != nullptr;
+  bool skip = MODE != 0 && v >= J.nviews;
+  if (win && !skip) {
+    int any = 0;
+    for (int t = tid; t < RW; t += T) {
+      const int r = local * RW + t;
+      int64_t o = -1;
+      if (r < J.ny * J.nz) {
+        const int y = r % J.ny, z = r / J.ny;
+        if (MODE == 0)
+          o = ((int64_t)((J.sz + z) % J.vnz) * J.vny + (J.sy + y) % J.vny) * J.vnx;
+        else if (y >= J.hy && y < J.hy + J.ey && z >= J.hz && z < J.hz + J.ez)
+          o = ((int64_t)(J.oz + z - J.hz) * J.vny + (J.oy + y - J.hy)) * J.vnx;
+      }
+      s_rows[t] = o;
+      any |= o >= 0;
+    }
+    // an update workgroup of halo rows only has nothing to write
+    skip = !__syncthreads_or(any);
+  }
+  if (skip) {
     if (tid == 0 && parts) {
       if (MODE == 1) {
         parts[blockIdx.x].ratio_clamps = 0;
@@ -473,9 +538,14 @@ __global__ void __launch_bounds__(64 * WPB)
 
   if (MODE == 0) {
     __syncthreads();  // twiddle tables
-    const GRow src{J.psi + rowoff, nx, nrw};
     Plain<LdsRow<M>> out{L};
-    CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, src, L, out);
+    if (win) {
+      const WinRow src{J.vol, s_rows + wave * RPW, J.sx, J.vnx, nrw};
+      CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, src, L, out);
+    } else {
+      const GRow src{J.psi + rowoff, nx, nrw};
+      CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, src, L, out);
+    }
   } else {
     // operands of the pointwise step, in the order the last inverse stage
     // produces its outputs
@@ -493,7 +563,16 @@ __global__ void __launch_bounds__(64 * WPB)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
-        pa[i][r] = (ok && opa) ? ld2(opa + g) : make_float2(0.f, 0.f);
+        if (MODE == 2 && win) {
+          // psi of the own voxels from the volume
+          const int64_t b = ok ? s_rows[wave * RPW + line] : -1;
+          const int x = 2 * (j + r * LM::NB) - J.hx;
+          const float* q = J.vol + b + J.ox + x;
+          pa[i][r] = make_float2(b >= 0 && x >= 0 && x < J.ex ? ldg(q) : 0.f,
+                                 b >= 0 && x + 1 >= 0 && x + 1 < J.ex ? ldg(q + 1) : 0.f);
+        } else {
+          pa[i][r] = (ok && opa) ? ld2(opa + g) : make_float2(0.f, 0.f);
+        }
         pb[i][r] = ((MODE == 2 || MODE == 4) && ok && opb) ? ld2(opb + g) : make_float2(0.f, 0.f);
       }
     }
@@ -533,6 +612,7 @@ __global__ void __launch_bounds__(64 * WPB)
     gsync<SYNC_WAVE>();
     RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff,
                                     (MODE == 3 || MODE == 4) ? J.acc + rowoff : nullptr,
+                                    win ? J.vol : nullptr, s_rows + wave * RPW, J.ox, J.hx, J.ex,
                                     nx,    nrw,   opb != nullptr,  first, geo,
                                     J.eps, J.lamp, 1.f / (float)J.nviews, 0.0, 0u, 0u, false};
     CtRun<true, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, op);

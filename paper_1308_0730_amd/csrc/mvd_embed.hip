@@ -2,9 +2,8 @@
 // at an offset inside a larger grid (the volume extended by the PSF radius
 // and rounded up to transform lengths); setup and copy work.  Block-wise
 // form: each block's grid is a window of the periodic volume (the block and
-// a halo around it), gathered before every view-update, and the block's own
-// voxels are pasted back after it.  Shapes are (nx, ny, nz) grids stored
-// [z][y][x].
+// a halo around it); its views and weights are gathered once.  Shapes are
+// (nx, ny, nz) grids stored [z][y][x].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,35 +69,6 @@ __global__ void __launch_bounds__(256) k_gather(float* __restrict__ grid, int gx
   }
 }
 
-// vol[oz + z][oy + y][ox + x] = grid[hz + z][hy + y][hx + x] for the block's
-// (ex, ey, ez) voxels; parts[blockIdx.x].flux receives the FP64 sum of the
-// values this workgroup wrote
-__global__ void __launch_bounds__(256) k_scatter(float* __restrict__ vol, int nx, int ny, const float* __restrict__ grid,
-                                                 int gx, int gy, int ox, int oy, int oz, int ex, int ey, int ez,
-                                                 int hx, int hy, int hz, Partial* __restrict__ parts) {
-  __shared__ double rf[4];
-  __shared__ unsigned ra[4], rb[4];
-  const int64_t rows = (int64_t)ey * ez;
-  double sum = 0.0;
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const int y = (int)(r % ey), z = (int)(r / ey);
-    float* dst = vol + ((int64_t)(oz + z) * ny + (oy + y)) * nx + ox;
-    const float* src = grid + ((int64_t)(hz + z) * gy + (hy + y)) * gx + hx;
-    for (int x = threadIdx.x; x < ex; x += 256) {
-      const float v = ldg(src + x);
-      stg(dst + x, v);
-      sum += (double)v;
-    }
-  }
-  unsigned a = 0, b = 0;
-  block_reduce<256>(sum, a, b, rf, ra, rb);
-  if (threadIdx.x == 0) {
-    parts[blockIdx.x].flux = sum;
-    parts[blockIdx.x].ratio_clamps = 0;
-    parts[blockIdx.x].neg_clamps = 0;
-  }
-}
-
 int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
 Box box(const int* grid, const int* user, const int* off) {
@@ -134,12 +104,5 @@ hipError_t mvd_launch_gather(float* grid, const int* gdims, const float* vol, co
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(rows, 4096));
   k_gather<<<nb, 256, 0, s>>>(grid, gdims[0], gdims[1], gdims[2], vol, vdims[0], vdims[1], vdims[2], start[0],
                               start[1], start[2]);
-  return hipGetLastError();
-}
-
-hipError_t mvd_launch_scatter(float* vol, const int* vdims, const float* grid, const int* gdims, const int* origin,
-                              const int* extent, const int* halo, Partial* parts, int nwg, hipStream_t s) {
-  k_scatter<<<nwg, 256, 0, s>>>(vol, vdims[0], vdims[1], grid, gdims[0], gdims[1], origin[0], origin[1], origin[2],
-                                extent[0], extent[1], extent[2], halo[0], halo[1], halo[2], parts);
   return hipGetLastError();
 }

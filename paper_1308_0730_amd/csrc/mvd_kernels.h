@@ -102,14 +102,9 @@ hipError_t mvd_launch_embed(float* grid, const int* gdims, const float* vol, con
 hipError_t mvd_launch_extract(float* vol, const int* udims, const float* grid, const int* gdims, const int* off,
                               hipStream_t s);
 // block-wise form (mvd_embed.hip): the (gx, gy, gz) window of the periodic
-// volume vdims starting at start (each 0 <= start < vdims) into grid; and
-// the block's extent voxels at grid offset halo back into the volume at
-// origin, with the FP64 sum of what each of the nwg workgroups wrote in
-// parts[0..nwg).flux
+// volume vdims starting at start (each 0 <= start < vdims) into grid
 hipError_t mvd_launch_gather(float* grid, const int* gdims, const float* vol, const int* vdims, const int* start,
                              hipStream_t s);
-hipError_t mvd_launch_scatter(float* vol, const int* vdims, const float* grid, const int* gdims, const int* origin,
-                              const int* extent, const int* halo, Partial* parts, int nwg, hipStream_t s);
 // every voxel of the grid outside the (ux, uy, uz) box at offset off gets val
 hipError_t mvd_launch_fill_outside(float* grid, const int* gdims, const int* udims, const int* off, float val,
                                    hipStream_t s);

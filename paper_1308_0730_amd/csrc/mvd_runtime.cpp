@@ -94,7 +94,8 @@ struct mvd_handle {
   // block-wise form: the volume (any extents, one period of a periodic
   // grid) is cut into near-equal blocks; each block computes on its own grid
   // (the block plus a halo on both sides, read periodically from the volume
-  // before every view-update) and pastes its own voxels back after it
+  // by every view-update's first x pass), and its update pass writes the
+  // block's own voxels into the volume
   bool blocked = false;
   struct Tiling {
     int dims[3] = {0, 0, 0};   // the volume (x, y, z)
@@ -102,12 +103,8 @@ struct mvd_handle {
     int halo[3] = {0, 0, 0};   // grid voxels before a block's first voxel, per axis
     int64_t V = 0;
     float* psi = nullptr;      // [V] the estimate
-    Partial* sparts = nullptr; // [nviews][blocks][kScatterWG] FP64 sums of the pasted voxels
-    double* sink_flux = nullptr;  // reduction outputs the block-wise form does not report
-    unsigned long long* sink_cnt = nullptr;
     std::vector<std::array<int, 3>> origin, extent, start;  // per block; start = (origin - halo) mod dims
   } tl;
-  static constexpr int kScatterWG = 256;
   // blocks of one geometry share the kernel planes of one block
   bool shared_kernels = false;
   // device tables
@@ -456,6 +453,17 @@ void build_jobs(mvd_handle* h) {
     j.saved = B.saved;
     j.eps = B.eps;
     j.lamp = B.lamp;
+    if (h->blocked) {
+      // the block's grid is a window of the volume's estimate
+      const auto& T = h->tl;
+      const size_t b = h->jobs.size();
+      j.vol = T.psi;
+      j.vnx = T.dims[0], j.vny = T.dims[1], j.vnz = T.dims[2];
+      j.sx = T.start[b][0], j.sy = T.start[b][1], j.sz = T.start[b][2];
+      j.ox = T.origin[b][0], j.oy = T.origin[b][1], j.oz = T.origin[b][2];
+      j.hx = T.halo[0], j.hy = T.halo[1], j.hz = T.halo[2];
+      j.ex = T.extent[b][0], j.ey = T.extent[b][1], j.ez = T.extent[b][2];
+    }
     h->jobs.push_back(j);
   }
   HIPCHECK(hipMemcpyAsync(h->d_jobs, h->jobs.data(), h->jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
@@ -514,6 +522,9 @@ void drop_graphs(mvd_handle* h) {
 // grows the partials buffer and drops the cached graphs.
 bool cfg_fits(const mvd_handle* h, int kind, int c) {
   if (c < 0 || c >= mvd_num_cfgs(kind)) return false;
+  // the block-wise form's x passes read and write the volume in place: the
+  // compile-time-plan row kernels only
+  if (h->blocked && kind == PASS_X && mvd_cfg_exact(kind, c) == 0) return false;
   if (c == mvd_exact_cfg(kind)) {
     for (const auto& B : h->blocks)
       if (mvd_exact_param(kind, job_len(B, kind)) <= 0) return false;
@@ -671,7 +682,8 @@ void alloc_block(mvd_handle* h, Block& B, bool weights) {
   B.V = (int64_t)B.nx * B.ny * B.nz;
   B.spec_main = (int64_t)B.Mp * B.ny * B.nz;
   B.spec_elems = B.spec_main + (int64_t)B.ny * B.nz;
-  B.psi = (float*)h->dalloc(B.V * sizeof(float));
+  // the block-wise form keeps its estimate in the volume only
+  if (!h->blocked) B.psi = (float*)h->dalloc(B.V * sizeof(float));
   B.spec = (float*)h->dalloc(B.spec_elems * 2 * sizeof(float));
   B.phi = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
   if (weights) B.w = (float*)h->dalloc((size_t)N * B.V * sizeof(float));
@@ -909,6 +921,7 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
     }
   }
   const int lim[3] = {2 * MVD_MAX_LEN, MVD_MAX_LEN_YZ, MVD_MAX_LEN_YZ};
+  const int lim_fast[3] = {1024, 512, 512};
   int G[3];
   for (int a = 0; a < 3; ++a) {
     T.halo[a] = halo ? halo[a] : 2 * R[a];
@@ -916,14 +929,21 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
     const int n = T.dims[a];
     auto grid_for = [&](int t) {
       const int ext = (n + t - 1) / t;
-      const int g = std::max({ext + 2 * T.halo[a], kmax[a], a == 0 ? 4 : 2});
+      const int g = std::max({ext + 2 * T.halo[a], kmax[a], a == 0 ? 8 : 2});
       return next_smooth5(g, a == 0);
     };
     int t = tiles ? tiles[a] : 0;
     if (t < 0 || t > n) bad("blocks per axis must be in [0, the extent] (0: as few as the transform lengths allow)");
     if (t == 0) {
+      // the fewest blocks whose grid keeps half-rows and columns within 512
+      // points (the kernels with the most lines per tile), else the fewest
+      // whose grid fits the transform lengths
       t = 1;
-      while (t < n && grid_for(t) > lim[a]) ++t;
+      while (t < n && grid_for(t) > lim_fast[a]) ++t;
+      if (grid_for(t) > lim_fast[a]) {
+        t = 1;
+        while (t < n && grid_for(t) > lim[a]) ++t;
+      }
     }
     G[a] = grid_for(t);
     if (G[a] > lim[a])
@@ -1028,10 +1048,6 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
     add_plans(h, B, plans, tw);
   }
   HIPCHECK(mvd_launch_fill(T.psi, T.V, (float)s, h->stream));
-  T.sparts = (Partial*)h->dalloc((size_t)N * nb * mvd_handle::kScatterWG * sizeof(Partial));
-  HIPCHECK(hipMemsetAsync(T.sparts, 0, (size_t)N * nb * mvd_handle::kScatterWG * sizeof(Partial), h->stream));
-  T.sink_flux = (double*)h->dalloc(N * sizeof(double));
-  T.sink_cnt = (unsigned long long*)h->dalloc(2 * N * sizeof(unsigned long long));
   finish_create(h, plans, tw);
 }
 
@@ -1180,25 +1196,19 @@ void enqueue_view_passes(mvd_handle* h, hipStream_t s, int variant, int v, PassT
   timed(4, [&] { run_x(h, s, 2, v, parts, spec_out ? XOPT_SPEC : 0); });
 }
 
-// One view-update; with the block-wise form every block first reads its
-// window of the volume's estimate and transforms it along x, and pastes its
-// own voxels back afterwards (every block reads the estimate before any
-// block writes it: the windows are gathered in one step, in stream order).
+// One view-update; with the block-wise form every block first transforms
+// its window of the volume's estimate along x (read in place), and its
+// update pass writes the block's own voxels into the volume.  Every block's
+// window is read before any block writes (the x pass over all blocks
+// precedes the update pass in stream order), and the own voxels of the
+// blocks are disjoint.
 void enqueue_view(mvd_handle* h, hipStream_t s, int variant, int v, PassTimer* t = nullptr) {
   if (!h->blocked) {
     enqueue_view_passes(h, s, variant, v, t, true);
     return;
   }
-  auto& T = h->tl;
-  const int nb = (int)h->blocks.size();
-  for (int b = 0; b < nb; ++b)
-    HIPCHECK(mvd_launch_gather(h->blocks[b].psi, grid_dims(h->blocks[b]), T.psi, T.dims, T.start[b].data(), s));
   run_x(h, s, 0, 0, nullptr, XOPT_SPEC);
   enqueue_view_passes(h, s, variant, v, t, false);
-  for (int b = 0; b < nb; ++b)
-    HIPCHECK(mvd_launch_scatter(T.psi, T.dims, h->blocks[b].psi, grid_dims(h->blocks[b]), T.origin[b].data(),
-                                T.extent[b].data(), T.halo,
-                                T.sparts + ((size_t)v * nb + b) * mvd_handle::kScatterWG, mvd_handle::kScatterWG, s));
 }
 
 // One iteration: every view once, in index order (section 7).  When every
@@ -1376,17 +1386,10 @@ hipGraphExec_t graph_for(mvd_handle* h, int variant, int scheme = 0) {
   return ex;
 }
 
-// Statistics of the last iteration from the partial results (the flux of the
-// block-wise form from the pasted voxels).
+// Statistics of the last iteration from the partial results (the block-wise
+// form's update passes count and sum the own voxels of every block).
 void reduce_stats(mvd_handle* h, hipStream_t s) {
-  if (!h->blocked) {
-    HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, s));
-    return;
-  }
-  auto& T = h->tl;
-  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, T.sink_flux, h->d_ratio, h->d_neg, s));
-  HIPCHECK(mvd_launch_reduce(T.sparts, (int)h->blocks.size() * mvd_handle::kScatterWG, h->nviews, h->d_flux,
-                             T.sink_cnt, T.sink_cnt + h->nviews, s));
+  HIPCHECK(mvd_launch_reduce(h->d_parts, h->grid_x, h->nviews, h->d_flux, h->d_ratio, h->d_neg, s));
 }
 
 // The graph of a whole block-major run of n iterations (one launch per run).

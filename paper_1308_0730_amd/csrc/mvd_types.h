@@ -58,6 +58,18 @@ struct JobDesc {
   float* acc;                  // [V] combined-update factor (product or sum over views), or nullptr
   float* saved;                // spec_elems complex: x/y-stage spectrum of psi kept over a combined
                                // iteration, or nullptr
+  // Block-wise form: the block's grid is a window of the volume's estimate
+  // vol (vnx x vny x vnz, periodic); grid voxel g sits at volume voxel
+  // (s + g) mod vn per axis.  The block's own voxels are the grid voxels
+  // [h, h + e) per axis (no wrap: they sit at o + g - h).  The forward x
+  // pass reads the window and the update writes the own voxels, both in the
+  // volume; psi is then nullptr.  vol is nullptr otherwise.
+  float* vol;
+  int vnx, vny, vnz;
+  int sx, sy, sz;
+  int ox, oy, oz;
+  int hx, hy, hz;
+  int ex, ey, ez;
 };
 
 // Linear boundary: a view holds this value on the grid voxels outside the

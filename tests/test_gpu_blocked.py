@@ -71,21 +71,24 @@ def test_thin_halo_follows_the_oracles_blocked_form(mvd, variant):
 
 
 def test_beyond_the_transform_lengths(mvd):
-    """2050x1030x8: x beyond 2048 and y beyond 1024 points; the default
-    blocking takes two blocks along each (1080x540x12 grids), one iteration
-    against the whole-volume oracle."""
+    """2050x1030x8: x beyond 2048 and y beyond 1024 points.  The default
+    blocking takes three blocks along x and y (720x360x12 grids: half-rows
+    and columns within 512 points); two blocks along each give the longest
+    grids (1080x540x12).  One iteration of each against the whole-volume
+    oracle."""
     views, psfs, _ = problem((2050, 1030, 8), 2, 403, psf_shape=(3, 5, 5))
     pb = O.Problem(views, psfs, None, 0.0)
-    with mvd.Deconvolver.blocked(views, psfs) as d:
-        tiles, halo, _ = d.blocking()
-        print("tiles", tiles, "halo", halo, "grid", d.grid_dims(0))
-        assert tiles == (2, 2, 1) and d.grid_dims(0) == (1080, 540, 12)
-        d.iterate(1, O.EFF)
-        got = d.estimate().cpu().numpy()
     ref = pb.iterate(pb.psi0(), 1, O.EFF)
-    e = rel(got, ref)
-    print(f"rel_l2={e:.3e}")
-    assert e <= ONE_STEP
+    for tiles_in, tiles_out, grid in ((None, (3, 3, 1), (720, 360, 12)), ((2, 2, 1), (2, 2, 1), (1080, 540, 12))):
+        with mvd.Deconvolver.blocked(views, psfs, tiles=tiles_in) as d:
+            tiles, halo, _ = d.blocking()
+            print("tiles", tiles, "halo", halo, "grid", d.grid_dims(0))
+            assert tiles == tiles_out and d.grid_dims(0) == grid
+            d.iterate(1, O.EFF)
+            got = d.estimate().cpu().numpy()
+        e = rel(got, ref)
+        print(f"rel_l2={e:.3e}")
+        assert e <= ONE_STEP
 
 
 def test_one_block_is_the_plain_run(mvd):
@@ -145,16 +148,16 @@ def larva():
 
 def test_larva_scale_sampled(mvd, larva):
     """1640x1070x345 with four views (Optimization II, lambda 0): two blocks
-    along y on 1728x576x405 grids; after one iteration, view 1's update at
-    sampled voxels (near the block seams and the wrap-around too) against the
-    oracle's windowed evaluation."""
+    along x and three along y on 864x400x405 grids; after one iteration, view
+    1's update at sampled voxels (near the block seams and the wrap-around
+    too) against the oracle's windowed evaluation."""
     s = larva
     v = 1
     dev = [torch.from_numpy(x).cuda() for x in s.views]
     with mvd.Deconvolver.blocked(dev, s.psfs) as d:
         tiles, halo, dims = d.blocking()
         print("tiles", tiles, "halo", halo, "grid", d.grid_dims(0), flush=True)
-        assert tiles == (1, 2, 1) and dims == (1640, 1070, 345)
+        assert tiles == (2, 3, 1) and dims == (1640, 1070, 345) and d.grid_dims(0) == (864, 400, 405)
         d.iterate(1, O.OPT2)
         psi = d.estimate().cpu().numpy()
         d.view_update(v, O.OPT2)
@@ -166,8 +169,10 @@ def test_larva_scale_sampled(mvd, larva):
     rng = np.random.default_rng(408)
     nz, ny, nx = psi.shape
     pts = [tuple(int(a) for a in p) for p in rng.integers(0, [nz, ny, nx], size=(30, 3))]
-    # the seam between the two y blocks (y = 535) and the wrap-around
-    pts += [(int(z), y, int(x)) for y in (533, 534, 535, 536) for z, x in rng.integers(0, [nz, nx], size=(3, 2))]
+    # the seams between the y blocks (y = 356, 713), the x blocks (x = 820)
+    # and the wrap-around
+    pts += [(int(z), y, int(x)) for y in (355, 356, 357, 712, 713, 714) for z, x in rng.integers(0, [nz, nx], size=(2, 2))]
+    pts += [(int(z), int(y), x) for x in (819, 820, 821) for z, y in rng.integers(0, [nz, ny], size=(2, 2))]
     pts += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (nz - 1, 0, 5), (3, ny - 1, nx - 2)]
     bright = np.argwhere(s.truth[::4, ::4, ::4] > np.percentile(s.truth[::4, ::4, ::4], 99.9)) * 4
     pts += [tuple(int(a) for a in bright[i]) for i in rng.integers(0, len(bright), size=10)]
