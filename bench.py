@@ -509,13 +509,24 @@ def blocked_form(steps, warmup):
         tiles, halo, dims = d.blocking()
         grid = d.grid_dims(0)
         nb = tiles[0] * tiles[1] * tiles[2]
+        # the column passes and the ratio pass over every block grid (one
+        # iteration, HIP events around each pass); the update pass reads and
+        # writes psi of the own voxels only and is left out
+        prof = d.profile(1, var)
+    by = pass_bytes([(grid, [p.shape for p in s.psfs])] * nb, False)
+    rates = {k: round(by[k] / (prof[k][0] / 1e3) / 1e9, 1) for k in PASS_NAMES if k != "x_update"}
+    dom = max(rates, key=lambda k: prof[k][0] * prof[k][1])
     vox = int(np.prod(s.dims)) * n * its
     gvox = int(np.prod(grid)) * nb * n * its
     return {"workload": "block-wise: 1640x1070x345, 4 views at 90 deg, 21x21x31 PSFs, Optimization II, "
                         "lambda 0, 10 iterations",
             "blocks": list(tiles), "halo": list(halo), "grid": list(grid), "ms_per_step": round(ms, 3),
             "value": round(vox / (ms / 1e3) / 1e9, 3), "unit": "Gvox/s",
-            "grid_value": round(gvox / (ms / 1e3) / 1e9, 3)}
+            "grid_value": round(gvox / (ms / 1e3) / 1e9, 3), "passes_GBps": rates,
+            "roofline": {"bound": "hbm", "achieved": rates[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(rates[dom] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                         "bytes_per_launch": by[dom], "avg_launch_ms": round(prof[dom][0], 5),
+                         "note": "one pass over every block grid timed as one launch"}}
 
 
 def spim_form():
@@ -579,6 +590,9 @@ def main():
                          "differentiated (forward against forward + backward), the convergence "
                          "(every scheme x variant to one distance from the ground truth), the "
                          "linear-boundary, the simulated-SPIM and the PSF-refinement measurements")
+    ap.add_argument("--only-form", type=str, default=None,
+                    choices=("batched", "small", "blocked", "grad", "convergence", "linear", "spim", "psf_refine"),
+                    help="run one side measurement alone (--steps timed runs after --warmup) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for HBM counters)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
@@ -603,6 +617,14 @@ def main():
 
     import torch
     from paper_1308_0730_amd import mvd
+
+    form_fns = {"batched": lambda st, wu: batched_form(st, wu), "small": small_form, "blocked": blocked_form,
+                "grad": grad_form, "convergence": lambda st, wu: convergence_form(),
+                "linear": linear_form, "spim": lambda st, wu: spim_form(),
+                "psf_refine": lambda st, wu: psf_refine_form()}
+    if args.only_form:
+        print(json.dumps({args.only_form: form_fns[args.only_form](args.steps, args.warmup)}), flush=True)
+        return
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -690,12 +712,13 @@ def main():
     forms = None
     if not args.no_forms:
         forms = {}
-        for name, fn in (("batched", lambda: batched_form(max(1, args.steps // 2), 1)),
-                         ("small", lambda: small_form(max(3, args.steps), 1)),
-                         ("blocked", lambda: blocked_form(max(1, args.steps // 2), 1)),
-                         ("grad", lambda: grad_form(3, 1)), ("convergence", convergence_form),
-                         ("linear", lambda: linear_form(max(1, args.steps // 2), 1)),
-                         ("spim", spim_form), ("psf_refine", psf_refine_form)):
+        for name, fn in (("batched", lambda: form_fns["batched"](max(1, args.steps // 2), 1)),
+                         ("small", lambda: form_fns["small"](max(3, args.steps), 1)),
+                         ("blocked", lambda: form_fns["blocked"](max(1, args.steps // 2), 1)),
+                         ("grad", lambda: form_fns["grad"](3, 1)),
+                         ("convergence", lambda: form_fns["convergence"](0, 0)),
+                         ("linear", lambda: form_fns["linear"](max(1, args.steps // 2), 1)),
+                         ("spim", lambda: form_fns["spim"](0, 0)), ("psf_refine", lambda: form_fns["psf_refine"](0, 0))):
             try:
                 forms[name] = fn()
             except Exception as e:  # a failing side measurement must not cost the main line

@@ -31,6 +31,7 @@ SOURCES = [
     ("mvd_exact_z.hip", True),
     ("mvd_exact_zext.hip", True),
     ("mvd_exact_x_comb.hip", True),
+    ("mvd_exact_x_win.hip", True),
     ("mvd_exact_x.hip", True),
     ("mvd_exact_y.hip", True),
     ("mvd_kernels_ct.hip", True),

@@ -131,8 +131,10 @@ struct ToRegs {
 // the last fold and the combined update (MODE 4), on the two real values held
 // by each complex output; the packed result goes to LDS as the input of the
 // forward transform.
-template <int MODE, int PITCH, int MAXB, int R>
+template <int MODE_, int PITCH, int MAXB, int R>
 struct RowOp {
+  static constexpr int MODE = MODE_ & 7;
+  static constexpr bool WIN = (MODE_ & XMODE_WIN) != 0;
   float2* buf;
   const float2 (&pa)[MAXB][R];
   const float2 (&pb)[MAXB][R];
@@ -165,7 +167,7 @@ struct RowOp {
       } else {
         o = make_float2(tx, ty);
       }
-      if (vol) {
+      if (WIN) {
         const int64_t b = own[line];
         const int x = 2 * pos - hx;
         if (b >= 0 && x >= 0 && x < ex) {
@@ -464,12 +466,15 @@ __global__ void __launch_bounds__(T)
 // ---------------------------------------------------------------------------
 // x pass (see k_xpass): MODE 0 R2C of psi, MODE 1 blur -> ratio -> R2C,
 // MODE 2 back-projection -> update -> R2C.  One wave owns RPW rows.
-template <int MODE, int WPB, int RPW, int M, int... Rs>
+template <int MODE_, int WPB, int RPW, int M, int... Rs>
 __global__ void __launch_bounds__(64 * WPB)
     k_xpass_ct(const JobDesc* __restrict__ jobs, int njobs, const FftPlan* __restrict__ plans,
                const float2* __restrict__ twp, int v, Partial* __restrict__ parts, int* __restrict__ flags,
                int opt) {
   constexpr int T = 64 * WPB;
+  constexpr int MODE = MODE_ & 7;
+  // the block-wise form's modes (0 and 2 reading and writing the volume)
+  constexpr bool WIN = (MODE_ & XMODE_WIN) != 0;
   constexpr bool UPD = MODE == 2 || MODE == 4;  // modes that write psi
   constexpr int RW = WPB * RPW;
   constexpr int NPAIR = M / 2 + 1;
@@ -483,16 +488,14 @@ __global__ void __launch_bounds__(64 * WPB)
   __shared__ unsigned ra[WPB], rb[WPB];
   // block-wise form: per row of the workgroup, the volume offset of its
   // window row (MODE 0) or of its own row (MODE 2; -1 for halo rows)
-  constexpr bool WIN = MODE == 0 || MODE == 2;
   __shared__ int64_t s_rows[WIN ? RW : 1];
   int local;
   const int jid = find_job(jobs, njobs, PASS_X, RW, local, true);
   if (jid < 0) return;
   const JobDesc& J = jobs[jid];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool win = WIN && J.vol != nullptr;
   bool skip = MODE != 0 && v >= J.nviews;
-  if (win && !skip) {
+  if (WIN && !skip) {
     int any = 0;
     for (int t = tid; t < RW; t += T) {
       const int r = local * RW + t;
@@ -539,7 +542,7 @@ __global__ void __launch_bounds__(64 * WPB)
   if (MODE == 0) {
     __syncthreads();  // twiddle tables
     Plain<LdsRow<M>> out{L};
-    if (win) {
+    if (WIN) {
       const WinRow src{J.vol, s_rows + wave * RPW, J.sx, J.vnx, nrw};
       CtRun<false, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, src, L, out);
     } else {
@@ -563,7 +566,7 @@ __global__ void __launch_bounds__(64 * WPB)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int64_t g = (int64_t)line * nx + 2 * (j + r * LM::NB);
-        if (MODE == 2 && win) {
+        if (MODE == 2 && WIN) {
           // psi of the own voxels from the volume
           const int64_t b = ok ? s_rows[wave * RPW + line] : -1;
           const int x = 2 * (j + r * LM::NB) - J.hx;
@@ -610,9 +613,9 @@ __global__ void __launch_bounds__(64 * WPB)
       }
     }
     gsync<SYNC_WAVE>();
-    RowOp<MODE, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff,
+    RowOp<MODE_, M, LM::MAXB, RL> op{L.p,   pa,    pb,  J.psi + rowoff,
                                     (MODE == 3 || MODE == 4) ? J.acc + rowoff : nullptr,
-                                    win ? J.vol : nullptr, s_rows + wave * RPW, J.ox, J.hx, J.ex,
+                                    J.vol, s_rows + wave * RPW, J.ox, J.hx, J.ex,
                                     nx,    nrw,   opb != nullptr,  first, geo,
                                     J.eps, J.lamp, 1.f / (float)J.nviews, 0.0, 0u, 0u, false};
     CtRun<true, M, 64, RPW, false, SYNC_WAVE, 1, true, Rs...>::run(lane, s_tw, L, L, op);

@@ -23,6 +23,7 @@ int mvd_exact_row_shape(int M, int* waves, int* rows) {
 
 hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt) {
   if (mode == 3 || mode == 4) return mvd_launch_x_exact_comb(a, M, mode, v, parts, flags, opt);
+  if (mode & XMODE_WIN) return mvd_launch_x_exact_win(a, M, mode, v, parts, flags, opt);
   switch (M) {
 #define XM(md, m, wpb, rpw, ...)                                                                         \
   case md:                                                                                               \

@@ -86,6 +86,8 @@ hipError_t mvd_launch_z_class(const LaunchArgs& a, int cls, int v, int role, int
 hipError_t mvd_launch_x_exact(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags, int opt);
 hipError_t mvd_launch_x_exact_comb(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
                                    int opt);
+hipError_t mvd_launch_x_exact_win(const LaunchArgs& a, int M, int mode, int v, Partial* parts, int* flags,
+                                  int opt);
 hipError_t mvd_launch_zext_exact(const LaunchArgs& a, int L, int v, int role, int conjH, float2* s_out,
                                  const float2* s_in, double2* acc, int acc_mode);
 

@@ -523,8 +523,8 @@ void drop_graphs(mvd_handle* h) {
 bool cfg_fits(const mvd_handle* h, int kind, int c) {
   if (c < 0 || c >= mvd_num_cfgs(kind)) return false;
   // the block-wise form's x passes read and write the volume in place: the
-  // compile-time-plan row kernels only
-  if (h->blocked && kind == PASS_X && mvd_cfg_exact(kind, c) == 0) return false;
+  // per-length row kernels only
+  if (h->blocked && kind == PASS_X && c != mvd_exact_cfg(kind)) return false;
   if (c == mvd_exact_cfg(kind)) {
     for (const auto& B : h->blocks)
       if (mvd_exact_param(kind, job_len(B, kind)) <= 0) return false;
@@ -1119,6 +1119,8 @@ void run_groups(mvd_handle* h, hipStream_t s, int kind, F&& launch) {
 }
 
 void run_x(mvd_handle* h, hipStream_t s, int mode, int v, Partial* parts, int opt) {
+  // the block-wise form's forward and update passes work on the volume
+  if (h->blocked && (mode == 0 || mode == 2)) mode |= XMODE_WIN;
   if (h->cfg_x != mvd_exact_cfg(PASS_X)) {
     HIPCHECK(mvd_launch_x(args(h, s, h->grid_x), h->cfg_x, mode, v, parts, h->d_flags, opt));
     return;

@@ -83,6 +83,11 @@ struct JobDesc {
 // product and |V|-th root, else by sum and division by |V|.
 enum { XOPT_SPEC = 1, XOPT_FIRST = 2, XOPT_GEO = 4 };
 
+// x pass modes 0 (forward of psi) and 2 (update) of the block-wise form take
+// this bit: the forward pass reads the block's window of the volume, the
+// update reads and writes the own voxels in the volume (JobDesc.vol).
+enum { XMODE_WIN = 8 };
+
 // Per-workgroup partial results of the x passes (one entry per x tile).
 struct Partial {
   double flux;
