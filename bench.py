@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 PASS_NAMES = ("y_forward", "y_inverse", "z_product", "x_ratio", "x_update")
 KERNEL_SOURCES = tuple("paper_1308_0730_amd/csrc/" + f for f in (
     "mvd_kernels.hip", "mvd_kernels_ct.hip", "mvd_ct_passes.h", "mvd_exact_x.hip", "mvd_exact_x_comb.hip",
+    "mvd_exact_x_win.hip",
     "mvd_exact_class.hip",
     "mvd_exact_y.hip", "mvd_exact_z.hip", "mvd_exact_lengths.h", "fft_engine.h", "fft_ct.h", "mvd_device.h",
     "mvd_gmem.h", "mvd_types.h", "fft_small_tw.h"))
