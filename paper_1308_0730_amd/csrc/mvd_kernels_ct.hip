@@ -17,7 +17,12 @@ using namespace mvdk;
   X(5, 128, 8, 256, 16, 16)       \
   X(6, 128, 16, 128, 16, 8)       \
   X(7, 64, 16, 64, 8, 8)          \
-  X(8, 512, 32, 256, 16, 16)
+  X(8, 512, 32, 256, 16, 16)      \
+  X(9, 64, 8, 128, 16, 8)         \
+  X(10, 64, 4, 128, 16, 8)        \
+  X(11, 128, 8, 128, 16, 8)       \
+  X(12, 64, 8, 64, 8, 8)          \
+  X(13, 64, 4, 64, 8, 8)
 
 #define MVD_CT_ROW_CFGS(X)      \
   X(0, 2, 4, 256, 16, 16)       \
@@ -27,7 +32,10 @@ using namespace mvdk;
   X(4, 2, 8, 128, 16, 8)        \
   X(5, 2, 8, 64, 8, 8)          \
   X(6, 2, 16, 32, 8, 4)         \
-  X(7, 4, 4, 256, 16, 16)
+  X(7, 4, 4, 256, 16, 16)       \
+  X(8, 1, 16, 32, 8, 4)         \
+  X(9, 1, 8, 64, 8, 8)          \
+  X(10, 1, 8, 128, 16, 8)
 
 static const int kCtColCfg[][3] = {
 #define X(i, t, tx, l, ...) {t, tx, l},

@@ -208,7 +208,8 @@ def test_device_value_checks(mvd):
     assert e.value.code == mvd.MVD_EINVAL
 
 
-SHAPE_DIMS = [(64, 64, 64), (512, 64, 32), (32, 512, 64), (32, 64, 256), (64, 128, 512), (150, 96, 100)]
+SHAPE_DIMS = [(64, 64, 64), (512, 64, 32), (32, 512, 64), (32, 64, 256), (64, 128, 512), (150, 96, 100), (128, 128, 64),
+              (256, 32, 128)]
 
 
 @pytest.mark.parametrize("dims", SHAPE_DIMS)
