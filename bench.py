@@ -97,6 +97,23 @@ def pass_bytes(blocks, weighted):
     return out
 
 
+def parse_tiles(d, spec):
+    """Launch shapes from 'x,y,z': a candidate index per pass kind, or p for
+    the per-length compile-time plans of that kind."""
+    from paper_1308_0730_amd import mvd
+    lens = d.max_lengths()
+    out = []
+    for kind, f in enumerate(spec.split(",")):
+        if f.strip() == "p":
+            c = [c for c in mvd.tile_candidates(kind, lens[kind]) if mvd.tile_shape(kind, c)["exact_len"] < 0]
+            if not c:
+                raise SystemExit(f"no per-length plan for pass kind {kind}")
+            out.append(c[0])
+        else:
+            out.append(int(f))
+    return out
+
+
 def source_hash():
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -582,7 +599,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=60.0)
     ap.add_argument("--profile-iters", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--tiles", type=str, default=None, help="force launch shapes 'x,y,z'")
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="force launch shapes 'x,y,z': candidate indices, or p for the per-length plans")
     ap.add_argument("--schedule", type=str, default=None, choices=("pass", "block", "run"),
                     help="force the schedule of a multi-block handle")
     ap.add_argument("--no-forms", action="store_true",
@@ -650,7 +668,7 @@ def main():
     print(f"[bench] created handle in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.time()
     if args.tiles:
-        d.set_tiles(*[int(x) for x in args.tiles.split(",")])
+        d.set_tiles(*parse_tiles(d, args.tiles))
         if args.schedule:
             d.set_schedule(args.schedule)
     elif not args.no_tune:

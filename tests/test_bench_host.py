@@ -90,3 +90,14 @@ def test_counter_summary_scales_by_the_copy(tmp_path):
     assert abs(measured - 2 * S) / (2 * S) < 1e-3
     assert abs(float(fields[3]) - 2 * S) <= 1e-4 * 2 * S
     assert fields[4] == "8"
+
+
+def test_tiles_spec_names_the_per_length_plans():
+    """--tiles takes a candidate index per pass kind or p for the per-length
+    plans (whatever index the candidate table gives them)."""
+    from paper_1308_0730_amd import mvd
+    d = SimpleNamespace(max_lengths=lambda: (256, 512, 256))
+    x, y, z = bench.parse_tiles(d, "p,9,12")
+    assert (y, z) == (9, 12)
+    assert mvd.tile_shape(0, x)["exact_len"] < 0 and x in mvd.tile_candidates(0, 256)
+    assert all(mvd.tile_shape(k, c)["exact_len"] < 0 for k, c in enumerate(bench.parse_tiles(d, "p,p,p")))
