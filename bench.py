@@ -196,6 +196,33 @@ def summarize_kernel_trace(d, title, command, top=20):
     return "\n".join(lines)
 
 
+def summarize_sq_counters(d, title, command, top=12):
+    """Per-launch averages of the SQ counters of a rocprofv3 --pmc run (CSV)
+    for the kernels with the most vector instructions; issue shares against
+    the chip's vector rate are left to the reader (one wave instruction
+    covers 64 lanes; a SIMD issues one every 4 cycles)."""
+    rows = _csv_rows(d, "counter_collection.csv")
+    agg, n, names = {}, {}, []
+    for r in rows:
+        k, c = r["Kernel_Name"], r["Counter_Name"]
+        if k not in agg:
+            agg[k], n[k] = {}, {}
+            names.append(k)
+        agg[k][c] = agg[k].get(c, 0.0) + float(r["Counter_Value"])
+        n[k][c] = n[k].get(c, 0) + 1
+    counters = sorted({c for k in agg for c in agg[k]})
+    key = "SQ_INSTS_VALU" if "SQ_INSTS_VALU" in counters else counters[0]
+    names = [k for k in names if pass_of_kernel(k)]
+    names.sort(key=lambda k: -agg[k].get(key, 0.0))
+    lines = [f"# rocprofv3 SQ counters per launch: {title}", f"# command: {command}",
+             f"# source_hash: {source_hash()}", "# name | launches | " + " | ".join(counters)]
+    for k in names[:top]:
+        m = max(n[k].values())
+        lines.append(f"{_short(k)} | {m} | " + " | ".join(f"{agg[k].get(c, 0.0) / n[k].get(c, 1):.4e}"
+                                                          for c in counters))
+    return "\n".join(lines)
+
+
 def summarize_counters(fetch_dir, write_dir, cfg, iterations, title, commands):
     """HBM bytes per pass launch (one pass over every block) from a
     FETCH_SIZE run and a WRITE_SIZE run, each scaled by what the counter
@@ -619,11 +646,16 @@ def main():
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "TITLE", "COMMANDS"),
                     help="print the HBM-traffic summary of a FETCH_SIZE and a WRITE_SIZE rocprofv3 run (CSV) of "
                          "--config; COMMANDS separated by ';;'")
+    ap.add_argument("--summarize-sq", nargs=3, metavar=("DIR", "TITLE", "COMMAND"),
+                    help="print the per-launch SQ counter summary of a rocprofv3 --pmc run (CSV)")
     ap.add_argument("--counted-iterations", type=int, default=12,
                     help="iterations the profiled command ran (1 at create + steps x iterations + profile iterations)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_kernel_trace(*args.summarize_trace))
+        return
+    if args.summarize_sq:
+        print(summarize_sq_counters(*args.summarize_sq))
         return
     if args.summarize_counters:
         fd, wd, title, cmds = args.summarize_counters

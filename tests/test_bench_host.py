@@ -101,3 +101,26 @@ def test_tiles_spec_names_the_per_length_plans():
     assert (y, z) == (9, 12)
     assert mvd.tile_shape(0, x)["exact_len"] < 0 and x in mvd.tile_candidates(0, 256)
     assert all(mvd.tile_shape(k, c)["exact_len"] < 0 for k, c in enumerate(bench.parse_tiles(d, "p,p,p")))
+
+
+def test_sq_counter_summary_averages_per_launch(tmp_path):
+    """Synthetic SQ counter file: two launches of a y pass and one of an x
+    pass; the summary lists per-launch averages, the kernel with the most
+    vector instructions first, and leaves out non-pass kernels."""
+    import csv
+    with open(tmp_path / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+        for val in (100.0, 300.0):
+            w.writerow(["void mvdk::k_ypass_ct<false, 64, 16, 64, 8, 8>(x)", "SQ_INSTS_VALU", val])
+            w.writerow(["void mvdk::k_ypass_ct<false, 64, 16, 64, 8, 8>(x)", "SQ_INSTS_LDS", 10.0])
+        w.writerow(["void mvdk::k_xpass_ct<1, 2, 8, 64, 8, 8>(x)", "SQ_INSTS_VALU", 1000.0])
+        w.writerow(["void mvdk::k_xpass_ct<1, 2, 8, 64, 8, 8>(x)", "SQ_INSTS_LDS", 50.0])
+        w.writerow(["k_reduce(x)", "SQ_INSTS_VALU", 5.0e6])
+    txt = bench.summarize_sq_counters(str(tmp_path), "t", "c")
+    body = [l for l in txt.splitlines() if not l.startswith("#")]
+    assert len(body) == 2 and body[0].startswith("void mvdk::k_xpass_ct<1")
+    header = [l for l in txt.splitlines() if l.startswith("# name")][0].split(" | ")
+    y = body[1].split(" | ")
+    assert y[1] == "2"
+    assert float(y[header.index("SQ_INSTS_VALU")]) == 200.0 and float(y[header.index("SQ_INSTS_LDS")]) == 10.0
