@@ -160,7 +160,8 @@ def pass_of_kernel(name):
         return "y_inverse" if arg == "true" else "y_forward"
     if kind == "zconv":
         return "z_product"
-    return {"0": "x_forward", "1": "x_ratio", "2": "x_update"}.get(arg)
+    # modes 8 and 10: the block-wise form's forward and update passes
+    return {"0": "x_forward", "1": "x_ratio", "2": "x_update", "8": "x_forward", "10": "x_update"}.get(arg)
 
 
 def _short(name, n=150):
@@ -196,7 +197,7 @@ def summarize_kernel_trace(d, title, command, top=20):
     return "\n".join(lines)
 
 
-def summarize_sq_counters(d, title, command, top=12):
+def summarize_sq_counters(d, title, command, top=20):
     """Per-launch averages of the SQ counters of a rocprofv3 --pmc run (CSV)
     for the kernels with the most vector instructions; issue shares against
     the chip's vector rate are left to the reader (one wave instruction

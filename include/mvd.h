@@ -187,8 +187,8 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
  * voxels on each side (wrapping periodically), runs the view-update of
  * mvd_iterate on that window's grid (the largest block plus twice the halo,
  * rounded up to a transform length; every block uses the same grid), and
- * pastes the block's own voxels back; every block of a view-update reads the
- * estimate from before that view-update.  With halo >= twice the largest
+ * writes the block's own voxels back into the estimate; every block of a
+ * view-update reads the estimate from before that view-update.  With halo >= twice the largest
  * PSF radius per axis the result equals the whole-volume update.
  *   p      the volume (dims any extents >= 1; views, PSFs and weights as for
  *          mvd_create; host or device memory)

@@ -58,6 +58,8 @@ def test_pass_of_kernel_names():
         "void mvdk::k_xpass_ct<1, 4, 2, 256, 8, 8, 4>(JobDesc const*)": "x_ratio",
         "void mvdk::k_xpass<2, 2, 4, 256>(JobDesc const*)": "x_update",
         "void mvdk::k_xpass_ct<0, 2, 4, 256, 16, 16>(JobDesc const*)": "x_forward",
+        "void mvdk::k_xpass_ct<8, 4, 2, 432, 4, 4, 3, 3, 3>(JobDesc const*)": "x_forward",
+        "void mvdk::k_xpass_ct<10, 4, 2, 432, 4, 4, 3, 3, 3>(JobDesc const*)": "x_update",
         "k_check(float const*, long)": None,
         "__amd_rocclr_copyBuffer": None,
     }
