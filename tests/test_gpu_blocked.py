@@ -182,3 +182,26 @@ def test_larva_scale_sampled(mvd, larva):
     emax = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), scale)))
     print(f"sampled view-update: rel_l2={e:.3e} max rel={emax:.3e} over {len(pts)} voxels")
     assert e <= 1e-5 and emax <= 1e-5
+
+
+@pytest.mark.parametrize("dims,psf_shape,tiles", [((10, 12, 9), (9, 9, 9), (1, 1, 1)),
+                                                  ((3, 5, 4), (3, 3, 3), (1, 1, 1)),
+                                                  ((21, 17, 13), (7, 5, 9), (3, 2, 2))])
+def test_windows_wider_than_the_volume(mvd, dims, psf_shape, tiles):
+    """Windows that wrap around the volume several times along x (a 30-point
+    grid on a 10-voxel volume), the smallest grid (8 points along x for a
+    3-voxel volume), and blocks thinner than their halo: still the
+    whole-volume update, two iterations with weights and lambda."""
+    views, psfs, w = problem(dims, 2, 409, True, psf_shape=psf_shape)
+    pb = O.Problem(views, psfs, w, 0.01)
+    psi = pb.psi0()
+    with mvd.Deconvolver.blocked(views, psfs, w, tiles=tiles, lam=0.01) as d:
+        g = d.grid_dims(0)
+        print("grid", g, "blocking", d.blocking())
+        assert g[0] >= 8
+        for it in range(2):
+            psi = pb.iterate(psi, 1, O.OPT1)
+            d.iterate(1, O.OPT1)
+            e = rel(d.estimate().cpu().numpy(), psi)
+            print(f"iteration {it + 1}: rel_l2={e:.3e}")
+            assert e <= (ONE_STEP if it == 0 else TRAJ), (it, e)
