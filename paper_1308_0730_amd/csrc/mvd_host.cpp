@@ -34,6 +34,25 @@ void parallel_for(int n, const std::function<void(int)>& f) {
   for (auto& t : th) t.join();
 }
 
+}  // namespace
+
+bool all_within(const float* x, int64_t n, float lo, float hi) {
+  constexpr int64_t chunk = 1 << 20;
+  const int nc = (int)((n + chunk - 1) / chunk);
+  std::atomic<bool> ok{true};
+  parallel_for(nc, [&](int c) {
+    if (!ok.load(std::memory_order_relaxed)) return;
+    const int64_t a = (int64_t)c * chunk, b = std::min(n, a + chunk);
+    // comparisons are false for NaN; the last one rejects +inf when hi is +inf
+    int64_t nbad = 0;
+    for (int64_t i = a; i < b; ++i) nbad += !(x[i] >= lo && x[i] <= hi && x[i] < INFINITY);
+    if (nbad) ok = false;
+  });
+  return ok;
+}
+
+namespace {
+
 inline int wrap(long long k, long long d, int n) {
   long long m = (k * d) % n;
   if (m < 0) m += n;
@@ -380,29 +399,70 @@ std::vector<std::vector<double>> compound_kernel_vjp(const std::vector<Kern>& P,
   return compound_kernels_vjp(P, variant, all);
 }
 
-std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny) {
+namespace {
+
+// x and y stages of the spectrum of a centred kernel on an (nx, ny) grid,
+// plane by plane in parallel; store(dz, ky, kx, value) receives every
+// kx <= nx / 2.
+template <class Store>
+void spectrum_xy_planes(const Kern& K, int nx, int ny, Store&& store) {
   const int M = nx / 2;
   const auto tx = twiddles(nx), ty = twiddles(ny);
   const int cx = (K.kx - 1) / 2, cy = (K.ky - 1) / 2;
-  std::vector<cd> A2((size_t)K.kz * ny * (M + 1));
+  const int W = M + 1;
   parallel_for(K.kz, [&](int z) {
-    std::vector<cd> A1((size_t)K.ky * (M + 1));
+    // x stage of every kernel row, real and imaginary parts apart so the
+    // y stage's inner loop vectorises
+    std::vector<double> re((size_t)K.ky * W), im((size_t)K.ky * W), sr(W), si(W);
     for (int y = 0; y < K.ky; ++y)
       for (int k = 0; k <= M; ++k) {
+        // phase index k (x - cx) mod nx, stepped by k along x
+        int idx = wrap(k, -cx, nx);
         cd s = 0;
-        for (int x = 0; x < K.kx; ++x) s += K.at(z, y, x) * tx[wrap(k, x - cx, nx)];
-        A1[(size_t)y * (M + 1) + k] = s;
+        for (int x = 0; x < K.kx; ++x) {
+          s += K.at(z, y, x) * tx[idx];
+          idx += k;
+          if (idx >= nx) idx -= nx;
+        }
+        re[(size_t)y * W + k] = s.real();
+        im[(size_t)y * W + k] = s.imag();
       }
     for (int k = 0; k < ny; ++k) {
-      cd* a2 = &A2[((size_t)z * ny + k) * (M + 1)];
+      std::fill(sr.begin(), sr.end(), 0.0);
+      std::fill(si.begin(), si.end(), 0.0);
       for (int y = 0; y < K.ky; ++y) {
-        const cd w = ty[wrap(k, y - cy, ny)];
-        const cd* a1 = &A1[(size_t)y * (M + 1)];
-        for (int x = 0; x <= M; ++x) a2[x] += a1[x] * w;
+        const double wr = ty[wrap(k, y - cy, ny)].real(), wi = ty[wrap(k, y - cy, ny)].imag();
+        const double* ar = &re[(size_t)y * W];
+        const double* ai = &im[(size_t)y * W];
+        for (int x = 0; x < W; ++x) {
+          sr[x] += ar[x] * wr - ai[x] * wi;
+          si[x] += ar[x] * wi + ai[x] * wr;
+        }
       }
+      for (int x = 0; x < W; ++x) store(z, k, x, sr[x], si[x]);
     }
   });
+}
+
+}  // namespace
+
+std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny) {
+  const int W = nx / 2 + 1;
+  std::vector<cd> A2((size_t)K.kz * ny * W);
+  spectrum_xy_planes(K, nx, ny, [&](int z, int ky, int kx, double r, double i) {
+    A2[((size_t)z * ny + ky) * W + kx] = cd(r, i);
+  });
   return A2;
+}
+
+void spectrum_xy_f32(const Kern& K, int nx, int ny, double scale, int d0, int Mp, int64_t h_main, float* out) {
+  const int M = nx / 2;
+  spectrum_xy_planes(K, nx, ny, [&](int z, int ky, int kx, double r, double i) {
+    const size_t d = (size_t)(z + d0);
+    const size_t o = kx < M ? (d * ny + ky) * Mp + kx : (size_t)h_main + d * ny + ky;
+    out[2 * o] = (float)(r * scale);
+    out[2 * o + 1] = (float)(i * scale);
+  });
 }
 
 void spectrum_host(const Kern& K, int nx, int ny, int nz, float* main_out, float* nyq_out) {

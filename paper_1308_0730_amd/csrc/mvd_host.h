@@ -19,6 +19,8 @@ struct Kern {
 };
 
 bool is_smooth5(int n);
+// True if every x[i] is finite and in [lo, hi] (checked on several threads).
+bool all_within(const float* x, int64_t n, float lo, float hi);
 // Radices (8, 4, 2, 3, 5) of a 5-smooth length, largest first.
 std::vector<int> factorize(int n);
 
@@ -48,6 +50,11 @@ std::vector<std::vector<double>> compound_kernels_vjp(const std::vector<Kern>& P
 // Stages x and y of the spectrum of a centred kernel on a volume grid:
 // A2[dz][ky][kx], kx in [0, nx/2], for every kernel plane dz.
 std::vector<cd> spectrum_xy(const Kern& K, int nx, int ny);
+// The same scaled by `scale` and rounded to FP32, written in the device
+// layout of kernel planes: plane dz goes to plane dz + d0, kx < nx / 2 at
+// ((dz + d0) ny + ky) Mp + kx and kx = nx / 2 at h_main + (dz + d0) ny + ky
+// (complex: real then imaginary float); nothing else of out is written.
+void spectrum_xy_f32(const Kern& K, int nx, int ny, double scale, int d0, int Mp, int64_t h_main, float* out);
 // exp(-2 pi i m / n), m < n.
 std::vector<cd> twiddles(int n);
 // Full spectrum on the host (all three stages), scaled by 1/V, split into

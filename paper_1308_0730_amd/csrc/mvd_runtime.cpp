@@ -279,14 +279,10 @@ void validate_host_values(const mvd_problem* p, int idx) {
   const std::string b = "block " + std::to_string(idx) + ": ";
   const int64_t V = vox(p->dims);
   for (int v = 0; v < p->n_views; ++v) {
-    const float* x = p->views[v];
-    for (int64_t i = 0; i < V; ++i)
-      if (!(x[i] >= 0.f) || !std::isfinite(x[i])) bad(b + "view " + std::to_string(v) + " has a negative or non-finite value");
-    if (p->weights) {
-      const float* w = p->weights[v];
-      for (int64_t i = 0; i < V; ++i)
-        if (!(w[i] >= 0.f && w[i] <= 1.f)) bad(b + "weights " + std::to_string(v) + " outside [0, 1]");
-    }
+    if (!mvdh::all_within(p->views[v], V, 0.f, INFINITY))
+      bad(b + "view " + std::to_string(v) + " has a negative or non-finite value");
+    if (p->weights && !mvdh::all_within(p->weights[v], V, 0.f, 1.f))
+      bad(b + "weights " + std::to_string(v) + " outside [0, 1]");
   }
 }
 
@@ -369,19 +365,9 @@ void set_kernel_window(Block& B) {
 // FP32.  The z stage is done by the z pass.
 void upload_kernel(mvd_handle* h, const Block& B, const mvdh::Kern& K, float* dst) {
   if (K.kz > B.kz || (B.kz - K.kz) % 2) bad("kernel does not fit the z window");
-  const auto A2 = mvdh::spectrum_xy(K, B.nx, B.ny);  // [K.kz][ny][M + 1]
-  const int M = B.M, ny = B.ny, d0 = (B.kz - K.kz) / 2;
-  const double inv = 1.0 / (double)B.V;
+  // x and y stages in FP64, scaled by 1/V, on the common z window
   std::vector<float> hk((size_t)B.h_elems * 2, 0.f);
-  for (int dz = 0; dz < K.kz; ++dz)
-    for (int ky = 0; ky < ny; ++ky)
-      for (int kx = 0; kx <= M; ++kx) {
-        const mvdh::cd a = A2[((size_t)dz * ny + ky) * (M + 1) + kx] * inv;
-        const size_t d = (size_t)(dz + d0);
-        const size_t o = kx < M ? (d * ny + ky) * B.Mp + kx : (size_t)B.h_main + d * ny + ky;
-        hk[2 * o] = (float)a.real();
-        hk[2 * o + 1] = (float)a.imag();
-      }
+  mvdh::spectrum_xy_f32(K, B.nx, B.ny, 1.0 / (double)B.V, (B.kz - K.kz) / 2, B.Mp, B.h_main, hk.data());
   HIPCHECK(hipMemcpyAsync(dst, hk.data(), hk.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
 }

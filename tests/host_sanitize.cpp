@@ -87,6 +87,31 @@ int main() {
     for (float x : main_out) CHECK(std::isfinite(x));
     // DC term: the kernel's sum times 1/V
     CHECK(std::fabs(main_out[0] - 1.0f / (nx * ny * nz)) < 1e-7f);
+    // the device layout of the kernel planes: one plane of margin on each
+    // side of the window, rows padded to 16 complex, the Nyquist column apart
+    const int kzw = P[0].kz + 2, M = nx / 2, Mp = 16;
+    const int64_t h_main = (int64_t)Mp * ny * kzw;
+    std::vector<float> planes((size_t)(h_main + (int64_t)ny * kzw) * 2, -7.0f);
+    spectrum_xy_f32(P[0], nx, ny, 0.5, 1, Mp, h_main, planes.data());
+    const auto A2 = spectrum_xy(P[0], nx, ny);
+    for (int d = 0; d < kzw; ++d)
+      for (int ky = 0; ky < ny; ++ky)
+        for (int kx = 0; kx < Mp; ++kx) {
+          const size_t o = ((size_t)d * ny + ky) * Mp + kx;
+          if (d == 0 || d == kzw - 1 || kx >= M) {
+            CHECK(planes[2 * o] == -7.0f && planes[2 * o + 1] == -7.0f);
+          } else {
+            const cd a = A2[((size_t)(d - 1) * ny + ky) * (M + 1) + kx] * 0.5;
+            CHECK(std::fabs(planes[2 * o] - (float)a.real()) <= 1e-6f * (1.0f + std::fabs((float)a.real())));
+            CHECK(std::fabs(planes[2 * o + 1] - (float)a.imag()) <= 1e-6f * (1.0f + std::fabs((float)a.imag())));
+          }
+        }
+    for (int d = 1; d + 1 < kzw; ++d)
+      for (int ky = 0; ky < ny; ++ky) {
+        const size_t o = (size_t)h_main + (size_t)d * ny + ky;
+        const cd a = A2[((size_t)(d - 1) * ny + ky) * (M + 1) + M] * 0.5;
+        CHECK(std::fabs(planes[2 * o] - (float)a.real()) <= 1e-6f * (1.0f + std::fabs((float)a.real())));
+      }
     for (int n = 1; n <= 1024; ++n)
       if (is_smooth5(n)) {
         int prod = 1;
