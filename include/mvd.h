@@ -23,7 +23,8 @@
  *   MVD_OPT2 K_v = (P_v*)^N                                     (eq. 240, Optimization II)
  * each normalised to sum one (every kernel is a probability distribution, eq. 3).
  * Scale: s = mean over all voxels of all views; psi starts flat at s (the
- * constant initial guess of eq. 15); eps = eps_scale * s; lambda' = lambda / s.
+ * constant initial guess of eq. 15); eps = eps_scale * s (in FP32, at least
+ * the smallest normal float); lambda' = lambda / s.
  *
  * Layout.  A volume of dims {nx, ny, nz} is nx*ny*nz float32, C order
  * [z][y][x], x fastest.  A PSF of dims {kx, ky, kz} is kx*ky*kz float32 in the

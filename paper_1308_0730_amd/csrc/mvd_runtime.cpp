@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <set>
@@ -295,6 +296,13 @@ std::vector<float> fetch_psf(const mvd_problem* p, int v) {
   else
     HIPCHECK(hipMemcpy(h.data(), p->psfs[v], n * sizeof(float), hipMemcpyDeviceToHost));
   return h;
+}
+
+// The ratio guard eps = eps_scale * s in FP32, at least the smallest normal
+// float: the ratio pass takes the hardware reciprocal of max(b, eps), which
+// must stay finite (only views with a mean below about 1e-32 reach it).
+float ratio_guard(const mvd_handle* h, double s) {
+  return std::max((float)(h->eps_scale * s), std::numeric_limits<float>::min());
 }
 
 // Device check of one array: count of values outside [lo, hi] (or
@@ -830,7 +838,7 @@ void create_impl(mvd_handle* h, int nb, const mvd_problem* ps, const mvd_options
       for (int v = 0; v < N; ++v)
         HIPCHECK(mvd_launch_fill_outside(B.phi + (size_t)v * B.V, grid_dims(B), user_dims(B), offsets(B), MVD_NO_DATA,
                                          h->stream));
-    B.eps = (float)(h->eps_scale * B.s);
+    B.eps = ratio_guard(h, B.s);
     B.lamp = (float)(h->lambda / B.s);
     if (p.mem_kind == MVD_MEM_DEVICE) {
       for (int v = 0; v < N; ++v) {
@@ -1015,7 +1023,7 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
   for (int b = 0; b < nb; ++b) {
     Block& B = h->blocks[b];
     B.s = s;
-    B.eps = (float)(h->eps_scale * s);
+    B.eps = ratio_guard(h, s);
     B.lamp = (float)(h->lambda / s);
     B.P = prepared;
     B.psf_sum = psf_sum;
