@@ -199,7 +199,9 @@ int mvd_create_batch(mvd_handle** out, int n_blocks, const mvd_problem* blocks,
  *          the transform lengths (nx <= 2 MVD_MAX_LEN, ny, nz <=
  *          MVD_MAX_LEN_YZ)
  *   halo   NULL (twice the largest odd-padded PSF radius per axis, the
- *          exact choice) or {hx, hy, hz} >= 0
+ *          exact choice; none along an axis with one block whose extent is
+ *          a transform length, where the grid is the volume's period) or
+ *          {hx, hy, hz} >= 0
  * MVD_EINVAL if a block's grid exceeds the transform lengths.  The handle
  * runs the sequential scheme (mvd_iterate, mvd_view_update, mvd_profile,
  * mvd_get_estimate and mvd_set_estimate of the whole volume as block 0,

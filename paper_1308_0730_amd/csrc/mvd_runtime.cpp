@@ -921,9 +921,13 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
     T.halo[a] = halo ? halo[a] : 2 * R[a];
     if (T.halo[a] < 0) bad("halo must be >= 0");
     const int n = T.dims[a];
+    // one block along an axis whose extent is a transform length: the grid
+    // is the volume's period itself, exact without a halo
+    const bool period = n >= kmax[a] && n >= (a == 0 ? 8 : 2) && next_smooth5(n, a == 0) == n;
+    auto halo_for = [&](int t) { return !halo && t == 1 && period ? 0 : T.halo[a]; };
     auto grid_for = [&](int t) {
       const int ext = (n + t - 1) / t;
-      const int g = std::max({ext + 2 * T.halo[a], kmax[a], a == 0 ? 8 : 2});
+      const int g = std::max({ext + 2 * halo_for(t), kmax[a], a == 0 ? 8 : 2});
       return next_smooth5(g, a == 0);
     };
     int t = tiles ? tiles[a] : 0;
@@ -939,6 +943,7 @@ void create_blocked_impl(mvd_handle* h, const mvd_problem* p, const mvd_options*
         while (t < n && grid_for(t) > lim[a]) ++t;
       }
     }
+    T.halo[a] = halo_for(t);
     G[a] = grid_for(t);
     if (G[a] > lim[a])
       bad("a block's grid (the block plus the halo on both sides) exceeds the largest transform length along axis " +

@@ -72,14 +72,14 @@ def test_thin_halo_follows_the_oracles_blocked_form(mvd, variant):
 
 def test_beyond_the_transform_lengths(mvd):
     """2050x1030x8: x beyond 2048 and y beyond 1024 points.  The default
-    blocking takes three blocks along x and y (720x360x12 grids: half-rows
-    and columns within 512 points); two blocks along each give the longest
-    grids (1080x540x12).  One iteration of each against the whole-volume
-    oracle."""
+    blocking takes three blocks along x and y (720x360x8 grids: half-rows
+    and columns within 512 points; z, one block of a transform length, needs
+    no halo); two blocks along each give the longest grids (1080x540x8).
+    One iteration of each against the whole-volume oracle."""
     views, psfs, _ = problem((2050, 1030, 8), 2, 403, psf_shape=(3, 5, 5))
     pb = O.Problem(views, psfs, None, 0.0)
     ref = pb.iterate(pb.psi0(), 1, O.EFF)
-    for tiles_in, tiles_out, grid in ((None, (3, 3, 1), (720, 360, 12)), ((2, 2, 1), (2, 2, 1), (1080, 540, 12))):
+    for tiles_in, tiles_out, grid in ((None, (3, 3, 1), (720, 360, 8)), ((2, 2, 1), (2, 2, 1), (1080, 540, 8))):
         with mvd.Deconvolver.blocked(views, psfs, tiles=tiles_in) as d:
             tiles, halo, _ = d.blocking()
             print("tiles", tiles, "halo", halo, "grid", d.grid_dims(0))
@@ -184,10 +184,10 @@ def test_larva_scale_sampled(mvd, larva):
     assert e <= 1e-5 and emax <= 1e-5
 
 
-@pytest.mark.parametrize("dims,psf_shape,tiles", [((10, 12, 9), (9, 9, 9), (1, 1, 1)),
-                                                  ((3, 5, 4), (3, 3, 3), (1, 1, 1)),
-                                                  ((21, 17, 13), (7, 5, 9), (3, 2, 2))])
-def test_windows_wider_than_the_volume(mvd, dims, psf_shape, tiles):
+@pytest.mark.parametrize("dims,psf_shape,tiles,halo", [((10, 12, 9), (9, 9, 9), (1, 1, 1), (8, 8, 8)),
+                                                       ((3, 5, 4), (3, 3, 3), (1, 1, 1), (2, 2, 2)),
+                                                       ((21, 17, 13), (7, 5, 9), (3, 2, 2), None)])
+def test_windows_wider_than_the_volume(mvd, dims, psf_shape, tiles, halo):
     """Windows that wrap around the volume several times along x (a 30-point
     grid on a 10-voxel volume), the smallest grid (8 points along x for a
     3-voxel volume), and blocks thinner than their halo: still the
@@ -195,10 +195,31 @@ def test_windows_wider_than_the_volume(mvd, dims, psf_shape, tiles):
     views, psfs, w = problem(dims, 2, 409, True, psf_shape=psf_shape)
     pb = O.Problem(views, psfs, w, 0.01)
     psi = pb.psi0()
-    with mvd.Deconvolver.blocked(views, psfs, w, tiles=tiles, lam=0.01) as d:
+    with mvd.Deconvolver.blocked(views, psfs, w, tiles=tiles, halo=halo, lam=0.01) as d:
         g = d.grid_dims(0)
         print("grid", g, "blocking", d.blocking())
         assert g[0] >= 8
+        for it in range(2):
+            psi = pb.iterate(psi, 1, O.OPT1)
+            d.iterate(1, O.OPT1)
+            e = rel(d.estimate().cpu().numpy(), psi)
+            print(f"iteration {it + 1}: rel_l2={e:.3e}")
+            assert e <= (ONE_STEP if it == 0 else TRAJ), (it, e)
+
+
+def test_single_block_axes_of_transform_length_take_no_halo(mvd):
+    """64x45x32 in one block along x and z (transform lengths: the grid is
+    the volume's period there, no halo) and two along y (45 is not a
+    transform length; halo of twice the radius): the whole-volume update,
+    two iterations with weights and lambda."""
+    views, psfs, w = problem((64, 45, 32), 2, 410, True)
+    pb = O.Problem(views, psfs, w, 0.01)
+    psi = pb.psi0()
+    with mvd.Deconvolver.blocked(views, psfs, w, tiles=(1, 2, 1), lam=0.01) as d:
+        tiles, halo, _ = d.blocking()
+        g = d.grid_dims(0)
+        print("halo", halo, "grid", g)
+        assert halo == (0, 6, 0) and g[0] == 64 and g[2] == 32
         for it in range(2):
             psi = pb.iterate(psi, 1, O.OPT1)
             d.iterate(1, O.OPT1)
