@@ -699,8 +699,10 @@ def main():
     d.synchronize()
     # create from host arrays: validation, the copies over PCIe, the kernel planes
     create_s = time.time() - t0
+    t1 = time.time()
     d.iterate(1, meta["variant"])  # builds the compound spectra and the graph
     d.synchronize()
+    first_s = time.time() - t1
     print(f"[bench] created handle in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.time()
     if args.tiles:
@@ -747,9 +749,13 @@ def main():
     for b in range(len(blocks)):
         d.estimate(b).cpu()
     d2h_s = time.time() - t1
-    pcie = {"create_s": round(create_s, 3), "d2h_ms": round(d2h_s * 1e3, 2),
-            "value": round(vox_updates / (create_s + ms / 1e3 + d2h_s) / 1e9, 3), "unit": "Gvox/s",
-            "note": "one run with its create from host arrays and the estimate copied back (wall clock)"}
+    # a one-shot run: create, the first iteration with its one-time builds
+    # (compound kernels, graph capture), the other iterations, the estimate back
+    one_shot = create_s + first_s + (its - 1) / its * ms / 1e3 + d2h_s
+    pcie = {"create_s": round(create_s, 3), "first_iteration_s": round(first_s, 3), "d2h_ms": round(d2h_s * 1e3, 2),
+            "value": round(vox_updates / one_shot / 1e9, 3), "unit": "Gvox/s",
+            "note": "one run with its create from host arrays, its first iteration's one-time builds and the "
+                    "estimate copied back (wall clock)"}
     by = pass_bytes(blocks, weighted)
     total = {k: prof[k][0] * prof[k][1] for k in PASS_NAMES}
     dom = max(total, key=total.get)

@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <exception>
 #include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <thread>
 
@@ -18,7 +20,8 @@ int n_threads() {
   return (int)std::min(h, 32u);
 }
 
-// Run f(i) for i in [0, n) on a few threads.
+// Run f(i) for i in [0, n) on a few threads; the first exception thrown by
+// f is rethrown on the calling thread once every thread has finished.
 void parallel_for(int n, const std::function<void(int)>& f) {
   const int nt = std::min(n, n_threads());
   if (nt <= 1) {
@@ -26,12 +29,21 @@ void parallel_for(int n, const std::function<void(int)>& f) {
     return;
   }
   std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
   std::vector<std::thread> th;
   for (int t = 0; t < nt; ++t)
     th.emplace_back([&] {
-      for (int i = next++; i < n; i = next++) f(i);
+      try {
+        for (int i = next++; i < n; i = next++) f(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!err) err = std::current_exception();
+        next = n;
+      }
     });
   for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
 }
 
 }  // namespace
@@ -53,6 +65,18 @@ bool all_within(const float* x, int64_t n, float lo, float hi) {
 
 namespace {
 
+// f[i] += b[i] * w for i < n, in real arithmetic (vectorises)
+inline void cmac(cd* f, const cd* b, cd w, size_t n) {
+  const double wr = w.real(), wi = w.imag();
+  const double* bp = reinterpret_cast<const double*>(b);
+  double* fp = reinterpret_cast<double*>(f);
+  for (size_t i = 0; i < n; ++i) {
+    const double br = bp[2 * i], bi = bp[2 * i + 1];
+    fp[2 * i] += br * wr - bi * wi;
+    fp[2 * i + 1] += br * wi + bi * wr;
+  }
+}
+
 inline int wrap(long long k, long long d, int n) {
   long long m = (k * d) % n;
   if (m < 0) m += n;
@@ -68,8 +92,14 @@ std::vector<cd> dft_grid(const Kern& K, int gx, int gy, int gz) {
   for (int z = 0; z < K.kz; ++z)
     for (int y = 0; y < K.ky; ++y)
       for (int k = 0; k < gx; ++k) {
+        // phase index k (x - cx) mod gx, stepped by k along x
+        int idx = wrap(k, -cx, gx);
         cd s = 0;
-        for (int x = 0; x < K.kx; ++x) s += K.at(z, y, x) * tx[wrap(k, x - cx, gx)];
+        for (int x = 0; x < K.kx; ++x) {
+          s += K.at(z, y, x) * tx[idx];
+          idx += k;
+          if (idx >= gx) idx -= gx;
+        }
         A[((size_t)z * K.ky + y) * gx + k] = s;
       }
   std::vector<cd> B((size_t)K.kz * gy * gx);
@@ -77,17 +107,13 @@ std::vector<cd> dft_grid(const Kern& K, int gx, int gy, int gz) {
     for (int k = 0; k < gy; ++k)
       for (int y = 0; y < K.ky; ++y) {
         const cd w = ty[wrap(k, y - cy, gy)];
-        const cd* a = &A[((size_t)z * K.ky + y) * gx];
-        cd* b = &B[((size_t)z * gy + k) * gx];
-        for (int x = 0; x < gx; ++x) b[x] += a[x] * w;
+        cmac(&B[((size_t)z * gy + k) * gx], &A[((size_t)z * K.ky + y) * gx], w, gx);
       }
   std::vector<cd> F((size_t)gz * gy * gx);
   for (int k = 0; k < gz; ++k)
     for (int z = 0; z < K.kz; ++z) {
       const cd w = tz[wrap(k, z - cz, gz)];
-      const cd* b = &B[(size_t)z * gy * gx];
-      cd* f = &F[(size_t)k * gy * gx];
-      for (size_t i = 0; i < (size_t)gy * gx; ++i) f[i] += b[i] * w;
+      cmac(&F[(size_t)k * gy * gx], &B[(size_t)z * gy * gx], w, (size_t)gy * gx);
     }
   return F;
 }
@@ -102,27 +128,30 @@ std::vector<double> idft_window(const std::vector<cd>& S, int gx, int gy, int gz
   for (int z = 0; z < wz; ++z)
     for (int k = 0; k < gz; ++k) {
       const cd w = std::conj(tz[wrap(k, z - cz, gz)]);
-      const cd* s = &S[(size_t)k * gy * gx];
-      cd* t = &T1[(size_t)z * gy * gx];
-      for (size_t i = 0; i < (size_t)gy * gx; ++i) t[i] += s[i] * w;
+      cmac(&T1[(size_t)z * gy * gx], &S[(size_t)k * gy * gx], w, (size_t)gy * gx);
     }
   std::vector<cd> T2((size_t)wz * wy * gx);
   for (int z = 0; z < wz; ++z)
     for (int y = 0; y < wy; ++y)
       for (int k = 0; k < gy; ++k) {
         const cd w = std::conj(ty[wrap(k, y - cy, gy)]);
-        const cd* s = &T1[((size_t)z * gy + k) * gx];
-        cd* t = &T2[((size_t)z * wy + y) * gx];
-        for (int x = 0; x < gx; ++x) t[x] += s[x] * w;
+        cmac(&T2[((size_t)z * wy + y) * gx], &T1[((size_t)z * gy + k) * gx], w, gx);
       }
   const double inv = 1.0 / ((double)gx * gy * gz);
   std::vector<double> out((size_t)wz * wy * wx);
   for (int z = 0; z < wz; ++z)
     for (int y = 0; y < wy; ++y)
       for (int x = 0; x < wx; ++x) {
+        // phase index k (x - cx) mod gx, stepped by x - cx along k
+        const int step = wrap(1, x - cx, gx);
+        int idx = 0;
         cd s = 0;
         const cd* t = &T2[((size_t)z * wy + y) * gx];
-        for (int k = 0; k < gx; ++k) s += t[k] * std::conj(tx[wrap(k, x - cx, gx)]);
+        for (int k = 0; k < gx; ++k) {
+          s += t[k] * std::conj(tx[idx]);
+          idx += step;
+          if (idx >= gx) idx -= gx;
+        }
         out[((size_t)z * wy + y) * wx + x] = s.real() * inv;
       }
   return out;
@@ -240,6 +269,12 @@ Kern compound_kernel(const std::vector<Kern>& P, int v, int variant) {
     for (size_t i = 0; i < K.a.size(); ++i) K.a[i] *= fac[w][i];
   }
   normalize(K);
+  return K;
+}
+
+std::vector<Kern> compound_kernels(const std::vector<Kern>& P, int variant) {
+  std::vector<Kern> K(P.size());
+  parallel_for((int)P.size(), [&](int v) { K[v] = compound_kernel(P, v, variant); });
   return K;
 }
 

@@ -35,6 +35,8 @@ Kern mirror(const Kern& k);
 // by a direct DFT on a grid large enough that circular equals linear
 // convolution, then cropped to the window.
 Kern compound_kernel(const std::vector<Kern>& P, int v, int variant);
+// The compound kernels of every view, computed in parallel.
+std::vector<Kern> compound_kernels(const std::vector<Kern>& P, int variant);
 
 // Adjoint of compound_kernel: given Kbar = dL/dK_v on K_v's window (the
 // window of P_v), dL/dP_w for every prepared PSF (same extents as P[w].a;

@@ -1059,10 +1059,8 @@ void ensure_role(mvd_handle* h, int role) {
       continue;
     }
     if (!B.H[role]) B.H[role] = (float*)h->dalloc((size_t)h->nviews * B.h_elems * 2 * sizeof(float));
-    for (int v = 0; v < h->nviews; ++v) {
-      const mvdh::Kern K = mvdh::compound_kernel(B.P, v, variant);
-      upload_kernel(h, B, K, B.H[role] + (size_t)v * B.h_elems * 2);
-    }
+    const auto K = mvdh::compound_kernels(B.P, variant);
+    for (int v = 0; v < h->nviews; ++v) upload_kernel(h, B, K[v], B.H[role] + (size_t)v * B.h_elems * 2);
   }
   build_jobs(h);
   h->built[role] = true;

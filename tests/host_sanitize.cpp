@@ -56,6 +56,22 @@ int main() {
     }
     CHECK(thrown);
   }
+  // every view's kernel at once (in parallel) equals the one-view builds;
+  // an exception on a worker thread reaches the caller
+  for (int variant = 0; variant < 4; ++variant) {
+    const auto all = compound_kernels(P, variant);
+    CHECK(all.size() == 3);
+    for (int v = 0; v < 3; ++v) CHECK(all[v].a == compound_kernel(P, v, variant).a);
+  }
+  {
+    bool thrown = false;
+    try {
+      compound_kernels(P, 7);
+    } catch (const std::invalid_argument&) {
+      thrown = true;
+    }
+    CHECK(thrown);
+  }
   for (int variant = 0; variant < 4; ++variant)
     for (int v = 0; v < 3; ++v) {
       Kern K = compound_kernel(P, v, variant);
