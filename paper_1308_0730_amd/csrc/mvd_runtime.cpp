@@ -123,7 +123,8 @@ struct mvd_handle {
   // block run on one stream in pass order: a sequential iteration forks the
   // side streams once and joins them at its end (defer_join); other
   // sequences fork and join around every pass.
-  static constexpr int kSide = 3;
+  static constexpr int kSide = 15;
+  int nside = 0;  // side lanes created: one per further block, at most kSide
   hipStream_t side[kSide] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kSide] = {};
@@ -475,7 +476,7 @@ void build_jobs(mvd_handle* h) {
     int64_t load[1 + mvd_handle::kSide] = {};
     for (const auto& g : groups) {
       int best = 0;
-      for (int l = 1; l <= mvd_handle::kSide && !h->blocked && !h->no_alloc; ++l)
+      for (int l = 1; l <= h->nside; ++l)
         if (load[l] < load[best]) best = l;
       for (int i : *g.second) h->block_lane[i] = best;
       load[best] += g.first;
@@ -660,7 +661,10 @@ void make_streams(mvd_handle* h, int nb) {
     h->use_graphs = false;
   } else {
     HIPCHECK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    for (int i = 0; i < mvd_handle::kSide; ++i) {
+    // side lanes only where blocks can use them (the block-wise form keeps
+    // its blocks on one stream)
+    h->nside = h->blocked ? 0 : std::min(mvd_handle::kSide, nb - 1);
+    for (int i = 0; i < h->nside; ++i) {
       HIPCHECK(hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking));
       HIPCHECK(hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming));
     }
@@ -1102,12 +1106,12 @@ void run_groups(mvd_handle* h, hipStream_t s, int kind, F&& launch) {
   const bool fork = (used & ~1u) != 0;
   if (fork) {
     HIPCHECK(hipEventRecord(h->ev_fork, s));
-    for (int l = 1; l <= mvd_handle::kSide; ++l)
+    for (int l = 1; l <= h->nside; ++l)
       if (used & (1u << l)) HIPCHECK(hipStreamWaitEvent(h->side[l - 1], h->ev_fork, 0));
   }
   for (const auto& g : h->groups[kind]) HIPCHECK(launch(g, g.lane ? h->side[g.lane - 1] : s));
   if (fork) {
-    for (int l = 1; l <= mvd_handle::kSide; ++l)
+    for (int l = 1; l <= h->nside; ++l)
       if (used & (1u << l)) {
         HIPCHECK(hipEventRecord(h->ev_join[l - 1], h->side[l - 1]));
         HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l - 1], 0));
@@ -1225,7 +1229,7 @@ void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t =
     return;
   }
   HIPCHECK(hipEventRecord(h->ev_fork, s));
-  for (int l = 0; l < mvd_handle::kSide; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
+  for (int l = 0; l < h->nside; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
   h->defer_join = true;
   try {
     for (int v = 0; v < h->nviews; ++v) enqueue_view(h, s, variant, v, nullptr);
@@ -1234,7 +1238,7 @@ void enqueue_iteration(mvd_handle* h, hipStream_t s, int variant, PassTimer* t =
     throw;
   }
   h->defer_join = false;
-  for (int l = 0; l < mvd_handle::kSide; ++l) {
+  for (int l = 0; l < h->nside; ++l) {
     HIPCHECK(hipEventRecord(h->ev_join[l], h->side[l]));
     HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l], 0));
   }
@@ -1283,8 +1287,8 @@ bool block_major(const mvd_handle* h) {
 // the same results; the lanes are forked once and joined at the end.
 void enqueue_run_blocks(mvd_handle* h, hipStream_t s, int variant, int n) {
   HIPCHECK(hipEventRecord(h->ev_fork, s));
-  for (int l = 0; l < mvd_handle::kSide; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
-  for (int l = 0; l <= mvd_handle::kSide; ++l) {
+  for (int l = 0; l < h->nside; ++l) HIPCHECK(hipStreamWaitEvent(h->side[l], h->ev_fork, 0));
+  for (int l = 0; l <= h->nside; ++l) {
     hipStream_t sl = l ? h->side[l - 1] : s;
     std::vector<int> mine;
     for (int b = 0; b < (int)h->blocks.size(); ++b)
@@ -1299,7 +1303,7 @@ void enqueue_run_blocks(mvd_handle* h, hipStream_t s, int variant, int n) {
           for (int v = 0; v < h->nviews; ++v) enqueue_view_block(h, sl, variant, v, b);
     }
   }
-  for (int l = 0; l < mvd_handle::kSide; ++l) {
+  for (int l = 0; l < h->nside; ++l) {
     HIPCHECK(hipEventRecord(h->ev_join[l], h->side[l]));
     HIPCHECK(hipStreamWaitEvent(s, h->ev_join[l], 0));
   }
