@@ -174,3 +174,29 @@ def test_schedules_give_the_same_results(mvd, graphs):
         for a, r in zip(out[sch][0], out["pass"][0]):
             np.testing.assert_array_equal(a, r)
         np.testing.assert_allclose(out[sch][1], out["pass"][1], rtol=1e-12)
+
+
+def test_shuffled_blocks_and_schedules_give_the_same_blocks(mvd):
+    """Scheduler stress: 20 blocks of mixed dims (repeated dims share a lane
+    and a launch; up to sixteen stream lanes), handed over in three seeded
+    random orders and run under every schedule with the per-length plans:
+    every block's estimate is bitwise the same as in the first order."""
+    dims = [DIMS[i % len(DIMS)] for i in range(20)]
+    blocks = [block(d, 300 + i) for i, d in enumerate(dims)]
+    rng = np.random.default_rng(311)
+    ref = None
+    for trial in range(3):
+        order = list(range(len(blocks))) if trial == 0 else list(rng.permutation(len(blocks)))
+        with mvd.Deconvolver.batch([blocks[i] for i in order], lam=0.01) as b:
+            b.set_tiles(*tiles_of(mvd, b.max_lengths(), -1))
+            for sch in ("pass", "block", "run"):
+                b.set_schedule(sch)
+                for j, i in enumerate(order):
+                    b.set_estimate(np.full(blocks[i][0][0].shape, 3.0, np.float32), j)
+                b.iterate(2, O.EFF)
+                got = {i: b.estimate(j).cpu().numpy() for j, i in enumerate(order)}
+                if ref is None:
+                    ref = got
+                    continue
+                for i in range(len(blocks)):
+                    np.testing.assert_array_equal(got[i], ref[i], err_msg=f"trial {trial} schedule {sch} block {i}")
